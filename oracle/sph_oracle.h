@@ -1,0 +1,121 @@
+/*
+ * sph_oracle.h -- plain FP64 CPU reference ("oracle") for the gearbox WCSPH
+ * hot path of Yu, Wu, Haidn, Hu, "A GPU-Accelerated Fully Coupled
+ * Fluid-Solid-Thermal SPH Solver for Industrial Gearboxes" (arXiv 2512.09904).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no code
+ * with the HIP library and must never be used as a fallback for it.
+ *
+ * Everything is FP64, compiled with -ffp-contract=off.  Arrays are plain C
+ * arrays: vectors are n x 3, row-major (AoS), in the caller's particle order.
+ */
+#ifndef SPH_ORACLE_H
+#define SPH_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORA_OK = 0, ORA_ERR_ARG = 1, ORA_ERR_OOM = 2, ORA_ERR_DOMAIN = 5 };
+
+typedef struct {
+  double dp, h_over_dp, rho0, c0, nu, k_f, cp_f;
+  double gravity[3];
+  double grid_lo[3], grid_hi[3];
+  double cfl_ad, cfl_ac;
+  double fixed_dt_ad;      /* > 0: use this advection step and fixed_nac sub-steps */
+  int32_t fixed_nac;
+  int32_t nac_max;         /* cap on acoustic sub-steps per advection step */
+  int32_t free_surface;    /* 1: eq. 14 re-initialisation, 0: eq. 15 */
+  int32_t eq13_printed;    /* 1: take eq. 13's printed sign (reading study only) */
+} ora_params;
+
+typedef struct { double center[3], axis[3], omega, T, k; } ora_body;
+
+typedef struct {
+  double t, dt_ad, dt;
+  int32_t n_ac, pad;
+  double vmax, mass, kinetic, thermal, heat_step, mass_proxy;
+} ora_report;
+
+typedef struct { double force[3], torque[3], torque_axis, power, heat_rate; } ora_body_report;
+
+/* Optional per-fluid-particle outputs of ora_step (any pointer may be NULL). */
+typedef struct {
+  double *a_visc;   /* nf*3 viscous acceleration (frozen for the step) */
+  double *dTdt;     /* nf   temperature rate (frozen for the step) */
+  double *sumW;     /* nf   kernel sum incl. self, fluid and solid */
+  double *S_visc;   /* nf   sum of |viscous pair terms| */
+  double *S_T;      /* nf   sum of |heat pair terms| */
+  double *a_p;      /* nf*3 pressure acceleration of the last sub-step */
+  double *S_p;      /* nf   sum of |pressure pair terms| of the last sub-step */
+  double *S_rho;    /* nf   sum of |continuity pair terms| of the last sub-step */
+} ora_rates;
+
+/* Neighbour sets and the frozen pair geometry of one advection step. */
+typedef struct ora_nbr ora_nbr;
+
+/* --- kernel (Wendland C2, support 2h) ------------------------------------ */
+double ora_kernel_W(double r, double h);
+double ora_kernel_dW(double r, double h);   /* dW/dr */
+double ora_kernel_F(double r, double h);    /* (dW/dr)/r, finite at r = 0 */
+/* dp^3 * sum over a perfect cubic lattice of W, self included, h = h_over_dp*dp */
+double ora_lattice_sum0(double h_over_dp);
+
+/* --- cells and ordering --------------------------------------------------- */
+uint32_t ora_morton3(uint32_t cx, uint32_t cy, uint32_t cz);
+int ora_grid_dims(const ora_params* P, int32_t dims[3]);
+/* cell coordinates of n points; returns ORA_ERR_DOMAIN if any lies outside */
+int ora_cells(const ora_params* P, int64_t n, const double* x, int32_t* cell);
+/* order[k] = index of the k-th point in ascending (morton(cell), id) order */
+int ora_sort_order(const ora_params* P, int64_t n, const double* x, const uint32_t* id,
+                   int64_t* order);
+
+/* --- neighbour search ------------------------------------------------------ */
+int ora_nbr_build(const ora_params* P, int64_t nf, const double* xf, int64_t ns,
+                  const double* xs, int32_t brute, ora_nbr** out);
+int64_t ora_nbr_total(const ora_nbr* nb, int32_t which);   /* 0 fluid, 1 solid */
+void ora_nbr_csr(const ora_nbr* nb, int32_t which, int64_t* offsets, int32_t* idx);
+void ora_nbr_free(ora_nbr* nb);
+
+/* --- sweeps over frozen neighbour sets ----------------------------------- */
+void ora_sum_w(const ora_params* P, const ora_nbr* nb, double* sumW);
+void ora_viscous(const ora_params* P, const ora_nbr* nb, int32_t nbody, const ora_body* B,
+                 const int32_t* body, const double* v, const double* rho, const double* mass,
+                 const double* vs, double* a, double* S, double* bforce, double* btorque);
+void ora_heat(const ora_params* P, const ora_nbr* nb, int32_t nbody, const ora_body* B,
+              const int32_t* body, const double* rho, const double* mass, const double* k,
+              const double* cp, const double* T, double* dTdt, double* S, double* bheat);
+void ora_momentum(const ora_params* P, const ora_nbr* nb, int32_t nbody, const ora_body* B,
+                  const int32_t* body, const double* v, const double* rho, const double* mass,
+                  const double* nsv, const double* vs, double* a, double* S, double* bforce,
+                  double* btorque);
+void ora_continuity(const ora_params* P, const ora_nbr* nb, const double* v,
+                    const double* rho, const double* mass, const double* nsv, const double* vs,
+                    double* drho, double* S);
+/* pair forces on i from j: pressure part f[0..2], viscous part f[3..5] */
+void ora_pair_force(const ora_params* P, const double* xi, const double* xj, const double* vi,
+                    const double* vj, double rhoi, double rhoj, double mi, double mj,
+                    double* f);
+
+/* --- bodies, time step, one advection step -------------------------------- */
+void ora_body_pose(int32_t nbody, const ora_body* B, int64_t ns, const double* x0,
+                   const double* n0, const int32_t* body, double t, double* xs, double* nsv,
+                   double* vs);
+void ora_timestep(const ora_params* P, int32_t nbody, const ora_body* B, int64_t ns,
+                  const double* x0, const int32_t* body, int64_t nf, const double* v,
+                  double* dt_ad, double* dt, int32_t* n_ac, double* vmax);
+int ora_step(const ora_params* P, int32_t nbody, const ora_body* B, int64_t nf, double* x,
+             double* v, double* rho, double* T, double* drho, int64_t ns, const double* x0,
+             const double* n0, const int32_t* body, double* t, ora_report* rep,
+             ora_body_report* brep, ora_rates* rates);
+/* totals of the state: mass, kinetic, thermal, mass proxy, vmax (Neumaier sums) */
+void ora_totals(const ora_params* P, int64_t nf, const double* v, const double* rho,
+                const double* T, double* out5);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
