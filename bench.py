@@ -1,0 +1,223 @@
+"""Benchmark of the WCSPH gearbox hot path on one MI355X.
+
+Workload: the 1.5 mm gearbox proxy (two meshing toothed disks, 20/40 teeth,
+module 4 mm, 300 rad/s, 30 mm immersion, nu = 1e-4; about 0.89 M fluid and
+0.48 M solid particles), synthetic seeded input, mixed FP32/FP64 arithmetic.
+
+A step is one advection step of the whole hot path: body pose, cell sort,
+neighbour rows, density re-initialisation, time step, viscous + heat sweep,
+n_ac acoustic sub-steps (momentum and continuity sweeps) and the reductions.
+
+Printed: one JSON line with particle-interactions/s (ordered pairs within 2h
+times pair sweeps per step), steps/s, per-sweep latency percentiles, the
+roofline of the dominant kernel and the FP64 oracle's rate on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2512_09904_amd", "csrc", "sph_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "momentum_gearbox_c2_traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def pair_counts(s, nf):
+    cnt = s.dump("nbr_count").reshape(2, nf).astype(np.int64)
+    return int(cnt[0].sum()), int(cnt[1].sum())
+
+
+def sweep_bytes(kernel, nf, ns, pf, ps, prec="mixed"):
+    """Algorithmic HBM bytes of one launch: each array touched once, rows streamed.
+
+    Rows hold 20 B per pair (index, r_ij, F) in mixed precision; the
+    neighbour-state gathers re-read arrays already counted once.
+    """
+    rb = 4 if prec != "fp64" else 8
+    rec = 4 + 4 * rb
+    if kernel == "momentum":
+        own = nf * (3 * rb + rb + 3 * rb + 2 * 3 * rb + 3 * rb + 8)   # v, rho, a_visc, drift rw, v_new, counts
+        return own + (pf + ps) * rec + ns * (4 + 3 * rb)              # + rows, solid body and lever arm
+    if kernel == "continuity":
+        own = nf * (3 * rb + rb + rb + 3 * rb + 8)                     # v_new, rho, drho, v, counts
+        return own + (pf + ps) * rec + ns * (4 * 0 + 6 * rb)           # + rows, solid normal and velocity
+    if kernel == "visc_heat":
+        own = nf * (3 * rb + rb + 8 + 3 * rb + rb + 8)                  # v, rho, T, a_visc, dTdt, counts
+        return own + (pf + ps) * (4 + rb) + ns * (4 + 6 * rb)          # index and F only
+    raise KeyError(kernel)
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a), q)) if len(a) else None
+
+
+def cpu_baseline(case, steps=2):
+    """The FP64 oracle on the host cores, on a bounded sample of the same workload."""
+    from oracle import oracle as O
+    O.build(force=False)
+    o = O.State(case)
+    nb = O.Nbr(case.params, case.xf, O.body_pose(case.bodies, case.xs0, case.ns0, case.body, 0.0)[0])
+    pf = int(nb.csr(0)[0][-1])
+    ps = int(nb.csr(1)[0][-1])
+    del nb
+    t0 = time.perf_counter()
+    nac = []
+    for _ in range(steps):
+        r = o.step()
+        nac.append(r["n_ac"])
+    dt = time.perf_counter() - t0
+    sweeps = sum(2 + 2 * n for n in nac)
+    cores = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
+    return {"value": (pf + ps) * sweeps / dt, "unit": "particle-interactions/s", "cores": cores,
+            "kind": "oracle", "steps_per_s": steps / dt,
+            "sample": f"{steps} advection steps of the full gearbox proxy (dp 1.5 mm, {case.nf} fluid + {case.ns} "
+                      f"solid particles) from the initial state, FP64 C/OpenMP oracle, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--timed-steps", type=int, default=20, help="steps of the per-kernel event-timed pass")
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64", "fp32"])
+    ap.add_argument("--dp", type=float, default=1.5e-3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--calib-copy", action="store_true", help="run one 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus > 1 or world > 1:
+        print("bench.py runs on one GPU only: every box here has a single MI355X and the path is "
+              "measured on one GPU's share; see the sharding design for more GPUs.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2512_09904_amd import cases, sph
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    if args.calib_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration copy: 1 GiB read + 1 GiB written")
+        return
+
+    t0 = time.perf_counter()
+    case = cases.gearbox(seed=0, dp=args.dp, omega_big=300.0, immersion=0.030, nu=1e-4)
+    log(f"case: nf={case.nf} ns={case.ns} generated in {time.perf_counter() - t0:.1f} s")
+    s = sph.Solver(case, precision=args.precision)
+    log("initialised")
+    s.step(args.warmup)
+    s.reduce()
+    pf0, ps0 = pair_counts(s, case.nf)
+
+    # timed region 1: captured graph per advection step
+    torch.cuda.synchronize()
+    s.stream.synchronize()
+    t0 = time.perf_counter()
+    s.step(args.steps)
+    r = s.reduce()
+    s.stream.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pf1, ps1 = pair_counts(s, case.nf)
+    pairs = 0.5 * (pf0 + pf1) + 0.5 * (ps0 + ps1)
+    n_ac = r["n_ac"]
+    sweeps = 2 + 2 * n_ac
+    ms_per_step = 1e3 * wall / args.steps
+    value = pairs * sweeps * args.steps / wall
+    log(f"graph: {ms_per_step:.3f} ms/step, n_ac={n_ac}, pairs/sweep={pairs:.3e}, {value:.3e} interactions/s")
+
+    # timed region 2: the same steps launched eagerly with HIP events per kernel
+    s.set_timing(True)
+    t0 = time.perf_counter()
+    s.step(args.timed_steps)
+    r2 = s.reduce()
+    wall2 = time.perf_counter() - t0
+    kt = {k: s.timing(k) for k in sph.KERNELS}
+    s.set_timing(False)
+    pf2, ps2 = pair_counts(s, case.nf)
+    per_step_kernel_ms = {k: float(v.sum() / args.timed_steps) for k, v in kt.items() if len(v)}
+    log("per-step kernel ms:", json.dumps({k: round(v, 4) for k, v in per_step_kernel_ms.items()}))
+    dom = "momentum"
+    avg_ms = float(np.mean(kt[dom]))
+    bytes_launch = sweep_bytes(dom, case.nf, case.ns, pf2, ps2, args.precision)
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_sha") == kernel_hash() and tr.get("precision") == args.precision:
+            traffic = tr.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": "k_momentum",
+                "bytes_per_launch": int(bytes_launch), "avg_launch_ms": round(avg_ms, 5)}
+    sweep_lat = {k: {"p50_ms": round(pct(kt[k], 50), 5), "p99_ms": round(pct(kt[k], 99), 5), "n": len(kt[k])}
+                 for k in ("build", "visc_heat", "momentum", "continuity") if len(kt[k])}
+    others = {}
+    for k in ("continuity", "visc_heat"):
+        b = sweep_bytes(k, case.nf, case.ns, pf2, ps2, args.precision)
+        gbs = b / (float(np.mean(kt[k])) * 1e-3) / 1e9
+        others[k] = {"achieved_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on the host")
+        cpu = cpu_baseline(case, args.cpu_steps)
+        log(f"cpu baseline: {cpu['value']:.3e} interactions/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": "particle-interactions/s & steps/s at 1M particles; p50/p99 sweep latency",
+        "value": value,
+        "unit": "particle-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "steps_per_s": 1e3 / ms_per_step,
+        "acoustic_substeps_per_s": n_ac * 1e3 / ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"mixed": "f32+f64", "fp64": "f64", "fp32": "f32"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"gearbox proxy dp={args.dp * 1e3:.2f} mm, two toothed disks 20/40 teeth at "
+                               f"-600/300 rad/s, 30 mm immersion, nu=1e-4",
+                   "n_fluid": case.nf, "n_solid": case.ns, "n_ac": n_ac, "pairs_per_sweep": int(pairs),
+                   "pair_sweeps_per_step": sweeps, "precision": args.precision, "parallelism": "single GPU"},
+        "sweep_latency": sweep_lat,
+        "event_timed": {"steps": args.timed_steps, "ms_per_step": 1e3 * wall2 / args.timed_steps,
+                        "kernel_ms_per_step": {k: round(v, 4) for k, v in per_step_kernel_ms.items()},
+                        "other_sweeps": others},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

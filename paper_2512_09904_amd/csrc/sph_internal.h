@@ -1,0 +1,95 @@
+// sph_internal.h -- shared layout between the host orchestrator and the HIP
+// kernels of the WCSPH hot path.  Not part of the public C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sph.h"
+
+namespace sphk {
+
+constexpr int BLOCK = 256;          // threads per workgroup (4 wave64)
+constexpr int WAVE = 64;            // CDNA wavefront; also the SELL slice height
+constexpr int MAX_SLOTS = 32;
+constexpr int NB = SPH_MAX_BODIES;
+constexpr int NACC = 2;             // distinct bodies one fluid particle may touch
+constexpr int NGLOB = 5;            // mass, kinetic, thermal, mass proxy, vmax
+
+enum Dom { DOM_FLUID = 0, DOM_SOLID = 1, DOM_CELL = 2, DOM_SLOT = 3, NDOM = 4 };
+enum Flag { F_DOMAIN = 1, F_NONFINITE = 2, F_CAPACITY = 4 };
+
+// Blocks of one launch: the slots it covers and, per domain, the prefix of
+// their block counts.  Passed by value (kernel argument segment).
+struct LaunchTab {
+  int32_t n;
+  int32_t slot[MAX_SLOTS];
+  int32_t blk0[NDOM][MAX_SLOTS + 1];
+};
+
+// Device-resident control block of a slot, written only by kernels.
+struct SlotCtl {
+  double t, dt_ad, dt;
+  int64_t step, target;
+  int32_t n_ac;
+  uint32_t flags;
+  double heat_total;
+  double cum[NB][3];     // time integrals: axial torque, energy, heat
+  sph_report rep;
+  sph_body_report brep[NB];
+};
+
+// Everything a kernel needs to know about one slot.  Arrays are in the
+// cell-sorted order; 3-vectors are SoA with stride n (x at [0,n), y, z).
+struct SlotDesc {
+  int32_t nf, ns, ncells, nslices;
+  int32_t kf, ks, nbody, nac_bound;
+  int32_t dims[3];
+  int32_t free_surface, fixed_nac, pad0;
+  int32_t nblk[NDOM];
+  int64_t rowlen_f, rowlen_s;          // nslices * k * 64
+  double dp, h, rho0, c0, eta, k_f, cp_f, mass, vol_w, S0, cut2, cs;
+  double cfl_ad, cfl_ac, fixed_dt_ad, nu;
+  double g[3], lo[3];
+  double kW, kF;                       // W = kW (1-q/2)^4 (1+2q);  F = kF (1-q/2)^3
+  double bc[NB][3], ba[NB][3], bom[NB], bT[NB], bk[NB], btip[NB];
+  SlotCtl* ctl;
+  // fluid state (sorted order) and its gather buffers
+  void *xa, *drift, *v, *vnew, *rho, *drho, *T, *av, *dTdt;
+  uint32_t *fid;
+  double *sumW;
+  uint32_t *fcell, *fperm;
+  void *xa2, *v2, *rho2, *drho2, *T2;
+  uint32_t *fid2;
+  // neighbour rows (SELL, slice height 64): index, r_ij (3 arrays), F
+  uint32_t *nfc, *nsc;
+  uint32_t *nj;
+  void *nr, *nF;
+  uint32_t *sj;
+  void *sr, *sF;
+  // solids
+  double *x0, *n0;
+  int32_t *body;
+  uint32_t *sid;
+  void *xw, *nw, *vw, *lev;
+  double *x0b, *n0b;
+  int32_t *bodyb;
+  uint32_t *sidb;
+  void *xwb, *nwb, *vwb, *levb;
+  uint32_t *scell, *sperm;
+  // cells
+  uint32_t *rank, *cnt_f, *cnt_s, *start_f, *start_s, *bsum_f, *bsum_s;
+  // per fluid-block partials
+  float *vmax_part;
+  double *visc_part;    // [nblk_f][NB][7]: force(3) torque(3) heat
+  double *press_part;   // [nblk_f][NB][6]: sum over sub-steps of force(3) torque(3)
+  double *glob_part;    // [nblk_f][NGLOB]
+};
+
+// Launch one kernel of the step.  prec: SPH_PREC_*; kid: SPH_K_*; sub: the
+// acoustic sub-step index (only for the sub-step kernels); which: 0 fluid, 1
+// solid (for the kernels launched once per particle set).
+hipError_t launch_kernel(int prec, int kid, int which, int sub, const SlotDesc* table,
+                         const LaunchTab& tab, hipStream_t stream);
+int grid_domain(int kid, int which);
+
+}  // namespace sphk

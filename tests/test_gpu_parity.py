@@ -1,0 +1,305 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Bars (written out in each test):
+  - cell codes, sort order, neighbour sets, r_ij records: bit-exact;
+  - per-particle rates: |gpu - oracle| <= tau * S_i with S_i the oracle's sum
+    of absolute pair terms; tau = 1e-5 (mixed FP32/FP64), 1e-11 (FP64 mode);
+  - one advection step from identical state, fixed dt: max normalised error
+    <= 1e-5 (mixed) with scales Q_rho = rho0 (Umax/c0)^2, Q_v = Umax,
+    Q_T = |T_wall - T_oil|, Q_x = dp; <= 1e-10 in FP64 mode.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2512_09904_amd import cases
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def sph():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_09904_amd import sph as S
+    S.lib()
+    return S
+
+
+def fixed_dt(case):
+    from oracle import oracle as O
+    d = O.timestep(case.params, case.bodies, case.xs0, case.body, case.vf)
+    return d["dt_ad"], d["n_ac"]
+
+
+def ragged_tank(seed=0):
+    """C1 tank with an odd particle count (ragged final wave and block)."""
+    c = cases.tank_c1(seed=seed)
+    keep = np.ones(c.nf, bool)
+    keep[np.arange(7, c.nf, 97)] = False
+    c.xf, c.vf, c.rhof, c.Tf = c.xf[keep], c.vf[keep], c.rhof[keep], c.Tf[keep]
+    return c
+
+
+# ---------------------------------------------------------------------------
+# stage parity: cells, order, neighbour sets, records (bit-exact)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_stage_parity_init(sph, ora, precision):
+    c = ragged_tank()
+    say("stage parity", precision, c.nf, c.ns)
+    s = sph.Solver(c, precision=precision)
+    fid = s.dump("fluid_ids").astype(np.int64)
+    rc, order = ora.sort_order(c.params, c.xf, np.arange(c.nf, dtype=np.uint32))
+    assert rc == 0
+    assert np.array_equal(fid, order)
+    rc, cell = ora.cells(c.params, c.xf)
+    mort = np.array([ora.morton3(*cc) for cc in cell[fid]], dtype=np.uint32)
+    assert np.array_equal(s.dump("fluid_cell"), mort)
+    xs, ns, vs = ora.body_pose(c.bodies, c.xs0, c.ns0, c.body, 0.0)
+    sid = s.dump("solid_ids").astype(np.int64)
+    rc, sorder = ora.sort_order(c.params, xs, np.arange(c.ns, dtype=np.uint32))
+    assert np.array_equal(sid, sorder)
+    st = s.dump("solid_state").reshape(c.ns, 13)
+    assert np.array_equal(st[:, 0:3], xs[sid])          # pose at t = 0 is bitwise
+    nb = ora.Nbr(c.params, c.xf, xs)
+    fl, so = s.neighbour_sets()
+    assert fl == nb.sets(0)
+    assert so == nb.sets(1)
+    # records: r_ij is the FP64 difference rounded to the interaction type
+    cnt = s.dump("nbr_count").reshape(2, c.nf)
+    kf = len(s.dump("nbr_fluid")) // c.nf
+    rows = s.dump("nbr_fluid").reshape(c.nf, kf)
+    geo = s.dump("geom_fluid").reshape(c.nf, kf, 4)
+    h = c.params["h_over_dp"] * c.params["dp"]
+    rt = np.float32 if precision == "mixed" else np.float64
+    for k in range(0, c.nf, 37):
+        n = cnt[0, k]
+        i, js = fid[k], fid[rows[k, :n]]
+        d = c.xf[i] - c.xf[js]
+        assert np.array_equal(geo[k, :n, :3], d.astype(rt).astype(np.float64))
+        F = np.array([ora.F(math.sqrt((dd[0] * dd[0] + dd[1] * dd[1]) + dd[2] * dd[2]), h) for dd in d])
+        assert np.all(np.abs(geo[k, :n, 3] - F.astype(rt)) <= np.abs(np.spacing(F.astype(rt))))
+    # kernel sums and the re-initialised density (eq. 14)
+    sw = ora.sum_w(c.params, nb)
+    assert np.allclose(s.dump("sumw")[np.argsort(fid)], sw, rtol=1e-12, atol=0)
+    S0 = ora.lattice_sum0(c.params["h_over_dp"])
+    rho_ref = np.maximum(c.rhof, c.params["rho0"] * c.params["dp"] ** 3 * sw / S0)
+    g = s.get_fluid()
+    tol = 1e-12 if precision == "fp64" else 2e-7
+    assert np.max(np.abs(g["rho"] - rho_ref) / c.params["rho0"]) <= tol
+    s.close()
+
+
+# ---------------------------------------------------------------------------
+# one advection step from identical state, fixed dt
+# ---------------------------------------------------------------------------
+
+def _one_step(sph, ora, case, precision):
+    dt, nac = fixed_dt(case)
+    o = ora.State(case, fixed_dt_ad=dt, fixed_nac=nac)
+    ro = o.step(want_rates=True)
+    s = sph.Solver(case, precision=precision, fixed_dt_ad=dt, fixed_nac=nac)
+    s.step(1)
+    rg = s.reduce()
+    g = s.get_fluid()
+    fid = s.dump("fluid_ids").astype(np.int64)
+    st = s.dump("fluid_state").reshape(case.nf, 16)
+    inv = np.argsort(fid)
+    st = st[inv]
+    s.close()
+    return o, ro, g, st, rg
+
+
+def _normalised_errors(case, o, g):
+    umax = case.meta["umax"]
+    c0 = case.params["c0"]
+    rho0 = case.params["rho0"]
+    Q = dict(rho=rho0 * (umax / c0) ** 2, v=umax, T=abs(case.bodies[0].T - case.Tf.mean()) or 1.0,
+             x=case.params["dp"])
+    return dict(
+        x=np.max(np.abs(g["x"] - o.x)) / Q["x"],
+        v=np.max(np.abs(g["v"] - o.v)) / Q["v"],
+        rho=np.max(np.abs(g["rho"] - o.rho)) / Q["rho"],
+        T=np.max(np.abs(g["T"] - o.T)) / Q["T"],
+    )
+
+
+@pytest.mark.parametrize("precision,bar,tau", [("mixed", 1e-5, 1e-5), ("fp64", 1e-10, 1e-11)])
+def test_one_step_parity(sph, ora, precision, bar, tau):
+    c = ragged_tank(seed=1)
+    say("one-step parity", precision, c.nf)
+    o, ro, g, st, rg = _one_step(sph, ora, c, precision)
+    e = _normalised_errors(c, o, g)
+    say("normalised errors", precision, e)
+    assert max(e.values()) <= bar, e
+    R = ro["rates"]
+    dv = np.max(np.abs(st[:, 12:15] - R["a_visc"]), axis=1)
+    assert np.all(dv <= tau * R["S_visc"] + 1e-300), np.max(dv / (R["S_visc"] + 1e-300))
+    dT = np.abs(st[:, 15] - R["dTdt"])
+    assert np.all(dT <= tau * R["S_T"] + 1e-300), np.max(dT / (R["S_T"] + 1e-300))
+    dr = np.abs(st[:, 10] - o.drho)
+    assert np.all(dr <= tau * R["S_rho"] + 1e-300), np.max(dr / (R["S_rho"] + 1e-300))
+    # reports: time, sub-steps and global sums
+    assert rg["step"] == 1 and rg["n_ac"] == ro["n_ac"]
+    assert rg["t"] == pytest.approx(ro["t"], rel=1e-15)
+    assert rg["mass"] == pytest.approx(ro["mass"], rel=1e-12)
+    rtol = 1e-10 if precision == "fp64" else 1e-5
+    assert rg["thermal"] == pytest.approx(ro["thermal"], rel=1e-12 if precision == "fp64" else 1e-9)
+    assert rg["heat_step"] == pytest.approx(ro["heat_step"], rel=rtol)
+    for b, (bg, bo) in enumerate(zip(rg["bodies"], ro["bodies"])):
+        fs = np.abs(bo["force"]).max() + 1e-30
+        ts = np.abs(bo["torque"]).max() + 1e-30
+        assert np.max(np.abs(bg["force"] - bo["force"])) <= 1e-3 * fs if precision == "mixed" else 1e-9 * fs
+        assert np.max(np.abs(bg["torque"] - bo["torque"])) <= 1e-3 * ts if precision == "mixed" else 1e-9 * ts
+        assert bg["heat_rate"] == pytest.approx(bo["heat_rate"], rel=1e-4 if precision == "mixed" else 1e-10)
+
+
+# ---------------------------------------------------------------------------
+# neighbour sets after the particles and bodies have moved
+# ---------------------------------------------------------------------------
+
+def test_neighbour_sets_after_motion(sph, ora):
+    c = cases.tank_c1(seed=2)
+    say("sets after motion", c.nf)
+    s = sph.Solver(c, precision="mixed")
+    s.step(6)
+    s.reduce()
+    fid = s.dump("fluid_ids").astype(np.int64)
+    sid = s.dump("solid_ids").astype(np.int64)
+    st = s.dump("fluid_state").reshape(c.nf, 16)
+    sst = s.dump("solid_state").reshape(c.ns, 13)
+    xa = np.empty((c.nf, 3))
+    xa[fid] = st[:, 0:3]            # anchors = positions of the last build
+    xw = np.empty((c.ns, 3))
+    xw[sid] = sst[:, 0:3]
+    nb = ora.Nbr(c.params, xa, xw)
+    fl, so = s.neighbour_sets()
+    assert fl == nb.sets(0)
+    assert so == nb.sets(1)
+    rc, order = ora.sort_order(c.params, xa, np.arange(c.nf, dtype=np.uint32))
+    assert np.array_equal(fid, order)
+    s.close()
+
+
+# ---------------------------------------------------------------------------
+# multi-step run: invariants and agreement of integral quantities
+# ---------------------------------------------------------------------------
+
+def test_multi_step_tank(sph, ora):
+    c = cases.tank_c1(seed=0)
+    steps = 40
+    say("multi-step tank", steps)
+    o = ora.State(c)
+    s = sph.Solver(c, precision="mixed")
+    tq_o, tq_g = [], []
+    for k in range(steps):
+        ro = o.step()
+        s.step(1)
+        rg = s.reduce()
+        tq_o.append(ro["bodies"][1]["torque_axis"])
+        tq_g.append(rg["bodies"][1]["torque_axis"])
+        assert rg["n_ac"] == ro["n_ac"]
+        assert rg["mass"] == pytest.approx(ro["mass"], rel=1e-12)
+    assert rg["t"] == pytest.approx(ro["t"], rel=1e-6)
+    dT_o = ro["thermal"] - o.cum["heat"]
+    assert abs(rg["thermal"] - rg["heat_total"] - dT_o) <= 1e-6 * abs(ro["thermal"])
+    # heat balance on the GPU: thermal energy change equals the heat inflow
+    g = s.get_fluid()
+    cp, m = c.params["cp_f"], c.params["rho0"] * c.params["dp"] ** 3
+    dE = math.fsum(m * cp * (g["T"] - c.Tf))
+    assert abs(dE - rg["heat_total"]) <= 1e-5 * abs(rg["heat_total"])
+    # mean disk torque over the run agrees with the oracle
+    mo, mg = np.mean(tq_o), np.mean(tq_g)
+    assert abs(mg - mo) <= 0.02 * np.mean(np.abs(tq_o)), (mg, mo)
+    s.close()
+
+
+def test_determinism_and_graph_equals_eager(sph):
+    c = cases.tank_c1(seed=3)
+    say("determinism")
+    outs = []
+    for graph in (True, True, False):
+        s = sph.Solver(c, precision="mixed", graph=graph)
+        s.step(5)
+        r = s.reduce()
+        outs.append((s.get_fluid(), r))
+        s.close()
+    for g, r in outs[1:]:
+        for k in ("x", "v", "rho", "T"):
+            assert np.array_equal(g[k], outs[0][0][k])
+        assert r["bodies"][1]["torque_axis"] == outs[0][1]["bodies"][1]["torque_axis"]
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+
+def _lone_particle_case(n=1):
+    c = cases.still_tank(dp=2e-3, box=(0.02, 0.02, 0.02), fill=0.0)
+    c = c.copy()
+    c.xf = np.array([[0.01 + 0.02 * k, 0.01, 0.5] for k in range(n)])
+    c.vf = np.tile([0.1, -0.2, 0.3], (n, 1))
+    c.rhof = np.full(n, 870.0)
+    c.Tf = np.full(n, 313.15)
+    c.xs0 = np.zeros((0, 3))
+    c.ns0 = np.zeros((0, 3))
+    c.body = np.zeros(0, np.int32)
+    c.params["grid_lo"] = (-0.1, -0.1, -1.0)
+    c.params["grid_hi"] = (0.1, 0.1, 1.0)
+    return c
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_free_fall_single_particle(sph, precision):
+    c = _lone_particle_case()
+    say("free fall", precision)
+    s = sph.Solver(c, precision=precision, fixed_dt_ad=1e-4, fixed_nac=5)
+    s.step(200)
+    r = s.reduce()
+    t = r["t"]
+    g = np.array(c.params["gravity"])
+    x = np.array([0.01, 0.01, 0.5]) + np.array([0.1, -0.2, 0.3]) * t + 0.5 * g * t * t
+    out = s.get_fluid()
+    tol = 1e-13 if precision == "fp64" else 1e-9
+    assert np.allclose(out["x"][0], x, rtol=0, atol=tol)
+    s.close()
+
+
+def test_domain_error_at_init(sph):
+    c = cases.tank_c1().copy()
+    c.xf[5] = [5.0, 0.0, 0.0]
+    say("domain error")
+    with pytest.raises(sph.SphError) as e:
+        sph.Solver(c)
+    assert e.value.code == sph.SPH_ERR_DOMAIN
+
+
+def test_capacity_error(sph):
+    c = cases.tank_c1()
+    say("capacity error")
+    with pytest.raises(sph.SphError) as e:
+        sph.Solver(c, max_fluid_nbrs=16)
+    assert e.value.code == sph.SPH_ERR_CAPACITY
+
+
+def test_nonfinite_is_latched(sph):
+    c = cases.tank_c1()
+    say("non-finite latch")
+    s = sph.Solver(c)
+    s.step(1)
+    s.reduce()
+    s.poke_velocity(100, [float("nan"), 0.0, 0.0])
+    s.step(2)
+    r = s.reduce(raise_on_fault=False)
+    assert r["rc"] == sph.SPH_ERR_NONFINITE
+    assert r["step"] == 1
+    s.close()
