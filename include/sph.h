@@ -104,6 +104,7 @@ typedef struct {
   double heat_step;     /* dt_ad * sum over bodies of the heat flow into the fluid */
   double heat_total;    /* sum of heat_step since init */
   double mass_proxy;    /* sum rho dp^3 (drift of the continuity equation) */
+  int64_t substeps;     /* acoustic sub-steps completed since init */
 } sph_report;
 
 /* Per-body report: the last step's values (viscous part frozen for the step,

@@ -947,6 +947,7 @@ extern "C" int sph_init(sph_solver* s) {
   tab_for(P, std::vector<int>{slot}, T);
   rc = enqueue_sort_build(P, T);
   if (rc) return rc;
+  LCHK(launch(P, T, SPH_K_VISC_HEAT, 0, 0));   // writes the rows' pair geometry
   SlotCtl c;
   LCHK(read_ctl(P, P->slots[slot], &c, true));
   s->inited = true;

@@ -29,7 +29,7 @@ struct LaunchTab {
 // Device-resident control block of a slot, written only by kernels.
 struct SlotCtl {
   double t, dt_ad, dt;
-  int64_t step, target;
+  int64_t step, target, substeps;
   int32_t n_ac;
   uint32_t flags;
   double heat_total;

@@ -137,6 +137,14 @@ __device__ __forceinline__ typename P::Real press(const SlotDesc& S, typename P:
   return P::kRel ? c2 * s : c2 * (s - (Real)S.rho0);
 }
 
+// Reciprocal and reciprocal square root of the interaction type: the FP32
+// hardware instructions (about 1 ulp) in the FP32 sweeps, IEEE operations in
+// FP64 mode.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+
 // per-thread accumulators for up to NACC (= 2) bodies touched by one fluid
 // particle; explicit register arrays, selected by branches (no indexing by a
 // runtime value, so nothing goes to scratch)
@@ -167,8 +175,9 @@ struct BodyAcc {
 // Deterministic block reduction of per-thread body accumulators: for each
 // body and component, wave butterfly then the four waves in order.
 template <int W>
-__device__ __forceinline__ void block_body_reduce(const BodyAcc<W> acc, int nbody, double* out, bool accumulate,
-                                  double* lds /* [4][NB][W] */) {
+// out is quantity-major: out[(b * W + k) * nblk + lb]
+__device__ __forceinline__ void block_body_reduce(const BodyAcc<W> acc, int nbody, double* out, size_t nblk,
+                                                  int lb, bool accumulate, double* lds /* [4][NB][W] */) {
   const int wv = threadIdx.x / WAVE, ln = threadIdx.x % WAVE;
   for (int b = 0; b < nbody; ++b) {
 #pragma unroll
@@ -185,8 +194,9 @@ __device__ __forceinline__ void block_body_reduce(const BodyAcc<W> acc, int nbod
     s += lds[(1 * NB + b) * W + k];
     s += lds[(2 * NB + b) * W + k];
     s += lds[(3 * NB + b) * W + k];
-    if (accumulate) out[b * W + k] += s;
-    else out[b * W + k] = s;
+    double* o = out + (size_t)(b * W + k) * nblk + lb;
+    if (accumulate) *o += s;
+    else *o = s;
   }
 }
 
@@ -490,14 +500,30 @@ __global__ __launch_bounds__(BLOCK) void k_reorder(const SlotDesc* table, Launch
 
 // ---------------------------------------------------------------------------
 // K: neighbour rows (Section 2.8: neighbour lists and kernel quantities are
-// refreshed once per advection step).  For each fluid particle, the 27
-// surrounding cells are scanned; the cutoff test d^2 < (2h)^2 is FP64 with
-// d^2 = (dx dx + dy dy) + dz dz and no contraction.  Each hit stores the
-// neighbour index, r_ij rounded to the interaction type and F = (dW/dr)/r of
-// the Wendland C2 kernel.  The kernel sum (self, fluid, solid) drives the
+// refreshed once per advection step).  The cutoff test d^2 < (2h)^2 is FP64
+// with d^2 = (dx dx + dy dy) + dz dz and no contraction.  Each hit stores the
+// neighbour index (the pair geometry r_ij, F is written by the first sweep,
+// whose stores are coalesced).  The kernel sum (self, fluid, solid) drives the
 // density re-initialisation of Section 2.4 (eq. 14 with a free surface, eq. 15
 // without), against the perfect-lattice sum S0.
+//
+// A wavefront holds 64 consecutive particles of the Morton order, i.e. a few
+// neighbouring cells.  It walks the cells of its lanes' bounding box (plus one
+// layer) once; inside a cell every lane sees the same candidate, so candidate
+// positions are wave-uniform (scalar) loads, and each lane keeps the
+// candidates of its own 27-cell stencil.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, WAVE));
+  return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, WAVE));
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
 template <class P>
 __global__ __launch_bounds__(BLOCK) void k_build(const SlotDesc* table, LaunchTab tab) {
 #pragma clang fp contract(off)
@@ -506,82 +532,69 @@ __global__ __launch_bounds__(BLOCK) void k_build(const SlotDesc* table, LaunchTa
   SLOT_PROLOGUE(DOM_FLUID);
   const int i = lb * BLOCK + threadIdx.x;
   const int nf = S.nf, ns = S.ns;
-  if (i >= nf) return;
+  const bool act = i < nf;
+  const int ii = act ? i : nf - 1;
   const Pos* xa = (const Pos*)S.xa;
   const Pos* xw = (const Pos*)S.xw;
-  const Pos xi = xa[i], yi = xa[nf + i], zi = xa[2 * nf + i];
+  const Pos xi = xa[ii], yi = xa[nf + ii], zi = xa[2 * nf + ii];
   int c[3];
   cell_coords<Pos>(S, xi, yi, zi, c);
+  int lo[3], hi[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = max(wave_min_i(c[a]) - 1, 0);
+    hi[a] = min(wave_max_i(c[a]) + 1, S.dims[a] - 1);
+  }
   const int lane = i & (WAVE - 1);
   const int64_t slice = i >> 6;
   const int64_t basef = slice * (int64_t)S.kf * WAVE + lane;
   const int64_t bases = slice * (int64_t)S.ks * WAVE + lane;
-  Real* nr = (Real*)S.nr;
-  Real* nF = (Real*)S.nF;
-  Real* sr = (Real*)S.sr;
-  Real* sF = (Real*)S.sF;
-  const int64_t Lf = S.rowlen_f, Ls = S.rowlen_s;
-  const double h = S.h, cut2 = S.cut2, kW = S.kW, kF = S.kF;
+  const double h = S.h, cut2 = S.cut2, kW = S.kW;
+  const int kf = S.kf, ks = S.ks;
   int cf = 0, cs = 0;
   double sw = kW;  // W(0)
-  for (int dz = -1; dz <= 1; ++dz) {
-    const int cz = c[2] + dz;
-    if (cz < 0 || cz >= S.dims[2]) continue;
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int cy = c[1] + dy;
-      if (cy < 0 || cy >= S.dims[1]) continue;
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int cx = c[0] + dx;
-        if (cx < 0 || cx >= S.dims[0]) continue;
+  for (int cz = lo[2]; cz <= hi[2]; ++cz) {
+    for (int cy = lo[1]; cy <= hi[1]; ++cy) {
+      for (int cx = lo[0]; cx <= hi[0]; ++cx) {
+        const bool need = act && abs(cx - c[0]) <= 1 && abs(cy - c[1]) <= 1 && abs(cz - c[2]) <= 1;
+        if (!__any(need)) continue;
         const uint32_t r = S.rank[cell_linear(S, cx, cy, cz)];
-        for (uint32_t j = S.start_f[r], je = S.start_f[r + 1]; j < je; ++j) {
-          if ((int)j == i) continue;
+        const uint32_t j0 = S.start_f[r], j1 = S.start_f[r + 1];
+        for (uint32_t j = j0; j < j1; ++j) {
           const Pos ddx = xi - xa[j], ddy = yi - xa[nf + j], ddz = zi - xa[2 * nf + j];
           const Pos s2 = ddx * ddx + ddy * ddy;
           const Pos d2 = s2 + ddz * ddz;
-          if ((double)d2 < cut2) {
+          if (need && (int)j != i && (double)d2 < cut2) {
             const double rr = sqrt((double)d2);
             const double q = rr / h;
-            const double s = 1.0 - 0.5 * q;
-            sw += kW * s * s * s * s * (1.0 + 2.0 * q);
-            if (cf < S.kf) {
-              const int64_t o = basef + (int64_t)cf * WAVE;
-              S.nj[o] = j;
-              nr[o] = (Real)ddx;
-              nr[Lf + o] = (Real)ddy;
-              nr[2 * Lf + o] = (Real)ddz;
-              nF[o] = (Real)(kF * s * s * s);
-            }
+            const double t = 1.0 - 0.5 * q;
+            sw += kW * t * t * t * t * (1.0 + 2.0 * q);
+            if (cf < kf) S.nj[basef + (int64_t)cf * WAVE] = j;
             ++cf;
           }
         }
-        for (uint32_t w = S.start_s[r], we = S.start_s[r + 1]; w < we; ++w) {
+        const uint32_t w0 = S.start_s[r], w1 = S.start_s[r + 1];
+        for (uint32_t w = w0; w < w1; ++w) {
           const Pos ddx = xi - xw[w], ddy = yi - xw[ns + w], ddz = zi - xw[2 * ns + w];
           const Pos s2 = ddx * ddx + ddy * ddy;
           const Pos d2 = s2 + ddz * ddz;
-          if ((double)d2 < cut2) {
+          if (need && (double)d2 < cut2) {
             const double rr = sqrt((double)d2);
             const double q = rr / h;
-            const double s = 1.0 - 0.5 * q;
-            sw += kW * s * s * s * s * (1.0 + 2.0 * q);
-            if (cs < S.ks) {
-              const int64_t o = bases + (int64_t)cs * WAVE;
-              S.sj[o] = w;
-              sr[o] = (Real)ddx;
-              sr[Ls + o] = (Real)ddy;
-              sr[2 * Ls + o] = (Real)ddz;
-              sF[o] = (Real)(kF * s * s * s);
-            }
+            const double t = 1.0 - 0.5 * q;
+            sw += kW * t * t * t * t * (1.0 + 2.0 * q);
+            if (cs < ks) S.sj[bases + (int64_t)cs * WAVE] = w;
             ++cs;
           }
         }
       }
     }
   }
-  if (cf > S.kf || cs > S.ks) {
+  if (!act) return;
+  if (cf > kf || cs > ks) {
     raise_flag(S, F_CAPACITY);
-    cf = min(cf, S.kf);
-    cs = min(cs, S.ks);
+    cf = min(cf, kf);
+    cs = min(cs, ks);
   }
   S.nfc[i] = (uint32_t)cf;
   S.nsc[i] = (uint32_t)cs;
@@ -639,9 +652,28 @@ __global__ __launch_bounds__(BLOCK) void k_dt(const SlotDesc* table, LaunchTab t
   C->n_ac = nac;
 }
 
+// Frozen pair geometry of a row entry: r_ij = x_i - x_j from the FP64 anchors
+// (rounded to the interaction type) and F = (dW/dr)/r = kF (1 - q/2)^3 from
+// the FP64 distance, evaluated exactly as in the build's cutoff test.
+template <class Pos, class Real>
+__device__ __forceinline__ Real pair_geom(const SlotDesc& S, Pos xi, Pos yi, Pos zi, Pos xj, Pos yj, Pos zj,
+                                          Real& rx, Real& ry, Real& rz) {
+#pragma clang fp contract(off)
+  const Pos ddx = xi - xj, ddy = yi - yj, ddz = zi - zj;
+  const Pos s2 = ddx * ddx + ddy * ddy;
+  const Pos d2 = s2 + ddz * ddz;
+  const double q = sqrt((double)d2) / S.h;
+  const double t = 1.0 - 0.5 * q;
+  rx = (Real)ddx;
+  ry = (Real)ddy;
+  rz = (Real)ddz;
+  return (Real)(S.kF * t * t * t);
+}
+
 // ---------------------------------------------------------------------------
 // K: viscous acceleration (eq. 10 fluid-fluid, eq. 18 fluid-wall) and heat
-// conduction rate (eq. 22), both frozen for the advection step.  Per-block
+// conduction rate (eq. 22), both frozen for the advection step.  As the first
+// sweep over fresh rows it also writes each row entry's pair geometry.  Per-block
 // partials: viscous force and torque on each body and its heat flow into the
 // fluid.  Also clears this block's pressure-force accumulators.
 // ---------------------------------------------------------------------------
@@ -653,7 +685,8 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
   SLOT_PROLOGUE(DOM_FLUID);
   const int nf = S.nf, ns = S.ns;
   const int i = lb * BLOCK + threadIdx.x;
-  if (threadIdx.x < NB * 6) S.press_part[(size_t)lb * NB * 6 + threadIdx.x] = 0.0;
+  const size_t nbf = (size_t)S.nblk[DOM_FLUID];
+  if (threadIdx.x < NB * 6) S.press_part[(size_t)threadIdx.x * nbf + lb] = 0.0;
   BodyAcc<7> acc;
   acc.init();
   bool wall = false;
@@ -665,20 +698,30 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
     const Real vix = v[i], viy = v[nf + i], viz = v[2 * nf + i];
     const Real rhoi = rho_abs<P>(S, rho[i]);
     const Temp Ti = T[i];
-    const Real c2 = (Real)(2.0 * S.eta) / rhoi;   // 2 eta V_i / m_i
+    const Real c2 = (Real)(2.0 * S.eta) * rcp(rhoi);   // 2 eta V_i / m_i
     const Real Kff = (Real)(4.0 * S.k_f * S.k_f / (S.k_f + S.k_f));
     Real ax = 0, ay = 0, az = 0, hs = 0;
     const int lane = i & (WAVE - 1);
     const int64_t slice = i >> 6;
+    typedef typename P::Pos Pos;
+    const Pos* xa = (const Pos*)S.xa;
+    const Pos xi = xa[i], yi = xa[nf + i], zi = xa[2 * nf + i];
     {
       const int n = (int)S.nfc[i];
       const int64_t base = slice * (int64_t)S.kf * WAVE + lane;
-      const Real* F = (const Real*)S.nF;
+      Real* R = (Real*)S.nr;
+      Real* F = (Real*)S.nF;
+      const int64_t L = S.rowlen_f;
       for (int k = 0; k < n; ++k) {
         const int64_t o = base + (int64_t)k * WAVE;
         const uint32_t j = S.nj[o];
-        const Real Fk = F[o];
-        const Real Vj = m / rho_abs<P>(S, rho[j]);
+        Real rx, ry, rz;
+        const Real Fk = pair_geom<Pos, Real>(S, xi, yi, zi, xa[j], xa[nf + j], xa[2 * nf + j], rx, ry, rz);
+        R[o] = rx;
+        R[L + o] = ry;
+        R[2 * L + o] = rz;
+        F[o] = Fk;
+        const Real Vj = m * rcp(rho_abs<P>(S, rho[j]));
         const Real cv = c2 * Vj * Fk;
         ax += cv * (vix - v[j]);
         ay += cv * (viy - v[nf + j]);
@@ -690,15 +733,23 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
       const int n = (int)S.nsc[i];
       wall = n > 0;
       const int64_t base = slice * (int64_t)S.ks * WAVE + lane;
-      const Real* F = (const Real*)S.sF;
+      Real* R = (Real*)S.sr;
+      Real* F = (Real*)S.sF;
+      const int64_t L = S.rowlen_s;
+      const Pos* xw = (const Pos*)S.xw;
       const Real* vw = (const Real*)S.vw;
       const Real* lv = (const Real*)S.lev;
       const Real Vw = (Real)S.vol_w;
-      const Real rc = (Real)1 / (rhoi * (Real)S.cp_f);
+      const Real rc = rcp(rhoi * (Real)S.cp_f);
       for (int k = 0; k < n; ++k) {
         const int64_t o = base + (int64_t)k * WAVE;
         const uint32_t w = S.sj[o];
-        const Real Fk = F[o];
+        Real rx, ry, rz;
+        const Real Fk = pair_geom<Pos, Real>(S, xi, yi, zi, xw[w], xw[ns + w], xw[2 * ns + w], rx, ry, rz);
+        R[o] = rx;
+        R[L + o] = ry;
+        R[2 * L + o] = rz;
+        F[o] = Fk;
         const int b = S.body[w];
         const Real cv = c2 * Vw * Fk;
         const Real fx = cv * (vix - vw[w]), fy = cv * (viy - vw[ns + w]), fz = cv * (viz - vw[2 * ns + w]);
@@ -723,9 +774,9 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
     }
   }
   if (__syncthreads_or(wall))
-    block_body_reduce<7>(acc, S.nbody, S.visc_part + (size_t)lb * NB * 7, false, lds);
+    block_body_reduce<7>(acc, S.nbody, S.visc_part, nbf, lb, false, lds);
   else if (threadIdx.x < NB * 7)
-    S.visc_part[(size_t)lb * NB * 7 + threadIdx.x] = 0.0;
+    S.visc_part[(size_t)threadIdx.x * nbf + lb] = 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -774,7 +825,7 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(const SlotDesc* table, Launc
     const Real rs = rho[i];
     const Real rhoi = rho_abs<P>(S, rs);
     const Real pi = press<P>(S, rs);
-    const Real c2 = (Real)2 / rhoi;   // 2 V_i / m_i
+    const Real c2 = (Real)2 * rcp(rhoi);   // 2 V_i / m_i
     Real ax = 0, ay = 0, az = 0;
     const int lane = i & (WAVE - 1);
     const int64_t slice = i >> 6;
@@ -790,15 +841,15 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(const SlotDesc* table, Launc
         const Real rx = R[o], ry = R[L + o], rz = R[2 * L + o], Fk = F[o];
         const Real r2 = rx * rx + ry * ry + rz * rz;
         if (r2 == (Real)0) continue;
-        const Real inv = (Real)1 / sqrt(r2);
+        const Real inv = rsq(r2);
         const Real rsj = rho[j];
         const Real rhoj = rho_abs<P>(S, rsj);
         const Real pj = press<P>(S, rsj);
         // U_L - U_R = -(v_i - v_j) . e_ij
         const Real dU = -((vix - v[j]) * rx + (viy - v[nf + j]) * ry + (viz - v[2 * nf + j]) * rz) * inv;
         const Real beta = fmin((Real)3 * fmax(dU, (Real)0), c0);
-        const Real ps = (Real)0.5 * (pi + pj) + rhoi * rhoj * beta * dU / (rhoi + rhoj);
-        const Real s = -c2 * (m / rhoj) * ps * Fk;
+        const Real ps = (Real)0.5 * (pi + pj) + rhoi * rhoj * beta * dU * rcp(rhoi + rhoj);
+        const Real s = -c2 * (m * rcp(rhoj)) * ps * Fk;
         ax += s * rx;
         ay += s * ry;
         az += s * rz;
@@ -823,7 +874,7 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(const SlotDesc* table, Launc
         // right state of eq. 17: P_R = P_L + rho_f g . (x_w - x_f), rho_R from the EoS
         const Real PR = pi - rhoi * (gx * rx + gy * ry + gz * rz);
         const Real rhoR = rho0 + PR * ic02;
-        const Real ps = (rhoi * PR + rhoR * pi) / (rhoi + rhoR);   // eq. 19
+        const Real ps = (rhoi * PR + rhoR * pi) * rcp(rhoi + rhoR);   // eq. 19
         const Real s = -c2 * Vw * ps * Fk;
         const Real fx = s * rx, fy = s * ry, fz = s * rz;
         ax += fx;
@@ -851,7 +902,7 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(const SlotDesc* table, Launc
     dr[2 * nf + i] += hdt * nz;
   }
   if (__syncthreads_or(wall))
-    block_body_reduce<6>(acc, S.nbody, S.press_part + (size_t)lb * NB * 6, true, lds);
+    block_body_reduce<6>(acc, S.nbody, S.press_part, (size_t)S.nblk[DOM_FLUID], lb, true, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -889,14 +940,14 @@ __global__ __launch_bounds__(BLOCK) void k_continuity(const SlotDesc* table, Lau
       const Real rx = R[o], ry = R[L + o], rz = R[2 * L + o], Fk = F[o];
       const Real r2 = rx * rx + ry * ry + rz * rz;
       if (r2 == (Real)0) continue;
-      const Real rr = sqrt(r2);
+      const Real rr = r2 * rsq(r2);
       const Real rsj = rho[j];
       const Real rhoj = rho_abs<P>(S, rsj);
       const Real pj = press<P>(S, rsj);
       // (U* - U_L) dW = [ (v_i - v_j) . r / 2 + (p_i - p_j) r / (c0 (rho_i + rho_j)) ] F
       const Real vr = (vix - v[j]) * rx + (viy - v[nf + j]) * ry + (viz - v[2 * nf + j]) * rz;
-      const Real dv = (Real)0.5 * vr + (pi - pj) * rr / (c0 * (rhoi + rhoj));
-      sum += (m / rhoj) * dv * Fk;
+      const Real dv = (Real)0.5 * vr + (pi - pj) * rr * rcp(c0 * (rhoi + rhoj));
+      sum += (m * rcp(rhoj)) * dv * Fk;
     }
   }
   {
@@ -920,7 +971,7 @@ __global__ __launch_bounds__(BLOCK) void k_continuity(const SlotDesc* table, Lau
       const Real rhoR = rho0 + PR * ic02;
       const Real UL = -(nx * vix + ny * viy + nz * viz);
       const Real uw = -(nx * vw[w] + ny * vw[ns + w] + nz * vw[2 * ns + w]);
-      const Real Us = uw + (pi - PR) / (c0 * (rhoi + rhoR));
+      const Real Us = uw + (pi - PR) * rcp(c0 * (rhoi + rhoR));
       sum += Vw * (Us - UL) * (nx * rx + ny * ry + nz * rz) * Fk;
     }
   }
@@ -991,7 +1042,7 @@ __global__ __launch_bounds__(BLOCK) void k_end(const SlotDesc* table, LaunchTab 
     double s;
     if (k == 4) s = fmax(fmax(lds[0][4], lds[1][4]), fmax(lds[2][4], lds[3][4]));
     else s = ((lds[0][k] + lds[1][k]) + lds[2][k]) + lds[3][k];
-    S.glob_part[(size_t)lb * NGLOB + k] = s;
+    S.glob_part[(size_t)k * S.nblk[DOM_FLUID] + lb] = s;
   }
 }
 
@@ -1009,35 +1060,25 @@ __global__ __launch_bounds__(BLOCK) void k_final(const SlotDesc* table, LaunchTa
   const int wv = threadIdx.x / WAVE, ln = threadIdx.x % WAVE;
   for (int qi = wv; qi < nq; qi += BLOCK / WAVE) {
     // quantity qi: global k, or body b component c (7 viscous then 6 pressure)
+    // partials are quantity-major: src[q * nblk + block]
     const double* src;
-    size_t stride, off;
     bool is_max = false;
     if (qi < NGLOB) {
-      src = S.glob_part;
-      stride = NGLOB;
-      off = qi;
+      src = S.glob_part + (size_t)qi * nblk;
       is_max = qi == 4;
     } else {
       const int b = (qi - NGLOB) / 13, c = (qi - NGLOB) % 13;
-      if (c < 7) {
-        src = S.visc_part;
-        stride = (size_t)NB * 7;
-        off = (size_t)b * 7 + c;
-      } else {
-        src = S.press_part;
-        stride = (size_t)NB * 6;
-        off = (size_t)b * 6 + (c - 7);
-      }
+      src = c < 7 ? S.visc_part + (size_t)(b * 7 + c) * nblk : S.press_part + (size_t)(b * 6 + c - 7) * nblk;
     }
     if (is_max) {
       double m = 0.0;
-      for (int k = ln; k < nblk; k += WAVE) m = fmax(m, src[(size_t)k * stride + off]);
+      for (int k = ln; k < nblk; k += WAVE) m = fmax(m, src[k]);
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, WAVE));
       if (ln == 0) res[qi] = m;
     } else {
       KS ks = {0.0, 0.0};
-      for (int k = ln; k < nblk; k += WAVE) ks_add(ks, src[(size_t)k * stride + off]);
+      for (int k = ln; k < nblk; k += WAVE) ks_add(ks, src[k]);
       ks = wave_ks(ks);
       if (ln == 0) res[qi] = ks.s + ks.c;
     }
@@ -1072,6 +1113,7 @@ __global__ __launch_bounds__(BLOCK) void k_final(const SlotDesc* table, LaunchTa
   }
   C->t += tad;
   C->step += 1;
+  C->substeps += C->n_ac;
   const double hs = tad * qsum;
   C->heat_total += hs;
   sph_report& R = C->rep;
@@ -1087,6 +1129,7 @@ __global__ __launch_bounds__(BLOCK) void k_final(const SlotDesc* table, LaunchTa
   R.vmax = res[4];
   R.heat_step = hs;
   R.heat_total = C->heat_total;
+  R.substeps = C->substeps;
   finite = finite && isfinite(res[1]) && isfinite(res[2]) && isfinite(res[3]);
   if (!finite) C->flags |= F_NONFINITE;
   R.flags = (int32_t)C->flags;

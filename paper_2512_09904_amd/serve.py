@@ -1,0 +1,127 @@
+"""Continuous-batching server for parameter-sweep solves (shaft speed, immersion, viscosity).
+
+Requests arrive over time (Poisson arrivals in the sweep workload).  A
+request is admitted into a slot of the HIP pool as soon as a slot and enough
+of the HBM budget are free; its particle state stays resident on the GPU
+until it finishes.  All admitted solves advance together: every pool step is
+one batched launch sequence (a captured hipGraph per slot composition) over
+all active slots, so work of requests that arrived at different times
+overlaps on the device.  Finished slots are released at once and queued
+requests take their place.  Each solve's result does not depend on its
+neighbours in the batch (slot-aligned blocks, deterministic reductions).
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import math
+import time
+from typing import List, Optional
+
+import numpy as np
+
+from . import cases, sph
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds after the start of the run
+    case: "cases.Case"
+    steps: int
+    admitted: Optional[float] = None
+    finished: Optional[float] = None
+    report: Optional[dict] = None
+    slot: Optional[int] = None
+
+    @property
+    def latency(self):
+        return None if self.finished is None else self.finished - self.arrival
+
+
+def sweep_requests(n=64, seed=64, steps=500, nf_lo=5e4, nf_hi=2e6, rate=None, scale=1.0):
+    """The parameter-sweep workload: U(150, 600) rad/s, immersion U(20, 60) mm,
+    nu U(0.5, 3)e-4, fluid count log-uniform in [nf_lo, nf_hi], Poisson arrivals.
+
+    `scale` multiplies the particle counts (small runs for tests).
+    Returns (requests without arrival times, rng) when rate is None.
+    """
+    rng = np.random.default_rng(seed)
+    reqs = []
+    t = 0.0
+    for k in range(n):
+        om = float(rng.uniform(150.0, 600.0))
+        imm = float(rng.uniform(0.020, 0.060))
+        nu = float(rng.uniform(0.5e-4, 3e-4))
+        nf = int(math.exp(rng.uniform(math.log(nf_lo), math.log(nf_hi))) * scale)
+        if rate is not None:
+            t += float(rng.exponential(1.0 / rate))
+        c = cases.serving_tank(max(nf, 2000), om, imm, nu, seed=k)
+        reqs.append(Request(rid=k, arrival=t if rate is not None else 0.0, case=c, steps=steps))
+    return reqs
+
+
+class Server:
+    """Admits requests by HBM budget and free slots; steps all active slots together."""
+
+    def __init__(self, hbm_budget: int, max_slots: int = 16, precision: str = "mixed",
+                 steps_per_call: int = 10, graph: bool = True):
+        self.pool = sph.Pool(hbm_budget, max_slots=max_slots, precision=precision, graph=graph)
+        self.precision = precision
+        self.k = steps_per_call
+        self.max_slots = max_slots
+        self.budget = hbm_budget
+        self.peak_bytes = 0
+        self.peak_active = 0
+
+    def run(self, requests: List[Request], clock=time.perf_counter):
+        """Serve every request; fills admitted/finished/report on each."""
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        queue: collections.deque = collections.deque()
+        active = {}
+        t0 = clock()
+        while pending or queue or active:
+            now = clock() - t0
+            while pending and pending[0].arrival <= now:
+                queue.append(pending.popleft())
+            while queue:
+                r = queue[0]
+                if sph.Pool.bytes_required(r.case, self.precision) > self.budget:
+                    raise ValueError(f"request {r.rid} can never fit the HBM budget")
+                slot = self.pool.admit(r.case, r.steps)
+                if slot is None:
+                    break
+                queue.popleft()
+                r.slot = slot
+                r.admitted = clock() - t0
+                active[slot] = r
+            used, nact = self.pool.usage()
+            self.peak_bytes = max(self.peak_bytes, used)
+            self.peak_active = max(self.peak_active, nact)
+            if active:
+                self.pool.step(self.k)
+                # finished slots (their work has completed on the device)
+                for slot in list(active):
+                    done, rep = self.pool.poll(slot)
+                    if done:
+                        r = active.pop(slot)
+                        r.finished = clock() - t0
+                        r.report = rep
+                        r.final = self.pool.get_fluid(slot) if getattr(r, "keep_state", False) else None
+                        self.pool.release(slot)
+            elif pending:
+                time.sleep(max(0.0, min(0.01, pending[0].arrival - (clock() - t0))))
+        self.pool.stream.synchronize()
+        return requests
+
+    def close(self):
+        self.pool.close()
+
+
+def summarize(requests: List[Request], wall: float):
+    lat = np.array([r.latency for r in requests])
+    pstep = sum(r.case.nf * r.steps for r in requests)
+    return dict(n=len(requests), p50_s=float(np.percentile(lat, 50)), p95_s=float(np.percentile(lat, 95)),
+                p99_s=float(np.percentile(lat, 99)), mean_s=float(lat.mean()), wall_s=wall,
+                particle_steps_per_s=pstep / wall,
+                faults=sum(1 for r in requests if r.report and r.report.get("rc", 0) != 0))

@@ -52,7 +52,7 @@ class Report(C.Structure):
     _fields_ = [("t", C.c_double), ("step", C.c_int64), ("n_ac", C.c_int32), ("flags", C.c_int32),
                 ("dt_ad", C.c_double), ("dt", C.c_double), ("vmax", C.c_double), ("mass", C.c_double),
                 ("kinetic", C.c_double), ("thermal", C.c_double), ("heat_step", C.c_double),
-                ("heat_total", C.c_double), ("mass_proxy", C.c_double)]
+                ("heat_total", C.c_double), ("mass_proxy", C.c_double), ("substeps", C.c_int64)]
 
 
 class BodyReport(C.Structure):

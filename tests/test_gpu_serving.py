@@ -1,0 +1,145 @@
+"""Serving pool on the GPU: batched solves equal solo solves, admission by budget.
+
+Each request's result must be identical (bitwise) whether it runs alone or
+batched with others admitted at different times, since slots own whole
+blocks and every reduction has a fixed order.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from paper_2512_09904_amd import cases
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def sph():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_09904_amd import sph as S
+    S.lib()
+    return S
+
+
+def _wait(pool, slot, tries=500):
+    for _ in range(tries):
+        done, rep = pool.poll(slot)
+        if done:
+            return rep
+        time.sleep(0.005)
+    raise AssertionError(f"slot {slot} did not finish")
+
+
+def _requests():
+    return [cases.serving_tank(6000, 300.0, 0.03, 1e-4, seed=1),
+            cases.serving_tank(9000, 450.0, 0.045, 2e-4, seed=2),
+            cases.serving_tank(4000, 200.0, 0.025, 0.7e-4, seed=3)]
+
+
+def _run_pool(sph, reqs, steps, stagger, max_slots=4):
+    pool = sph.Pool(1 << 40, max_slots=max_slots)
+    out = {}
+    slots = {}
+    pending = list(range(len(reqs)))
+    k = 0
+    while pending or slots:
+        # admit request q once `stagger[q]` pool steps have been taken
+        for q in list(pending):
+            if stagger[q] <= k:
+                s = pool.admit(reqs[q], steps[q])
+                if s is not None:
+                    slots[s] = q
+                    pending.remove(q)
+        pool.step(1)
+        k += 1
+        for s in list(slots):
+            done, rep = pool.poll(s)
+            if done:
+                q = slots.pop(s)
+                out[q] = (pool.get_fluid(s), rep)
+                pool.release(s)
+        if k > 1000:
+            raise RuntimeError("pool did not drain")
+    pool.close()
+    return out
+
+
+def test_alone_equals_in_mix(sph):
+    reqs = _requests()
+    steps = [7, 5, 9]
+    say("serving: alone vs mix")
+    alone = {q: _run_pool(sph, [reqs[q]], [steps[q]], [0])[0] for q in range(3)}
+    mix = _run_pool(sph, reqs, steps, [0, 2, 3])
+    for q in range(3):
+        ga, ra = alone[q]
+        gm, rm = mix[q]
+        assert ra["rc"] == 0 and rm["rc"] == 0
+        assert ra["step"] == steps[q] == rm["step"]
+        for key in ("x", "v", "rho", "T"):
+            assert np.array_equal(ga[key], gm[key]), (q, key)
+        assert ra["bodies"][1]["torque_axis"] == rm["bodies"][1]["torque_axis"]
+        assert ra["heat_total"] == rm["heat_total"]
+
+
+def test_solver_equals_pool_slot(sph):
+    c = _requests()[0]
+    say("serving: solver vs pool")
+    s = sph.Solver(c)
+    s.step(5)
+    r = s.reduce()
+    g = s.get_fluid()
+    s.close()
+    gp, rp = _run_pool(sph, [c], [5], [0])[0]
+    for key in ("x", "v", "rho", "T"):
+        assert np.array_equal(g[key], gp[key]), key
+    assert r["bodies"][1]["torque_axis"] == rp["bodies"][1]["torque_axis"]
+
+
+def test_admission_respects_budget(sph):
+    reqs = _requests()
+    need = [sph.Pool.bytes_required(c) for c in reqs]
+    budget = need[0] + need[2] + 1
+    say("serving: budget", need, budget)
+    pool = sph.Pool(budget, max_slots=8)
+    s0 = pool.admit(reqs[0], 3)
+    assert s0 is not None
+    assert pool.admit(reqs[1], 3) is None          # does not fit next to request 0
+    s2 = pool.admit(reqs[2], 3)
+    assert s2 is not None
+    used, active = pool.usage()
+    assert used <= budget and active == 2
+    pool.step(3)
+    for s in (s0, s2):
+        rep = _wait(pool, s)
+        assert rep["rc"] == 0 and rep["step"] == 3
+        pool.release(s)
+    assert pool.admit(reqs[1], 3) is not None       # admitted once budget is free
+    pool.close()
+
+
+def test_faulted_slot_does_not_disturb_others(sph):
+    reqs = _requests()
+    bad = reqs[1].copy()
+    bad.xf[10] = [1.0, 1.0, 1.0]   # outside the grid: this solve faults at its first step
+    say("serving: fault isolation")
+    ref = _run_pool(sph, [reqs[0]], [4], [0])[0]
+    pool = sph.Pool(1 << 40, max_slots=4)
+    a = pool.admit(reqs[0], 4)
+    b = pool.admit(bad, 4)
+    pool.step(4)
+    rep_b = _wait(pool, b)
+    assert rep_b["rc"] == sph.SPH_ERR_DOMAIN
+    rep_a = _wait(pool, a)
+    assert rep_a["rc"] == 0 and rep_a["step"] == 4
+    g = pool.get_fluid(a)
+    for key in ("x", "v", "rho", "T"):
+        assert np.array_equal(g[key], ref[0][key])
+    pool.close()
