@@ -92,6 +92,87 @@ def cpu_baseline(case, steps=2):
                       f"solid particles) from the initial state, FP64 C/OpenMP oracle, {dt:.1f} s"}
 
 
+def serve_bench(args):
+    """Parameter-sweep serving: continuous batching vs one solve at a time.
+
+    Requests: shaft speed U(150, 600) rad/s, immersion U(20, 60) mm, nu
+    U(0.5, 3)e-4, fluid count log-uniform 50k-2M, `serve_steps` advection steps
+    each.  Each request's service time alone is measured first (one slot);
+    arrivals are Poisson with rate 0.85 / mean service time; the
+    one-at-a-time server's latencies follow exactly from the measured service
+    times (FIFO); the batched server is run live.
+    """
+    import torch
+    from paper_2512_09904_amd import serve, sph
+    budget = int(args.serve_budget_gb * (1 << 30))
+    t0 = time.perf_counter()
+    reqs = serve.sweep_requests(n=args.serve_n, seed=64, steps=args.serve_steps, scale=args.serve_scale)
+    log(f"generated {len(reqs)} requests in {time.perf_counter() - t0:.1f} s; "
+        f"fluid {sum(r.case.nf for r in reqs)} total")
+    # service time of each request alone
+    svc = []
+    for r in reqs:
+        pool = sph.Pool(budget, max_slots=1)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        slot = pool.admit(r.case, r.steps)
+        pool.step(r.steps)
+        while True:
+            done, rep = pool.poll(slot)
+            if done:
+                break
+            time.sleep(0.0005)
+        svc.append(time.perf_counter() - a)
+        r.alone = rep
+        pool.release(slot)
+        pool.close()
+    svc = np.array(svc)
+    sbar = float(svc.mean())
+    log(f"alone: mean service {sbar:.3f} s, total {svc.sum():.1f} s")
+    results = []
+    for seed in range(64, 64 + args.serve_seeds):
+        rng = np.random.default_rng(seed)
+        rate = 0.85 / sbar
+        arr = np.cumsum(rng.exponential(1.0 / rate, len(reqs)))
+        arr -= arr[0]
+        # one-at-a-time FIFO server on the same GPU: latencies from the service times
+        fin = np.zeros(len(reqs))
+        free = 0.0
+        for k in np.argsort(arr, kind="stable"):
+            start = max(arr[k], free)
+            fin[k] = start + svc[k]
+            free = fin[k]
+        lat1 = fin - arr
+        for r, a in zip(reqs, arr):
+            r.arrival = float(a)
+            r.admitted = r.finished = r.report = None
+        srv = serve.Server(budget, max_slots=args.serve_slots)
+        a = time.perf_counter()
+        srv.run(reqs)
+        wall = time.perf_counter() - a
+        summ = serve.summarize(reqs, wall)
+        same = all(np.array_equal(r.report["bodies"][1]["torque_axis"], r.alone["bodies"][1]["torque_axis"]) and
+                   r.report["heat_total"] == r.alone["heat_total"] for r in reqs)
+        results.append(dict(seed=seed, rate_per_s=rate, batched=summ, peak_slots=srv.peak_active,
+                            peak_gb=srv.peak_bytes / (1 << 30), results_equal_alone=bool(same),
+                            one_at_a_time=dict(p50_s=float(np.percentile(lat1, 50)),
+                                               p95_s=float(np.percentile(lat1, 95)),
+                                               p99_s=float(np.percentile(lat1, 99)),
+                                               wall_s=float(fin.max()),
+                                               particle_steps_per_s=float(sum(r.case.nf * r.steps for r in reqs) / fin.max()))))
+        srv.close()
+        log(json.dumps(results[-1]))
+    b = results[0]["batched"]
+    out = {"metric": "serving sweep: p50/p99 time-to-result and throughput, batched vs one at a time",
+           "value": b["particle_steps_per_s"], "unit": "fluid particle-steps/s", "n_gpus": 1,
+           "higher_is_better": True, "data": "synthetic", "dtype": "f32+f64",
+           "config": {"workload": f"{len(reqs)} serving-tank requests, {args.serve_steps} steps each, Poisson "
+                                  f"arrivals at 0.85/mean service, budget {args.serve_budget_gb} GB, "
+                                  f"{args.serve_slots} slots, particle scale {args.serve_scale}"},
+           "mean_service_alone_s": sbar, "seeds": results}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +184,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--calib-copy", action="store_true", help="run one 1 GiB device copy (counter calibration)")
+    ap.add_argument("--serve", action="store_true", help="serving sweep instead of the single-solve bench")
+    ap.add_argument("--serve-n", type=int, default=64)
+    ap.add_argument("--serve-steps", type=int, default=500)
+    ap.add_argument("--serve-scale", type=float, default=1.0, help="multiplies every request's particle count")
+    ap.add_argument("--serve-budget-gb", type=float, default=24.0)
+    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-seeds", type=int, default=1, help="arrival seeds (64, 65, ...)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -123,6 +211,10 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         log("calibration copy: 1 GiB read + 1 GiB written")
+        return
+
+    if args.serve:
+        serve_bench(args)
         return
 
     t0 = time.perf_counter()

@@ -89,8 +89,9 @@ static int make_plan(const sph_params* p, int prec, int64_t nf, int64_t ns, Plan
   P->nf = nf;
   P->ns = ns;
   P->ncells = (int32_t)ncell;
-  P->kf = p->max_fluid_nbrs > 0 ? p->max_fluid_nbrs : 128;
-  P->ks = p->max_solid_nbrs > 0 ? p->max_solid_nbrs : 96;
+  // capacities are rounded up to multiples of 4 (rows are walked 4 at a time)
+  P->kf = ((p->max_fluid_nbrs > 0 ? p->max_fluid_nbrs : 128) + 3) & ~3;
+  P->ks = ((p->max_solid_nbrs > 0 ? p->max_solid_nbrs : 96) + 3) & ~3;
   if (P->kf > 1024 || P->ks > 1024) return fail(SPH_ERR_ARG, "neighbour capacity above 1024");
   P->nslices = (int32_t)ceil_div(nf, WAVE);
   P->rowlen_f = (int64_t)P->nslices * P->kf * WAVE;
@@ -131,49 +132,43 @@ static size_t carve(const Plan& P, void* base, SlotDesc* d) {
   const size_t ps = P.pos_sz, rs = P.real_sz, ts = P.temp_sz;
   const size_t nbf = (size_t)P.nblk[DOM_FLUID], nbc = (size_t)P.nblk[DOM_CELL];
   C.take(D.ctl, sizeof(SlotCtl));
-  C.takev(D.xa, 3 * nf * ps);
-  C.takev(D.drift, 3 * nf * rs);
-  C.takev(D.v, 3 * nf * rs);
-  C.takev(D.vnew, 3 * nf * rs);
-  C.takev(D.rho, nf * rs);
+  C.takev(D.xa, 4 * nf * ps);
+  C.takev(D.drift, 4 * nf * rs);
+  C.takev(D.vr, 4 * nf * rs);
+  C.takev(D.vrn, 4 * nf * rs);
   C.takev(D.drho, nf * rs);
   C.takev(D.T, nf * ts);
-  C.takev(D.av, 3 * nf * rs);
-  C.takev(D.dTdt, nf * rs);
+  C.takev(D.ah, 4 * nf * rs);
   C.take(D.fid, nf * 4);
   C.take(D.sumW, nf * 8);
   C.take(D.fcell, nf * 4);
   C.take(D.fperm, nf * 4);
-  C.takev(D.xa2, 3 * nf * ps);
-  C.takev(D.v2, 3 * nf * rs);
-  C.takev(D.rho2, nf * rs);
+  C.takev(D.xa2, 4 * nf * ps);
+  C.takev(D.vr2, 4 * nf * rs);
   C.takev(D.drho2, nf * rs);
   C.takev(D.T2, nf * ts);
   C.take(D.fid2, nf * 4);
   C.take(D.nfc, nf * 4);
   C.take(D.nsc, nf * 4);
-  C.take(D.nj, (size_t)P.rowlen_f * 4);
-  C.takev(D.nr, 3 * (size_t)P.rowlen_f * rs);
-  C.takev(D.nF, (size_t)P.rowlen_f * rs);
-  C.take(D.sj, (size_t)P.rowlen_s * 4);
-  C.takev(D.sr, 3 * (size_t)P.rowlen_s * rs);
-  C.takev(D.sF, (size_t)P.rowlen_s * rs);
-  C.take(D.x0, 3 * ns * 8);
-  C.take(D.n0, 3 * ns * 8);
+  C.take(D.jstage, nf * (size_t)(P.kf + P.ks) * 4);
+  C.takev(D.nrec, 4 * (size_t)P.rowlen_f * rs);
+  C.takev(D.srec, 4 * (size_t)P.rowlen_s * rs);
+  C.takev(D.x0, ns * 32);
+  C.takev(D.n0, ns * 32);
   C.take(D.body, ns * 4);
   C.take(D.sid, ns * 4);
-  C.takev(D.xw, 3 * ns * ps);
-  C.takev(D.nw, 3 * ns * rs);
-  C.takev(D.vw, 3 * ns * rs);
-  C.takev(D.lev, 3 * ns * rs);
-  C.take(D.x0b, 3 * ns * 8);
-  C.take(D.n0b, 3 * ns * 8);
+  C.takev(D.xw, 4 * ns * ps);
+  C.takev(D.nw, 4 * ns * rs);
+  C.takev(D.vw, 4 * ns * rs);
+  C.takev(D.lev, 4 * ns * rs);
+  C.takev(D.x0b, ns * 32);
+  C.takev(D.n0b, ns * 32);
   C.take(D.bodyb, ns * 4);
   C.take(D.sidb, ns * 4);
-  C.takev(D.xwb, 3 * ns * ps);
-  C.takev(D.nwb, 3 * ns * rs);
-  C.takev(D.vwb, 3 * ns * rs);
-  C.takev(D.levb, 3 * ns * rs);
+  C.takev(D.xwb, 4 * ns * ps);
+  C.takev(D.nwb, 4 * ns * rs);
+  C.takev(D.vwb, 4 * ns * rs);
+  C.takev(D.levb, 4 * ns * rs);
   C.take(D.scell, ns * 4);
   C.take(D.sperm, ns * 4);
   C.take(D.rank, nc * 4);
@@ -490,31 +485,29 @@ static int upload_slot(sph_pool* P, SlotHost& S, const double* x, const double* 
   const bool rel = pl.prec != SPH_PREC_FP32;
   std::vector<uint32_t> rank;
   rank_table(pl.dims, rank, S.morton_of_rank);
-  // staging: xa | v | rho | T | fid | x0 | n0 | body | sid | rank
-  const size_t o_xa = 0, o_v = o_xa + 3 * nf * ps, o_rho = o_v + 3 * nf * rs, o_T = o_rho + nf * rs,
-               o_fid = o_T + nf * ts, o_x0 = o_fid + nf * 4, o_n0 = o_x0 + 3 * ns * 8, o_b = o_n0 + 3 * ns * 8,
-               o_sid = o_b + ns * 4, o_rank = o_sid + ns * 4, o_end = o_rank + rank.size() * 4;
+  // staging: xa (x,y,z,0) | vr (vx,vy,vz,rho) | T | fid | x0 (x,y,z,0) | n0 | body | sid | rank
+  const size_t o_xa = 0, o_v = o_xa + 4 * nf * ps, o_T = o_v + 4 * nf * rs, o_fid = o_T + nf * ts,
+               o_x0 = o_fid + nf * 4, o_n0 = o_x0 + ns * 32, o_b = o_n0 + ns * 32, o_sid = o_b + ns * 4,
+               o_rank = o_sid + ns * 4, o_end = o_rank + rank.size() * 4;
   S.staging.assign(o_end, 0);
   std::vector<char>& B = S.staging;
+  auto put_real = [&](size_t off, size_t sz, size_t idx, double val) {
+    if (sz == 8) put<double>(B, off + idx * 8, val);
+    else put<float>(B, off + idx * 4, (float)val);
+  };
   for (size_t i = 0; i < nf; ++i) {
     for (size_t k = 0; k < 3; ++k) {
-      const double xv = x[3 * i + k], vv = v ? v[3 * i + k] : 0.0;
-      if (ps == 8) put<double>(B, o_xa + (k * nf + i) * 8, xv);
-      else put<float>(B, o_xa + (k * nf + i) * 4, (float)xv);
-      if (rs == 8) put<double>(B, o_v + (k * nf + i) * 8, vv);
-      else put<float>(B, o_v + (k * nf + i) * 4, (float)vv);
+      put_real(o_xa, ps, 4 * i + k, x[3 * i + k]);
+      put_real(o_v, rs, 4 * i + k, v ? v[3 * i + k] : 0.0);
     }
-    const double r = rel ? rho[i] - rho0 : rho[i];
-    if (rs == 8) put<double>(B, o_rho + i * 8, r);
-    else put<float>(B, o_rho + i * 4, (float)r);
-    if (ts == 8) put<double>(B, o_T + i * 8, T[i]);
-    else put<float>(B, o_T + i * 4, (float)T[i]);
+    put_real(o_v, rs, 4 * i + 3, rel ? rho[i] - rho0 : rho[i]);
+    put_real(o_T, ts, i, T[i]);
     put<uint32_t>(B, o_fid + i * 4, (uint32_t)i);
   }
   for (size_t w = 0; w < ns; ++w) {
     for (size_t k = 0; k < 3; ++k) {
-      put<double>(B, o_x0 + (k * ns + w) * 8, x0[3 * w + k]);
-      put<double>(B, o_n0 + (k * ns + w) * 8, n0[3 * w + k]);
+      put<double>(B, o_x0 + (4 * w + k) * 8, x0[3 * w + k]);
+      put<double>(B, o_n0 + (4 * w + k) * 8, n0[3 * w + k]);
     }
     put<int32_t>(B, o_b + w * 4, body[w]);
     put<uint32_t>(B, o_sid + w * 4, (uint32_t)w);
@@ -523,14 +516,13 @@ static int upload_slot(sph_pool* P, SlotHost& S, const double* x, const double* 
   hipStream_t st = P->stream;
   const SlotDesc& D = S.d;
   HIPCHK(hipMemsetAsync(S.arena, 0, S.bytes, st));
-  HIPCHK(hipMemcpyAsync(D.xa, B.data() + o_xa, 3 * nf * ps, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(D.v, B.data() + o_v, 3 * nf * rs, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(D.rho, B.data() + o_rho, nf * rs, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(D.xa, B.data() + o_xa, 4 * nf * ps, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(D.vr, B.data() + o_v, 4 * nf * rs, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(D.T, B.data() + o_T, nf * ts, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(D.fid, B.data() + o_fid, nf * 4, hipMemcpyHostToDevice, st));
   if (ns) {
-    HIPCHK(hipMemcpyAsync(D.x0, B.data() + o_x0, 3 * ns * 8, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(D.n0, B.data() + o_n0, 3 * ns * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(D.x0, B.data() + o_x0, ns * 32, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(D.n0, B.data() + o_n0, ns * 32, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(D.body, B.data() + o_b, ns * 4, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(D.sid, B.data() + o_sid, ns * 4, hipMemcpyHostToDevice, st));
   }
@@ -862,22 +854,20 @@ static int slot_get_fluid(sph_pool* P, SlotHost& S, double* x, double* v, double
   const Plan& pl = S.plan;
   const size_t nf = (size_t)pl.nf;
   std::vector<uint32_t> fid(nf);
-  std::vector<char> xa(3 * nf * pl.pos_sz), dr(3 * nf * pl.real_sz), vv(3 * nf * pl.real_sz),
-      rr(nf * pl.real_sz), tt(nf * pl.temp_sz);
+  std::vector<char> xa(4 * nf * pl.pos_sz), dr(4 * nf * pl.real_sz), vv(4 * nf * pl.real_sz), tt(nf * pl.temp_sz);
   LCHK(d2h(fid.data(), S.d.fid, nf * 4));
   LCHK(d2h(xa.data(), S.d.xa, xa.size()));
   LCHK(d2h(dr.data(), S.d.drift, dr.size()));
-  LCHK(d2h(vv.data(), S.d.v, vv.size()));
-  LCHK(d2h(rr.data(), S.d.rho, rr.size()));
+  LCHK(d2h(vv.data(), S.d.vr, vv.size()));
   LCHK(d2h(tt.data(), S.d.T, tt.size()));
   const bool rel = pl.prec != SPH_PREC_FP32;
   for (size_t k = 0; k < nf; ++k) {
     const size_t o = fid[k];
     for (size_t a = 0; a < 3; ++a) {
-      if (x) x[3 * o + a] = get_as_double(xa.data(), a * nf + k, pl.pos_sz) + get_as_double(dr.data(), a * nf + k, pl.real_sz);
-      if (v) v[3 * o + a] = get_as_double(vv.data(), a * nf + k, pl.real_sz);
+      if (x) x[3 * o + a] = get_as_double(xa.data(), 4 * k + a, pl.pos_sz) + get_as_double(dr.data(), 4 * k + a, pl.real_sz);
+      if (v) v[3 * o + a] = get_as_double(vv.data(), 4 * k + a, pl.real_sz);
     }
-    if (rho) rho[o] = get_as_double(rr.data(), k, pl.real_sz) + (rel ? S.params.rho0 : 0.0);
+    if (rho) rho[o] = get_as_double(vv.data(), 4 * k + 3, pl.real_sz) + (rel ? S.params.rho0 : 0.0);
     if (T) T[o] = get_as_double(tt.data(), k, pl.temp_sz);
   }
   return SPH_OK;
@@ -1068,12 +1058,24 @@ extern "C" int sph_debug_dump(sph_solver* s, int32_t what, void* buf, size_t byt
     }
     case SPH_DUMP_NBR_FLUID:
     case SPH_DUMP_NBR_SOLID: {
+      // the index lives in the fourth lane of each row record
       const bool sol = what == SPH_DUMP_NBR_SOLID;
-      const int K = sol ? pl.kf * 0 + pl.ks : pl.kf;
-      std::vector<uint32_t> raw((size_t)(sol ? pl.rowlen_s : pl.rowlen_f));
-      LCHK(d2h(raw.data(), sol ? (void*)D.sj : (void*)D.nj, raw.size() * 4));
+      const int K = sol ? pl.ks : pl.kf;
+      const size_t L = (size_t)(sol ? pl.rowlen_s : pl.rowlen_f);
+      std::vector<char> r(4 * L * rs);
+      LCHK(d2h(r.data(), sol ? D.srec : D.nrec, r.size()));
       uint32_t* o = (uint32_t*)buf;
-      unsell(pl, K, [&](size_t i, int k, size_t src) { o[i * (size_t)K + (size_t)k] = raw[src]; });
+      unsell(pl, K, [&](size_t i, int k, size_t src) {
+        uint32_t j;
+        if (rs == 8) {
+          double d;
+          std::memcpy(&d, r.data() + (4 * src + 3) * 8, 8);
+          j = (uint32_t)d;
+        } else {
+          std::memcpy(&j, r.data() + (4 * src + 3) * 4, 4);
+        }
+        o[i * (size_t)K + (size_t)k] = j;
+      });
       return SPH_OK;
     }
     case SPH_DUMP_GEOM_FLUID:
@@ -1081,49 +1083,43 @@ extern "C" int sph_debug_dump(sph_solver* s, int32_t what, void* buf, size_t byt
       const bool sol = what == SPH_DUMP_GEOM_SOLID;
       const int K = sol ? pl.ks : pl.kf;
       const size_t L = (size_t)(sol ? pl.rowlen_s : pl.rowlen_f);
-      std::vector<char> r(3 * L * rs), F(L * rs);
-      LCHK(d2h(r.data(), sol ? D.sr : D.nr, r.size()));
-      LCHK(d2h(F.data(), sol ? D.sF : D.nF, F.size()));
+      std::vector<char> r(4 * L * rs);
+      LCHK(d2h(r.data(), sol ? D.srec : D.nrec, r.size()));
       double* o = (double*)buf;
       unsell(pl, K, [&](size_t i, int k, size_t src) {
         double* e = o + (i * (size_t)K + (size_t)k) * 4;
-        e[0] = get_as_double(r.data(), src, rs);
-        e[1] = get_as_double(r.data(), L + src, rs);
-        e[2] = get_as_double(r.data(), 2 * L + src, rs);
-        e[3] = get_as_double(F.data(), src, rs);
+        for (size_t a = 0; a < 3; ++a) e[a] = get_as_double(r.data(), 4 * src + a, rs);
+        e[3] = 0.0;
       });
       return SPH_OK;
     }
     case SPH_DUMP_FLUID_STATE: {
-      std::vector<char> xa(3 * nf * ps), dr(3 * nf * rs), v(3 * nf * rs), rho(nf * rs), drho(nf * rs),
-          T(nf * ts), av(3 * nf * rs), dT(nf * rs);
+      std::vector<char> xa(4 * nf * ps), dr(4 * nf * rs), v(4 * nf * rs), drho(nf * rs), T(nf * ts), ah(4 * nf * rs);
       LCHK(d2h(xa.data(), D.xa, xa.size()));
       LCHK(d2h(dr.data(), D.drift, dr.size()));
-      LCHK(d2h(v.data(), D.v, v.size()));
-      LCHK(d2h(rho.data(), D.rho, rho.size()));
+      LCHK(d2h(v.data(), D.vr, v.size()));
       LCHK(d2h(drho.data(), D.drho, drho.size()));
       LCHK(d2h(T.data(), D.T, T.size()));
-      LCHK(d2h(av.data(), D.av, av.size()));
-      LCHK(d2h(dT.data(), D.dTdt, dT.size()));
+      LCHK(d2h(ah.data(), D.ah, ah.size()));
       const bool rel = pl.prec != SPH_PREC_FP32;
       double* o = (double*)buf;
       for (size_t i = 0; i < nf; ++i) {
         double* e = o + i * 16;
         for (size_t a = 0; a < 3; ++a) {
-          e[a] = get_as_double(xa.data(), a * nf + i, ps);
-          e[3 + a] = get_as_double(dr.data(), a * nf + i, rs);
-          e[6 + a] = get_as_double(v.data(), a * nf + i, rs);
-          e[12 + a] = get_as_double(av.data(), a * nf + i, rs);
+          e[a] = get_as_double(xa.data(), 4 * i + a, ps);
+          e[3 + a] = get_as_double(dr.data(), 4 * i + a, rs);
+          e[6 + a] = get_as_double(v.data(), 4 * i + a, rs);
+          e[12 + a] = get_as_double(ah.data(), 4 * i + a, rs);
         }
-        e[9] = get_as_double(rho.data(), i, rs) + (rel ? S.params.rho0 : 0.0);
+        e[9] = get_as_double(v.data(), 4 * i + 3, rs) + (rel ? S.params.rho0 : 0.0);
         e[10] = get_as_double(drho.data(), i, rs);
         e[11] = get_as_double(T.data(), i, ts);
-        e[15] = get_as_double(dT.data(), i, rs);
+        e[15] = get_as_double(ah.data(), 4 * i + 3, rs);
       }
       return SPH_OK;
     }
     case SPH_DUMP_SOLID_STATE: {
-      std::vector<char> x(3 * ns * ps), n(3 * ns * rs), v(3 * ns * rs), l(3 * ns * rs);
+      std::vector<char> x(4 * ns * ps), n(4 * ns * rs), v(4 * ns * rs), l(4 * ns * rs);
       std::vector<int32_t> b(ns);
       LCHK(d2h(x.data(), D.xw, x.size()));
       LCHK(d2h(n.data(), D.nw, n.size()));
@@ -1134,10 +1130,10 @@ extern "C" int sph_debug_dump(sph_solver* s, int32_t what, void* buf, size_t byt
       for (size_t w = 0; w < ns; ++w) {
         double* e = o + w * 13;
         for (size_t a = 0; a < 3; ++a) {
-          e[a] = get_as_double(x.data(), a * ns + w, ps);
-          e[3 + a] = get_as_double(n.data(), a * ns + w, rs);
-          e[6 + a] = get_as_double(v.data(), a * ns + w, rs);
-          e[9 + a] = get_as_double(l.data(), a * ns + w, rs);
+          e[a] = get_as_double(x.data(), 4 * w + a, ps);
+          e[3 + a] = get_as_double(n.data(), 4 * w + a, rs);
+          e[6 + a] = get_as_double(v.data(), 4 * w + a, rs);
+          e[9 + a] = get_as_double(l.data(), 4 * w + a, rs);
         }
         e[12] = (double)b[w];
       }
@@ -1158,13 +1154,14 @@ extern "C" int sph_debug_poke_velocity(sph_solver* s, int64_t orig, const double
   LCHK(d2h(fid.data(), S.d.fid, fid.size() * 4));
   size_t k = 0;
   while (k < fid.size() && fid[k] != (uint32_t)orig) ++k;
-  const size_t nf = (size_t)pl.nf;
+  if (k == fid.size()) return fail(SPH_ERR_ARG, "index not found");
   for (size_t a = 0; a < 3; ++a) {
+    char* dst = (char*)S.d.vr + (4 * k + a) * pl.real_sz;
     if (pl.real_sz == 8) {
-      HIPCHK(hipMemcpy((char*)S.d.v + (a * nf + k) * 8, &v3[a], 8, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(dst, &v3[a], 8, hipMemcpyHostToDevice));
     } else {
       const float f = (float)v3[a];
-      HIPCHK(hipMemcpy((char*)S.d.v + (a * nf + k) * 4, &f, 4, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(dst, &f, 4, hipMemcpyHostToDevice));
     }
   }
   return SPH_OK;

@@ -39,7 +39,11 @@ struct SlotCtl {
 };
 
 // Everything a kernel needs to know about one slot.  Arrays are in the
-// cell-sorted order; 3-vectors are SoA with stride n (x at [0,n), y, z).
+// cell-sorted order.  Vectors are stored as 4-wide records (16 B in FP32,
+// 32 B in FP64) so that one load or one gather moves a whole record:
+//   anchor x (x, y, z, 0)          velocity state (vx, vy, vz, delta-rho)
+//   rates (ax, ay, az, dT/dt)       row entry (rx, ry, rz, F)
+//   solid lever arm (lx, ly, lz, body index)
 struct SlotDesc {
   int32_t nf, ns, ncells, nslices;
   int32_t kf, ks, nbody, nac_bound;
@@ -54,35 +58,34 @@ struct SlotDesc {
   double bc[NB][3], ba[NB][3], bom[NB], bT[NB], bk[NB], btip[NB];
   SlotCtl* ctl;
   // fluid state (sorted order) and its gather buffers
-  void *xa, *drift, *v, *vnew, *rho, *drho, *T, *av, *dTdt;
+  void *xa, *drift, *vr, *vrn, *drho, *T, *ah;
   uint32_t *fid;
   double *sumW;
   uint32_t *fcell, *fperm;
-  void *xa2, *v2, *rho2, *drho2, *T2;
+  void *xa2, *vr2, *drho2, *T2;
   uint32_t *fid2;
-  // neighbour rows (SELL, slice height 64): index, r_ij (3 arrays), F
+  // neighbour rows (SELL, slice height 64) of records (rx, ry, rz, j)
   uint32_t *nfc, *nsc;
-  uint32_t *nj;
-  void *nr, *nF;
-  uint32_t *sj;
-  void *sr, *sF;
-  // solids
-  double *x0, *n0;
+  uint32_t *jstage;     // build output: per particle kf fluid then ks solid indices
+  void *nrec;
+  void *srec;
+  // solids: FP64 reference pose (x, y, z, 0) and normal, body; current pose
+  void *x0, *n0;
   int32_t *body;
   uint32_t *sid;
   void *xw, *nw, *vw, *lev;
-  double *x0b, *n0b;
+  void *x0b, *n0b;
   int32_t *bodyb;
   uint32_t *sidb;
   void *xwb, *nwb, *vwb, *levb;
   uint32_t *scell, *sperm;
   // cells
   uint32_t *rank, *cnt_f, *cnt_s, *start_f, *start_s, *bsum_f, *bsum_s;
-  // per fluid-block partials
+  // per fluid-block partials, quantity-major ([quantity][block])
   float *vmax_part;
-  double *visc_part;    // [nblk_f][NB][7]: force(3) torque(3) heat
-  double *press_part;   // [nblk_f][NB][6]: sum over sub-steps of force(3) torque(3)
-  double *glob_part;    // [nblk_f][NGLOB]
+  double *visc_part;    // [NB * 7]: force(3) torque(3) heat
+  double *press_part;   // [NB * 6]: sum over sub-steps of force(3) torque(3)
+  double *glob_part;    // [NGLOB]
 };
 
 // Launch one kernel of the step.  prec: SPH_PREC_*; kid: SPH_K_*; sub: the

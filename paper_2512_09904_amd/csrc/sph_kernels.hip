@@ -20,30 +20,63 @@ namespace sphk {
 // ---------------------------------------------------------------------------
 // precision policies: position anchors, interaction arithmetic, temperature
 // ---------------------------------------------------------------------------
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+
 struct PMixed {
   typedef double Pos;
   typedef float Real;
   typedef double Temp;
+  typedef d4 Pos4;
+  typedef f4 Real4;
   static constexpr bool kRel = true;   // density stored as rho - rho0
 };
 struct PF64 {
   typedef double Pos;
   typedef double Real;
   typedef double Temp;
+  typedef d4 Pos4;
+  typedef d4 Real4;
   static constexpr bool kRel = true;
 };
 struct PF32 {
   typedef float Pos;
   typedef float Real;
   typedef float Temp;
+  typedef f4 Pos4;
+  typedef f4 Real4;
   static constexpr bool kRel = false;  // absolute density in FP32
 };
+
+// Arrays live in device global memory; loads through these pointers compile
+// to global (not flat) memory instructions.
+#define GLB __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ GLB T* gp(void* p) {
+  return (GLB T*)p;
+}
+template <class T>
+__device__ __forceinline__ const GLB T* gpc(const void* p) {
+  return (const GLB T*)p;
+}
 
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Logical block numbers are laid out so that every XCD runs one
+// contiguous range of blocks, i.e. one contiguous range of Morton-sorted
+// particles, and the neighbour gathers of adjacent blocks hit the same L2.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_block(int b, int g) {
+  const int q = g / NXCD, r = g % NXCD;
+  const int x = b % NXCD, k = b / NXCD;
+  return x * q + min(x, r) + k;
+}
+
 __device__ __forceinline__ int find_slot(const LaunchTab& L, int dom, int& lb) {
-  const int blk = blockIdx.x;
+  const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
   int k = 0;
   for (int s = 1; s < L.n; ++s)
     if (blk >= L.blk0[dom][s]) k = s;
@@ -145,6 +178,29 @@ __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
 
+// A row entry is one 4-wide record (rx, ry, rz, j): the pair vector of the
+// build, rounded to the interaction type, with the neighbour index in the
+// fourth lane (bit pattern in FP32, exact value in FP64).
+__device__ __forceinline__ float pack_index(uint32_t j, float) { return __builtin_bit_cast(float, j); }
+__device__ __forceinline__ double pack_index(uint32_t j, double) { return (double)j; }
+__device__ __forceinline__ uint32_t unpack_index(float w) { return __builtin_bit_cast(uint32_t, w); }
+__device__ __forceinline__ uint32_t unpack_index(double w) { return (uint32_t)w; }
+
+// F = (dW/dr)/r = kF (1 - q/2)^3 of the Wendland C2 kernel from |r|^2
+template <class Real>
+__device__ __forceinline__ Real kernel_F(Real r2, Real inv_h, Real kF) {
+  const Real q = r2 * rsq(r2) * inv_h;
+  const Real t = (Real)1 - (Real)0.5 * q;
+  return r2 > (Real)0 ? kF * t * t * t : kF;
+}
+
+// rows are streamed once per sweep: non-temporal loads keep them from
+// evicting the gathered particle state in L2
+template <class T>
+__device__ __forceinline__ T ldnt(const GLB T* p) {
+  return __builtin_nontemporal_load(p);
+}
+
 // per-thread accumulators for up to NACC (= 2) bodies touched by one fluid
 // particle; explicit register arrays, selected by branches (no indexing by a
 // runtime value, so nothing goes to scratch)
@@ -223,22 +279,22 @@ __global__ __launch_bounds__(BLOCK) void k_pose(const SlotDesc* table, LaunchTab
 #pragma clang fp contract(off)
   typedef typename P::Pos Pos;
   typedef typename P::Real Real;
+  typedef typename P::Pos4 Pos4;
+  typedef typename P::Real4 Real4;
   SLOT_PROLOGUE(DOM_SOLID);
   const int w = lb * BLOCK + threadIdx.x;
-  const int ns = S.ns;
-  if (w >= ns) return;
+  if (w >= S.ns) return;
   const int b = S.body[w];
   const double th = S.bom[b] * S.ctl->t;
   double sn, cs;
   sincos(th, &sn, &cs);
   const double* a = S.ba[b];
   const double* ctr = S.bc[b];
-  double u[3], n[3], ru[3], rn[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    u[k] = S.x0[k * ns + w] - ctr[k];
-    n[k] = S.n0[k * ns + w];
-  }
+  const d4 x0 = gpc<d4>(S.x0)[w];
+  const d4 n0 = gpc<d4>(S.n0)[w];
+  const double u[3] = {x0.x - ctr[0], x0.y - ctr[1], x0.z - ctr[2]};
+  const double n[3] = {n0.x, n0.y, n0.z};
+  double ru[3], rn[3];
   {
     const double axu[3] = {a[1] * u[2] - a[2] * u[1], a[2] * u[0] - a[0] * u[2], a[0] * u[1] - a[1] * u[0]};
     const double au = a[0] * u[0] + a[1] * u[1] + a[2] * u[2];
@@ -253,32 +309,32 @@ __global__ __launch_bounds__(BLOCK) void k_pose(const SlotDesc* table, LaunchTab
   const double om = S.bom[b];
   const double wa[3] = {om * a[0], om * a[1], om * a[2]};
   const double vw[3] = {wa[1] * ru[2] - wa[2] * ru[1], wa[2] * ru[0] - wa[0] * ru[2], wa[0] * ru[1] - wa[1] * ru[0]};
-  Pos* xw = (Pos*)S.xwb;
-  Real* nw = (Real*)S.nwb;
-  Real* vv = (Real*)S.vwb;
-  Real* lv = (Real*)S.levb;
-  Pos xp[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    xp[k] = (Pos)(ctr[k] + ru[k]);
-    xw[k * ns + w] = xp[k];
-    nw[k * ns + w] = (Real)rn[k];
-    vv[k * ns + w] = (Real)vw[k];
-    lv[k * ns + w] = (Real)ru[k];
-    S.x0b[k * ns + w] = S.x0[k * ns + w];
-    S.n0b[k * ns + w] = S.n0[k * ns + w];
-  }
+  Pos4 xp;
+  xp.x = (Pos)(ctr[0] + ru[0]);
+  xp.y = (Pos)(ctr[1] + ru[1]);
+  xp.z = (Pos)(ctr[2] + ru[2]);
+  xp.w = (Pos)0;
+  Real4 nw, vv, lv;
+  nw.x = (Real)rn[0]; nw.y = (Real)rn[1]; nw.z = (Real)rn[2]; nw.w = (Real)0;
+  vv.x = (Real)vw[0]; vv.y = (Real)vw[1]; vv.z = (Real)vw[2]; vv.w = (Real)0;
+  lv.x = (Real)ru[0]; lv.y = (Real)ru[1]; lv.z = (Real)ru[2]; lv.w = (Real)b;
+  gp<Pos4>(S.xwb)[w] = xp;
+  gp<Real4>(S.nwb)[w] = nw;
+  gp<Real4>(S.vwb)[w] = vv;
+  gp<Real4>(S.levb)[w] = lv;
+  gp<d4>(S.x0b)[w] = x0;
+  gp<d4>(S.n0b)[w] = n0;
   S.bodyb[w] = b;
   S.sidb[w] = S.sid[w];
   int c[3];
-  if (!cell_coords<Pos>(S, xp[0], xp[1], xp[2], c)) raise_flag(S, F_DOMAIN);
+  if (!cell_coords<Pos>(S, xp.x, xp.y, xp.z, c)) raise_flag(S, F_DOMAIN);
   const uint32_t r = S.rank[cell_linear(S, c[0], c[1], c[2])];
   S.scell[w] = r;
   atomicAdd(&S.cnt_s[r], 1u);
 }
 
 // ---------------------------------------------------------------------------
-// K: fold the FP32 drift into the FP64 anchor, stage the fluid arrays for the
+// K: fold the drift into the FP64 anchor, stage the fluid arrays for the
 // gather, bin into cells, and per-block max |v| for the time step.
 // ---------------------------------------------------------------------------
 template <class P>
@@ -286,40 +342,34 @@ __global__ __launch_bounds__(BLOCK) void k_fold(const SlotDesc* table, LaunchTab
   typedef typename P::Pos Pos;
   typedef typename P::Real Real;
   typedef typename P::Temp Temp;
+  typedef typename P::Pos4 Pos4;
+  typedef typename P::Real4 Real4;
   __shared__ float red[BLOCK / WAVE];
   SLOT_PROLOGUE(DOM_FLUID);
-  const int nf = S.nf;
   const int i = lb * BLOCK + threadIdx.x;
   float vm = 0.0f;
-  if (i < nf) {
-    Pos* xa = (Pos*)S.xa;
-    Pos* xa2 = (Pos*)S.xa2;
-    Real* dr = (Real*)S.drift;
-    const Real* v = (const Real*)S.v;
-    Real* v2 = (Real*)S.v2;
-    Pos x[3];
-    bool finite = true;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      x[k] = xa[k * nf + i] + (Pos)dr[k * nf + i];
-      xa2[k * nf + i] = x[k];
-      dr[k * nf + i] = (Real)0;
-      const Real vk = v[k * nf + i];
-      v2[k * nf + i] = vk;
-      finite = finite && isfinite((double)x[k]) && isfinite((double)vk);
-    }
-    const Real rs = ((const Real*)S.rho)[i];
-    const Temp T = ((const Temp*)S.T)[i];
-    ((Real*)S.rho2)[i] = rs;
-    ((Real*)S.drho2)[i] = ((const Real*)S.drho)[i];
-    ((Temp*)S.T2)[i] = T;
+  if (i < S.nf) {
+    Pos4 x = gpc<Pos4>(S.xa)[i];
+    const Real4 d = gpc<Real4>(S.drift)[i];
+    x.x += (Pos)d.x;
+    x.y += (Pos)d.y;
+    x.z += (Pos)d.z;
+    gp<Pos4>(S.xa2)[i] = x;
+    gp<Real4>(S.drift)[i] = Real4(0);
+    const Real4 v = gpc<Real4>(S.vr)[i];
+    gp<Real4>(S.vr2)[i] = v;
+    gp<Real>(S.drho2)[i] = gpc<Real>(S.drho)[i];
+    const Temp T = gpc<Temp>(S.T)[i];
+    gp<Temp>(S.T2)[i] = T;
     S.fid2[i] = S.fid[i];
-    finite = finite && isfinite((double)rs) && isfinite((double)T);
+    const bool finite = isfinite((double)x.x) && isfinite((double)x.y) && isfinite((double)x.z) &&
+                        isfinite((double)v.x) && isfinite((double)v.y) && isfinite((double)v.z) &&
+                        isfinite((double)v.w) && isfinite((double)T);
     if (!finite) raise_flag(S, F_NONFINITE);
-    const float v0 = (float)v[i], v1 = (float)v[nf + i], vz = (float)v[2 * nf + i];
-    vm = sqrtf(v0 * v0 + v1 * v1 + vz * vz);
+    const float v0 = (float)v.x, v1 = (float)v.y, v2 = (float)v.z;
+    vm = sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
     int c[3];
-    if (!cell_coords<Pos>(S, x[0], x[1], x[2], c)) raise_flag(S, F_DOMAIN);
+    if (!cell_coords<Pos>(S, x.x, x.y, x.z, c)) raise_flag(S, F_DOMAIN);
     const uint32_t r = S.rank[cell_linear(S, c[0], c[1], c[2])];
     S.fcell[i] = r;
     atomicAdd(&S.cnt_f[r], 1u);
@@ -462,37 +512,29 @@ __global__ __launch_bounds__(BLOCK) void k_cellsort(const SlotDesc* table, Launc
 // ---------------------------------------------------------------------------
 template <class P>
 __global__ __launch_bounds__(BLOCK) void k_reorder(const SlotDesc* table, LaunchTab tab, int which) {
-  typedef typename P::Pos Pos;
   typedef typename P::Real Real;
   typedef typename P::Temp Temp;
+  typedef typename P::Pos4 Pos4;
+  typedef typename P::Real4 Real4;
   SLOT_PROLOGUE(which ? DOM_SOLID : DOM_FLUID);
   const int k = lb * BLOCK + threadIdx.x;
   if (!which) {
-    const int nf = S.nf;
-    if (k >= nf) return;
+    if (k >= S.nf) return;
     const uint32_t s = S.fperm[k];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      ((Pos*)S.xa)[a * nf + k] = ((const Pos*)S.xa2)[a * nf + s];
-      ((Real*)S.v)[a * nf + k] = ((const Real*)S.v2)[a * nf + s];
-    }
-    ((Real*)S.rho)[k] = ((const Real*)S.rho2)[s];
-    ((Real*)S.drho)[k] = ((const Real*)S.drho2)[s];
-    ((Temp*)S.T)[k] = ((const Temp*)S.T2)[s];
+    gp<Pos4>(S.xa)[k] = gpc<Pos4>(S.xa2)[s];
+    gp<Real4>(S.vr)[k] = gpc<Real4>(S.vr2)[s];
+    gp<Real>(S.drho)[k] = gpc<Real>(S.drho2)[s];
+    gp<Temp>(S.T)[k] = gpc<Temp>(S.T2)[s];
     S.fid[k] = S.fid2[s];
   } else {
-    const int ns = S.ns;
-    if (k >= ns) return;
+    if (k >= S.ns) return;
     const uint32_t s = S.sperm[k];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      S.x0[a * ns + k] = S.x0b[a * ns + s];
-      S.n0[a * ns + k] = S.n0b[a * ns + s];
-      ((Pos*)S.xw)[a * ns + k] = ((const Pos*)S.xwb)[a * ns + s];
-      ((Real*)S.nw)[a * ns + k] = ((const Real*)S.nwb)[a * ns + s];
-      ((Real*)S.vw)[a * ns + k] = ((const Real*)S.vwb)[a * ns + s];
-      ((Real*)S.lev)[a * ns + k] = ((const Real*)S.levb)[a * ns + s];
-    }
+    gp<d4>(S.x0)[k] = gpc<d4>(S.x0b)[s];
+    gp<d4>(S.n0)[k] = gpc<d4>(S.n0b)[s];
+    gp<Pos4>(S.xw)[k] = gpc<Pos4>(S.xwb)[s];
+    gp<Real4>(S.nw)[k] = gpc<Real4>(S.nwb)[s];
+    gp<Real4>(S.vw)[k] = gpc<Real4>(S.vwb)[s];
+    gp<Real4>(S.lev)[k] = gpc<Real4>(S.levb)[s];
     S.body[k] = S.bodyb[s];
     S.sid[k] = S.sidb[s];
   }
@@ -508,10 +550,13 @@ __global__ __launch_bounds__(BLOCK) void k_reorder(const SlotDesc* table, Launch
 // without), against the perfect-lattice sum S0.
 //
 // A wavefront holds 64 consecutive particles of the Morton order, i.e. a few
-// neighbouring cells.  It walks the cells of its lanes' bounding box (plus one
-// layer) once; inside a cell every lane sees the same candidate, so candidate
-// positions are wave-uniform (scalar) loads, and each lane keeps the
-// candidates of its own 27-cell stencil.
+// distinct neighbouring cells.  It visits the union of their 27-cell stencils
+// once (each distinct cell's stencil minus the cells already visited; the
+// stencil's cell ranges are fetched lane-parallel).  A cell's candidates are
+// staged with one coalesced load per 64 into the wave's LDS slots, and each
+// lane tests them (those of its own stencil) into a hit mask, without branches
+// or stores per candidate.  The kernel sum is then taken over each lane's own
+// hits.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int wave_min_i(int v) {
 #pragma unroll
@@ -524,70 +569,172 @@ __device__ __forceinline__ int wave_max_i(int v) {
   return __builtin_amdgcn_readfirstlane(v);
 }
 
+// value of lane l (wave-uniform l) as a scalar
+__device__ __forceinline__ uint32_t rl_u(uint32_t v, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+__device__ __forceinline__ float rl(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double rl(double v, int l) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 template <class P>
 __global__ __launch_bounds__(BLOCK) void k_build(const SlotDesc* table, LaunchTab tab) {
 #pragma clang fp contract(off)
   typedef typename P::Pos Pos;
   typedef typename P::Real Real;
+  typedef typename P::Pos4 Pos4;
+  typedef typename P::Real4 Real4;
+  __shared__ Pos4 lds_stage[BLOCK / WAVE][WAVE];
+  __shared__ int lds_cells[BLOCK / WAVE][3 * WAVE];
   SLOT_PROLOGUE(DOM_FLUID);
   const int i = lb * BLOCK + threadIdx.x;
-  const int nf = S.nf, ns = S.ns;
+  const int nf = S.nf;
   const bool act = i < nf;
   const int ii = act ? i : nf - 1;
-  const Pos* xa = (const Pos*)S.xa;
-  const Pos* xw = (const Pos*)S.xw;
-  const Pos xi = xa[ii], yi = xa[nf + ii], zi = xa[2 * nf + ii];
+  Pos4* stage = lds_stage[threadIdx.x / WAVE];
+  const GLB Pos4* xa = gpc<Pos4>(S.xa);
+  const GLB Pos4* xw = gpc<Pos4>(S.xw);
+  const Pos4 xi4 = xa[ii];
+  const Pos xi = xi4.x, yi = xi4.y, zi = xi4.z;
   int c[3];
   cell_coords<Pos>(S, xi, yi, zi, c);
-  int lo[3], hi[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = max(wave_min_i(c[a]) - 1, 0);
-    hi[a] = min(wave_max_i(c[a]) + 1, S.dims[a] - 1);
-  }
-  const int lane = i & (WAVE - 1);
-  const int64_t slice = i >> 6;
-  const int64_t basef = slice * (int64_t)S.kf * WAVE + lane;
-  const int64_t bases = slice * (int64_t)S.ks * WAVE + lane;
+  // indices go to per-particle contiguous staging rows (the first sweep moves
+  // them into the SELL rows): a lane's successive stores fill whole lines
+  GLB uint32_t* nj = gp<uint32_t>(S.jstage) + (int64_t)ii * (S.kf + S.ks);
+  GLB uint32_t* sj = nj + S.kf;
   const double h = S.h, cut2 = S.cut2, kW = S.kW;
   const int kf = S.kf, ks = S.ks;
+  const GLB uint32_t* rank = gpc<uint32_t>(S.rank);
+  const GLB uint32_t* stf = gpc<uint32_t>(S.start_f);
+  const GLB uint32_t* sts = gpc<uint32_t>(S.start_s);
   int cf = 0, cs = 0;
   double sw = kW;  // W(0)
-  for (int cz = lo[2]; cz <= hi[2]; ++cz) {
-    for (int cy = lo[1]; cy <= hi[1]; ++cy) {
-      for (int cx = lo[0]; cx <= hi[0]; ++cx) {
-        const bool need = act && abs(cx - c[0]) <= 1 && abs(cy - c[1]) <= 1 && abs(cz - c[2]) <= 1;
-        if (!__any(need)) continue;
-        const uint32_t r = S.rank[cell_linear(S, cx, cy, cz)];
-        const uint32_t j0 = S.start_f[r], j1 = S.start_f[r + 1];
-        for (uint32_t j = j0; j < j1; ++j) {
-          const Pos ddx = xi - xa[j], ddy = yi - xa[nf + j], ddz = zi - xa[2 * nf + j];
-          const Pos s2 = ddx * ddx + ddy * ddy;
-          const Pos d2 = s2 + ddz * ddz;
-          if (need && (int)j != i && (double)d2 < cut2) {
-            const double rr = sqrt((double)d2);
-            const double q = rr / h;
-            const double t = 1.0 - 0.5 * q;
-            sw += kW * t * t * t * t * (1.0 + 2.0 * q);
-            if (cf < kf) S.nj[basef + (int64_t)cf * WAVE] = j;
-            ++cf;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const double inv_h = 1.0 / h;
+  // distinct cells of the wave: runs of equal cells in the sorted order
+  const uint32_t myr = rank[cell_linear(S, c[0], c[1], c[2])];
+  const uint32_t prevr = (uint32_t)__shfl_up((int)myr, 1, WAVE);
+  uint64_t runs = __ballot(act && (lane == 0 || prevr != myr));
+  // this lane's offset in a 27-cell stencil
+  const int ox = lane % 3 - 1, oy = (lane / 3) % 3 - 1, oz = lane / 9 - 1;
+  int* done = lds_cells[threadIdx.x / WAVE];
+  int ndone = 0;
+  while (runs) {
+    const int L = __builtin_ctzll(runs);
+    runs &= runs - 1;
+    const int dx = __builtin_amdgcn_readlane(c[0], L), dy = __builtin_amdgcn_readlane(c[1], L),
+              dz = __builtin_amdgcn_readlane(c[2], L);
+    // stencil cell of this lane, unless an earlier distinct cell's stencil has it
+    const int nx = dx + ox, ny = dy + oy, nz = dz + oz;
+    bool take = lane < 27 && nx >= 0 && ny >= 0 && nz >= 0 && nx < S.dims[0] && ny < S.dims[1] && nz < S.dims[2];
+    for (int q = 0; q < ndone; ++q)
+      take = take && !(abs(nx - done[3 * q]) <= 1 && abs(ny - done[3 * q + 1]) <= 1 && abs(nz - done[3 * q + 2]) <= 1);
+    uint32_t f0 = 0, f1 = 0, s0 = 0, s1 = 0;
+    if (take) {
+      const uint32_t r = rank[cell_linear(S, nx, ny, nz)];
+      f0 = stf[r];
+      f1 = stf[r + 1];
+      s0 = sts[r];
+      s1 = sts[r + 1];
+    }
+    uint64_t todo = __ballot(take);
+    if (lane == 0) {
+      done[3 * ndone] = dx;
+      done[3 * ndone + 1] = dy;
+      done[3 * ndone + 2] = dz;
+    }
+    ++ndone;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    while (todo) {
+      const int t = __builtin_ctzll(todo);
+      todo &= todo - 1;
+      const int cx = __builtin_amdgcn_readlane(nx, t), cy = __builtin_amdgcn_readlane(ny, t),
+                cz = __builtin_amdgcn_readlane(nz, t);
+      const bool need = act && abs(cx - c[0]) <= 1 && abs(cy - c[1]) <= 1 && abs(cz - c[2]) <= 1;
+      // fluid candidates, 64 at a time: one coalesced load into this wave's
+      // LDS slots, a branch-free FP64 test per candidate building a hit mask,
+      // then the hits are written
+      const uint32_t a0 = rl_u(f0, t), a1 = rl_u(f1, t);
+      for (uint32_t jb = a0; jb < a1; jb += WAVE) {
+        const int m = (int)min((uint32_t)WAVE, a1 - jb);
+        if (lane < m) stage[lane] = xa[jb + lane];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        uint64_t hits = 0;
+        if (need) {
+          for (int e = 0; e < m; ++e) {
+            const Pos4 xj = stage[e];
+            const Pos ddx = xi - xj.x, ddy = yi - xj.y, ddz = zi - xj.z;
+            const Pos s2 = ddx * ddx + ddy * ddy;
+            const Pos d2 = s2 + ddz * ddz;
+            hits |= (uint64_t)((double)d2 < cut2) << e;
           }
+          if ((uint32_t)i - jb < (uint32_t)m) hits &= ~(1ull << ((uint32_t)i - jb));
         }
-        const uint32_t w0 = S.start_s[r], w1 = S.start_s[r + 1];
-        for (uint32_t w = w0; w < w1; ++w) {
-          const Pos ddx = xi - xw[w], ddy = yi - xw[ns + w], ddz = zi - xw[2 * ns + w];
-          const Pos s2 = ddx * ddx + ddy * ddy;
-          const Pos d2 = s2 + ddz * ddz;
-          if (need && (double)d2 < cut2) {
-            const double rr = sqrt((double)d2);
-            const double q = rr / h;
-            const double t = 1.0 - 0.5 * q;
-            sw += kW * t * t * t * t * (1.0 + 2.0 * q);
-            if (cs < ks) S.sj[bases + (int64_t)cs * WAVE] = w;
-            ++cs;
-          }
+        while (hits) {
+          const int e = __builtin_ctzll(hits);
+          hits &= hits - 1;
+          if (cf < kf) nj[cf] = jb + (uint32_t)e;
+          ++cf;
         }
+        __builtin_amdgcn_wave_barrier();
       }
+      const uint32_t b0 = rl_u(s0, t), b1 = rl_u(s1, t);
+      for (uint32_t wb = b0; wb < b1; wb += WAVE) {
+        const int m = (int)min((uint32_t)WAVE, b1 - wb);
+        if (lane < m) stage[lane] = xw[wb + lane];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        uint64_t hits = 0;
+        if (need) {
+          for (int e = 0; e < m; ++e) {
+            const Pos4 xq = stage[e];
+            const Pos ddx = xi - xq.x, ddy = yi - xq.y, ddz = zi - xq.z;
+            const Pos s2 = ddx * ddx + ddy * ddy;
+            const Pos d2 = s2 + ddz * ddz;
+            hits |= (uint64_t)((double)d2 < cut2) << e;
+          }
+        }
+        while (hits) {
+          const int e = __builtin_ctzll(hits);
+          hits &= hits - 1;
+          if (cs < ks) sj[cs] = wb + (uint32_t)e;
+          ++cs;
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+  }
+  // kernel sum over this particle's own hits (self, fluid, solid)
+  if (act) {
+    const int nfh = min(cf, kf), nsh = min(cs, ks);
+    for (int k = 0; k < nfh; ++k) {
+      const Pos4 xj = xa[nj[k]];
+      const Pos ddx = xi - xj.x, ddy = yi - xj.y, ddz = zi - xj.z;
+      const Pos s2 = ddx * ddx + ddy * ddy;
+      const Pos d2 = s2 + ddz * ddz;
+      const double qq = sqrt((double)d2) * inv_h;
+      const double tt = 1.0 - 0.5 * qq;
+      sw += kW * tt * tt * tt * tt * (1.0 + 2.0 * qq);
+    }
+    for (int k = 0; k < nsh; ++k) {
+      const Pos4 xq = xw[sj[k]];
+      const Pos ddx = xi - xq.x, ddy = yi - xq.y, ddz = zi - xq.z;
+      const Pos s2 = ddx * ddx + ddy * ddy;
+      const Pos d2 = s2 + ddz * ddz;
+      const double qq = sqrt((double)d2) * inv_h;
+      const double tt = 1.0 - 0.5 * qq;
+      sw += kW * tt * tt * tt * tt * (1.0 + 2.0 * qq);
     }
   }
   if (!act) return;
@@ -600,12 +747,14 @@ __global__ __launch_bounds__(BLOCK) void k_build(const SlotDesc* table, LaunchTa
   S.nsc[i] = (uint32_t)cs;
   S.sumW[i] = sw;
   // density re-initialisation
-  Real* rho = (Real*)S.rho;
+  GLB Real4* vr = gp<Real4>(S.vr);
+  Real4 v = vr[i];
   const double dp3 = S.dp * S.dp * S.dp;
   const double rre = S.rho0 * (dp3 * sw) / S.S0;
-  const double rcur = P::kRel ? S.rho0 + (double)rho[i] : (double)rho[i];
+  const double rcur = P::kRel ? S.rho0 + (double)v.w : (double)v.w;
   const double rn = S.free_surface ? fmax(rcur, rre) : rre;
-  rho[i] = P::kRel ? (Real)(rn - S.rho0) : (Real)rn;
+  v.w = P::kRel ? (Real)(rn - S.rho0) : (Real)rn;
+  vr[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -655,35 +804,47 @@ __global__ __launch_bounds__(BLOCK) void k_dt(const SlotDesc* table, LaunchTab t
 // Frozen pair geometry of a row entry: r_ij = x_i - x_j from the FP64 anchors
 // (rounded to the interaction type) and F = (dW/dr)/r = kF (1 - q/2)^3 from
 // the FP64 distance, evaluated exactly as in the build's cutoff test.
-template <class Pos, class Real>
-__device__ __forceinline__ Real pair_geom(const SlotDesc& S, Pos xi, Pos yi, Pos zi, Pos xj, Pos yj, Pos zj,
-                                          Real& rx, Real& ry, Real& rz) {
+template <class Pos, class Real4>
+__device__ __forceinline__ Real4 pair_geom(const SlotDesc& S, Pos xi, Pos yi, Pos zi, Pos xj, Pos yj, Pos zj) {
 #pragma clang fp contract(off)
+  typedef decltype(Real4().x) Real;
   const Pos ddx = xi - xj, ddy = yi - yj, ddz = zi - zj;
   const Pos s2 = ddx * ddx + ddy * ddy;
   const Pos d2 = s2 + ddz * ddz;
   const double q = sqrt((double)d2) / S.h;
   const double t = 1.0 - 0.5 * q;
-  rx = (Real)ddx;
-  ry = (Real)ddy;
-  rz = (Real)ddz;
-  return (Real)(S.kF * t * t * t);
+  Real4 r;
+  r.x = (Real)ddx;
+  r.y = (Real)ddy;
+  r.z = (Real)ddz;
+  r.w = (Real)(S.kF * t * t * t);
+  return r;
 }
+
+// Rows are walked four entries at a time; entries past a row's count are
+// loaded from the row's capacity (always in bounds, capacities are multiples
+// of four) and replaced by a null entry: own index, r = 0, F = 0, which adds
+// exactly zero to every sum.
+#define ROW_UNROLL 4
 
 // ---------------------------------------------------------------------------
 // K: viscous acceleration (eq. 10 fluid-fluid, eq. 18 fluid-wall) and heat
 // conduction rate (eq. 22), both frozen for the advection step.  As the first
-// sweep over fresh rows it also writes each row entry's pair geometry.  Per-block
-// partials: viscous force and torque on each body and its heat flow into the
-// fluid.  Also clears this block's pressure-force accumulators.
+// sweep over fresh rows it moves the build's indices into the SELL rows as
+// records (r_ij, j).
+// Per-block partials: viscous force and torque on each body and its heat flow
+// into the fluid.  Also clears this block's pressure-force accumulators.
 // ---------------------------------------------------------------------------
 template <class P>
 __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, LaunchTab tab) {
+  typedef typename P::Pos Pos;
   typedef typename P::Real Real;
   typedef typename P::Temp Temp;
+  typedef typename P::Pos4 Pos4;
+  typedef typename P::Real4 Real4;
   __shared__ double lds[4 * NB * 7];
   SLOT_PROLOGUE(DOM_FLUID);
-  const int nf = S.nf, ns = S.ns;
+  const int nf = S.nf;
   const int i = lb * BLOCK + threadIdx.x;
   const size_t nbf = (size_t)S.nblk[DOM_FLUID];
   if (threadIdx.x < NB * 6) S.press_part[(size_t)threadIdx.x * nbf + lb] = 0.0;
@@ -691,86 +852,96 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
   acc.init();
   bool wall = false;
   if (i < nf) {
-    const Real* v = (const Real*)S.v;
-    const Real* rho = (const Real*)S.rho;
-    const Temp* T = (const Temp*)S.T;
+    const GLB Pos4* xa = gpc<Pos4>(S.xa);
+    const GLB Real4* vr = gpc<Real4>(S.vr);
+    const GLB Temp* T = gpc<Temp>(S.T);
     const Real m = (Real)S.mass;
-    const Real vix = v[i], viy = v[nf + i], viz = v[2 * nf + i];
-    const Real rhoi = rho_abs<P>(S, rho[i]);
+    const Pos4 xi = xa[i];
+    const Real4 vi = vr[i];
+    const Real rhoi = rho_abs<P>(S, vi.w);
     const Temp Ti = T[i];
     const Real c2 = (Real)(2.0 * S.eta) * rcp(rhoi);   // 2 eta V_i / m_i
     const Real Kff = (Real)(4.0 * S.k_f * S.k_f / (S.k_f + S.k_f));
     Real ax = 0, ay = 0, az = 0, hs = 0;
     const int lane = i & (WAVE - 1);
     const int64_t slice = i >> 6;
-    typedef typename P::Pos Pos;
-    const Pos* xa = (const Pos*)S.xa;
-    const Pos xi = xa[i], yi = xa[nf + i], zi = xa[2 * nf + i];
     {
       const int n = (int)S.nfc[i];
       const int64_t base = slice * (int64_t)S.kf * WAVE + lane;
-      Real* R = (Real*)S.nr;
-      Real* F = (Real*)S.nF;
-      const int64_t L = S.rowlen_f;
-      for (int k = 0; k < n; ++k) {
-        const int64_t o = base + (int64_t)k * WAVE;
-        const uint32_t j = S.nj[o];
-        Real rx, ry, rz;
-        const Real Fk = pair_geom<Pos, Real>(S, xi, yi, zi, xa[j], xa[nf + j], xa[2 * nf + j], rx, ry, rz);
-        R[o] = rx;
-        R[L + o] = ry;
-        R[2 * L + o] = rz;
-        F[o] = Fk;
-        const Real Vj = m * rcp(rho_abs<P>(S, rho[j]));
-        const Real cv = c2 * Vj * Fk;
-        ax += cv * (vix - v[j]);
-        ay += cv * (viy - v[nf + j]);
-        az += cv * (viz - v[2 * nf + j]);
-        hs += Vj * Kff * (Real)(Ti - T[j]) * Fk;
+      const GLB u4* JS = gpc<u4>(S.jstage) + (int64_t)i * ((S.kf + S.ks) / 4);
+      GLB Real4* R = gp<Real4>(S.nrec) + base;
+      for (int k = 0; k < n; k += ROW_UNROLL) {
+        uint32_t j[ROW_UNROLL];
+        const u4 js = JS[k / 4];
+#pragma unroll
+        for (int u = 0; u < ROW_UNROLL; ++u) j[u] = k + u < n ? js[u] : (uint32_t)i;
+        Pos4 xj[ROW_UNROLL];
+        Real4 vj[ROW_UNROLL];
+        Temp Tj[ROW_UNROLL];
+#pragma unroll
+        for (int u = 0; u < ROW_UNROLL; ++u) {
+          xj[u] = xa[j[u]];
+          vj[u] = vr[j[u]];
+          Tj[u] = T[j[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < ROW_UNROLL; ++u) {
+          if (k + u >= n) continue;
+          const Real4 g = pair_geom<Pos, Real4>(S, xi.x, xi.y, xi.z, xj[u].x, xj[u].y, xj[u].z);
+          Real4 rec = g;
+          rec.w = pack_index(j[u], (Real)0);
+          R[(int64_t)(k + u) * WAVE] = rec;
+          const Real Vj = m * rcp(rho_abs<P>(S, vj[u].w));
+          const Real cv = c2 * Vj * g.w;
+          ax += cv * (vi.x - vj[u].x);
+          ay += cv * (vi.y - vj[u].y);
+          az += cv * (vi.z - vj[u].z);
+          hs += Vj * Kff * (Real)(Ti - Tj[u]) * g.w;
+        }
       }
     }
     {
       const int n = (int)S.nsc[i];
       wall = n > 0;
       const int64_t base = slice * (int64_t)S.ks * WAVE + lane;
-      Real* R = (Real*)S.sr;
-      Real* F = (Real*)S.sF;
-      const int64_t L = S.rowlen_s;
-      const Pos* xw = (const Pos*)S.xw;
-      const Real* vw = (const Real*)S.vw;
-      const Real* lv = (const Real*)S.lev;
+      const GLB uint32_t* JS = gpc<uint32_t>(S.jstage) + (int64_t)i * (S.kf + S.ks) + S.kf;
+      GLB Real4* R = gp<Real4>(S.srec) + base;
+      const GLB Pos4* xw = gpc<Pos4>(S.xw);
+      const GLB Real4* vw = gpc<Real4>(S.vw);
+      const GLB Real4* lv = gpc<Real4>(S.lev);
       const Real Vw = (Real)S.vol_w;
       const Real rc = rcp(rhoi * (Real)S.cp_f);
       for (int k = 0; k < n; ++k) {
-        const int64_t o = base + (int64_t)k * WAVE;
-        const uint32_t w = S.sj[o];
-        Real rx, ry, rz;
-        const Real Fk = pair_geom<Pos, Real>(S, xi, yi, zi, xw[w], xw[ns + w], xw[2 * ns + w], rx, ry, rz);
-        R[o] = rx;
-        R[L + o] = ry;
-        R[2 * L + o] = rz;
-        F[o] = Fk;
-        const int b = S.body[w];
-        const Real cv = c2 * Vw * Fk;
-        const Real fx = cv * (vix - vw[w]), fy = cv * (viy - vw[ns + w]), fz = cv * (viz - vw[2 * ns + w]);
+        const uint32_t w = JS[k];
+        const Pos4 xq = xw[w];
+        const Real4 vq = vw[w];
+        const Real4 lq = lv[w];
+        const Real4 g = pair_geom<Pos, Real4>(S, xi.x, xi.y, xi.z, xq.x, xq.y, xq.z);
+        Real4 rec = g;
+        rec.w = pack_index(w, (Real)0);
+        R[(int64_t)k * WAVE] = rec;
+        const int b = (int)lq.w;
+        const Real cv = c2 * Vw * g.w;
+        const Real fx = cv * (vi.x - vq.x), fy = cv * (vi.y - vq.y), fz = cv * (vi.z - vq.z);
         ax += fx;
         ay += fy;
         az += fz;
         const Real Kiw = (Real)(4.0 * S.k_f * S.bk[b] / (S.k_f + S.bk[b]));
-        const Real term = Vw * Kiw * (Real)(Ti - (Temp)S.bT[b]) * Fk;
+        const Real term = Vw * Kiw * (Real)(Ti - (Temp)S.bT[b]) * g.w;
         hs += term;
         // force of the fluid on the body is -m_i times this pair's acceleration
         const double gx = -(double)m * fx, gy = -(double)m * fy, gz = -(double)m * fz;
-        const double lx = lv[w], ly = lv[ns + w], lz = lv[2 * ns + w];
+        const double lx = lq.x, ly = lq.y, lz = lq.z;
         const double contrib[7] = {gx, gy, gz, ly * gz - lz * gy, lz * gx - lx * gz, lx * gy - ly * gx,
                                    (double)m * (double)S.cp_f * (double)(rc * term)};
         if (!acc.add(b, contrib)) raise_flag(S, F_CAPACITY);
       }
-      Real* av = (Real*)S.av;
-      av[i] = ax;
-      av[nf + i] = ay;
-      av[2 * nf + i] = az;
-      ((Real*)S.dTdt)[i] = rc * hs;
+      Real4 a;
+      a.x = ax;
+      a.y = ay;
+      a.z = az;
+      a.w = rc * hs;
+      gp<Real4>(S.ah)[i] = a;
     }
   }
   if (__syncthreads_or(wall))
@@ -785,18 +956,22 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
 template <class P>
 __global__ __launch_bounds__(BLOCK) void k_half_a(const SlotDesc* table, LaunchTab tab, int sub) {
   typedef typename P::Real Real;
+  typedef typename P::Real4 Real4;
   SLOT_PROLOGUE(DOM_FLUID);
   if (sub >= S.ctl->n_ac) return;
-  const int nf = S.nf;
   const int i = lb * BLOCK + threadIdx.x;
-  if (i >= nf) return;
+  if (i >= S.nf) return;
   const Real hdt = (Real)(0.5 * S.ctl->dt);
-  Real* rho = (Real*)S.rho;
-  rho[i] += hdt * ((const Real*)S.drho)[i];
-  Real* dr = (Real*)S.drift;
-  const Real* v = (const Real*)S.v;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) dr[k * nf + i] += hdt * v[k * nf + i];
+  GLB Real4* vr = gp<Real4>(S.vr);
+  Real4 v = vr[i];
+  v.w += hdt * gpc<Real>(S.drho)[i];
+  vr[i] = v;
+  GLB Real4* dr = gp<Real4>(S.drift);
+  Real4 d = dr[i];
+  d.x += hdt * v.x;
+  d.y += hdt * v.y;
+  d.z += hdt * v.z;
+  dr[i] = d;
 }
 
 // ---------------------------------------------------------------------------
@@ -808,23 +983,22 @@ __global__ __launch_bounds__(BLOCK) void k_half_a(const SlotDesc* table, LaunchT
 template <class P>
 __global__ __launch_bounds__(BLOCK) void k_momentum(const SlotDesc* table, LaunchTab tab, int sub) {
   typedef typename P::Real Real;
+  typedef typename P::Real4 Real4;
   __shared__ double lds[4 * NB * 6];
   SLOT_PROLOGUE(DOM_FLUID);
   if (sub >= S.ctl->n_ac) return;
-  const int nf = S.nf, ns = S.ns;
+  const int nf = S.nf;
   const int i = lb * BLOCK + threadIdx.x;
   BodyAcc<6> acc;
   acc.init();
   bool wall = false;
   if (i < nf) {
-    const Real* v = (const Real*)S.v;
-    const Real* rho = (const Real*)S.rho;
+    const GLB Real4* vr = gpc<Real4>(S.vr);
     const Real c0 = (Real)S.c0;
     const Real m = (Real)S.mass;
-    const Real vix = v[i], viy = v[nf + i], viz = v[2 * nf + i];
-    const Real rs = rho[i];
-    const Real rhoi = rho_abs<P>(S, rs);
-    const Real pi = press<P>(S, rs);
+    const Real4 vi = vr[i];
+    const Real rhoi = rho_abs<P>(S, vi.w);
+    const Real pi = press<P>(S, vi.w);
     const Real c2 = (Real)2 * rcp(rhoi);   // 2 V_i / m_i
     Real ax = 0, ay = 0, az = 0;
     const int lane = i & (WAVE - 1);
@@ -832,74 +1006,85 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(const SlotDesc* table, Launc
     {
       const int n = (int)S.nfc[i];
       const int64_t base = slice * (int64_t)S.kf * WAVE + lane;
-      const Real* R = (const Real*)S.nr;
-      const Real* F = (const Real*)S.nF;
-      const int64_t L = S.rowlen_f;
-      for (int k = 0; k < n; ++k) {
-        const int64_t o = base + (int64_t)k * WAVE;
-        const uint32_t j = S.nj[o];
-        const Real rx = R[o], ry = R[L + o], rz = R[2 * L + o], Fk = F[o];
-        const Real r2 = rx * rx + ry * ry + rz * rz;
-        if (r2 == (Real)0) continue;
-        const Real inv = rsq(r2);
-        const Real rsj = rho[j];
-        const Real rhoj = rho_abs<P>(S, rsj);
-        const Real pj = press<P>(S, rsj);
-        // U_L - U_R = -(v_i - v_j) . e_ij
-        const Real dU = -((vix - v[j]) * rx + (viy - v[nf + j]) * ry + (viz - v[2 * nf + j]) * rz) * inv;
-        const Real beta = fmin((Real)3 * fmax(dU, (Real)0), c0);
-        const Real ps = (Real)0.5 * (pi + pj) + rhoi * rhoj * beta * dU * rcp(rhoi + rhoj);
-        const Real s = -c2 * (m * rcp(rhoj)) * ps * Fk;
-        ax += s * rx;
-        ay += s * ry;
-        az += s * rz;
+      const GLB Real4* R = gpc<Real4>(S.nrec) + base;
+      const Real inv_h = (Real)(1.0 / S.h), kF = (Real)S.kF;
+      for (int k = 0; k < n; k += ROW_UNROLL) {
+        uint32_t j[ROW_UNROLL];
+        Real4 g[ROW_UNROLL];
+#pragma unroll
+        for (int u = 0; u < ROW_UNROLL; ++u) {
+          const Real4 gr = ldnt(R + (int64_t)(k + u) * WAVE);
+          const bool ok = k + u < n;
+          j[u] = ok ? unpack_index(gr.w) : (uint32_t)i;
+          g[u] = ok ? gr : Real4(0);
+        }
+        Real4 vj[ROW_UNROLL];
+#pragma unroll
+        for (int u = 0; u < ROW_UNROLL; ++u) vj[u] = vr[j[u]];
+#pragma unroll
+        for (int u = 0; u < ROW_UNROLL; ++u) {
+          const Real r2 = g[u].x * g[u].x + g[u].y * g[u].y + g[u].z * g[u].z;
+          const Real inv = r2 > (Real)0 ? rsq(r2) : (Real)0;
+          const Real Fk = k + u < n ? kernel_F(r2, inv_h, kF) : (Real)0;
+          const Real rhoj = rho_abs<P>(S, vj[u].w);
+          const Real pj = press<P>(S, vj[u].w);
+          // U_L - U_R = -(v_i - v_j) . e_ij
+          const Real dU = -((vi.x - vj[u].x) * g[u].x + (vi.y - vj[u].y) * g[u].y + (vi.z - vj[u].z) * g[u].z) * inv;
+          const Real beta = fmin((Real)3 * fmax(dU, (Real)0), c0);
+          const Real ps = (Real)0.5 * (pi + pj) + rhoi * rhoj * beta * dU * rcp(rhoi + rhoj);
+          const Real s = -c2 * (m * rcp(rhoj)) * ps * Fk;
+          ax += s * g[u].x;
+          ay += s * g[u].y;
+          az += s * g[u].z;
+        }
       }
     }
     {
       const int n = (int)S.nsc[i];
       wall = n > 0;
       const int64_t base = slice * (int64_t)S.ks * WAVE + lane;
-      const Real* R = (const Real*)S.sr;
-      const Real* F = (const Real*)S.sF;
-      const Real* lv = (const Real*)S.lev;
-      const int64_t L = S.rowlen_s;
+      const GLB Real4* R = gpc<Real4>(S.srec) + base;
+      const GLB Real4* lv = gpc<Real4>(S.lev);
+      const Real inv_h = (Real)(1.0 / S.h), kF = (Real)S.kF;
       const Real gx = (Real)S.g[0], gy = (Real)S.g[1], gz = (Real)S.g[2];
       const Real rho0 = (Real)S.rho0;
       const Real ic02 = (Real)(1.0 / (S.c0 * S.c0));
       const Real Vw = (Real)S.vol_w;
       for (int k = 0; k < n; ++k) {
-        const int64_t o = base + (int64_t)k * WAVE;
-        const uint32_t w = S.sj[o];
-        const Real rx = R[o], ry = R[L + o], rz = R[2 * L + o], Fk = F[o];
+        const Real4 g = ldnt(R + (int64_t)k * WAVE);
+        const uint32_t w = unpack_index(g.w);
+        const Real Fk = kernel_F(g.x * g.x + g.y * g.y + g.z * g.z, inv_h, kF);
+        const Real4 lq = lv[w];
         // right state of eq. 17: P_R = P_L + rho_f g . (x_w - x_f), rho_R from the EoS
-        const Real PR = pi - rhoi * (gx * rx + gy * ry + gz * rz);
+        const Real PR = pi - rhoi * (gx * g.x + gy * g.y + gz * g.z);
         const Real rhoR = rho0 + PR * ic02;
         const Real ps = (rhoi * PR + rhoR * pi) * rcp(rhoi + rhoR);   // eq. 19
         const Real s = -c2 * Vw * ps * Fk;
-        const Real fx = s * rx, fy = s * ry, fz = s * rz;
+        const Real fx = s * g.x, fy = s * g.y, fz = s * g.z;
         ax += fx;
         ay += fy;
         az += fz;
         const double hx = -(double)m * fx, hy = -(double)m * fy, hz = -(double)m * fz;
-        const double lx = lv[w], ly = lv[ns + w], lz = lv[2 * ns + w];
+        const double lx = lq.x, ly = lq.y, lz = lq.z;
         const double contrib[6] = {hx, hy, hz, ly * hz - lz * hy, lz * hx - lx * hz, lx * hy - ly * hx};
-        if (!acc.add(S.body[w], contrib)) raise_flag(S, F_CAPACITY);
+        if (!acc.add((int)lq.w, contrib)) raise_flag(S, F_CAPACITY);
       }
     }
     const Real dt = (Real)S.ctl->dt;
     const Real hdt = (Real)(0.5 * S.ctl->dt);
-    const Real* av = (const Real*)S.av;
-    Real* vn = (Real*)S.vnew;
-    Real* dr = (Real*)S.drift;
-    const Real nx = vix + dt * (ax + av[i] + (Real)S.g[0]);
-    const Real ny = viy + dt * (ay + av[nf + i] + (Real)S.g[1]);
-    const Real nz = viz + dt * (az + av[2 * nf + i] + (Real)S.g[2]);
-    vn[i] = nx;
-    vn[nf + i] = ny;
-    vn[2 * nf + i] = nz;
-    dr[i] += hdt * nx;
-    dr[nf + i] += hdt * ny;
-    dr[2 * nf + i] += hdt * nz;
+    const Real4 a = gpc<Real4>(S.ah)[i];
+    Real4 vn;
+    vn.x = vi.x + dt * (ax + a.x + (Real)S.g[0]);
+    vn.y = vi.y + dt * (ay + a.y + (Real)S.g[1]);
+    vn.z = vi.z + dt * (az + a.z + (Real)S.g[2]);
+    vn.w = vi.w;
+    gp<Real4>(S.vrn)[i] = vn;
+    GLB Real4* dr = gp<Real4>(S.drift);
+    Real4 d = dr[i];
+    d.x += hdt * vn.x;
+    d.y += hdt * vn.y;
+    d.z += hdt * vn.z;
+    dr[i] = d;
   }
   if (__syncthreads_or(wall))
     block_body_reduce<6>(acc, S.nbody, S.press_part, (size_t)S.nblk[DOM_FLUID], lb, true, lds);
@@ -912,74 +1097,79 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(const SlotDesc* table, Launc
 template <class P>
 __global__ __launch_bounds__(BLOCK) void k_continuity(const SlotDesc* table, LaunchTab tab, int sub) {
   typedef typename P::Real Real;
+  typedef typename P::Real4 Real4;
   SLOT_PROLOGUE(DOM_FLUID);
   if (sub >= S.ctl->n_ac) return;
-  const int nf = S.nf, ns = S.ns;
   const int i = lb * BLOCK + threadIdx.x;
-  if (i >= nf) return;
-  const Real* v = (const Real*)S.vnew;
-  const Real* rho = (const Real*)S.rho;
+  if (i >= S.nf) return;
+  const GLB Real4* vrn = gpc<Real4>(S.vrn);
   const Real c0 = (Real)S.c0;
   const Real m = (Real)S.mass;
-  const Real vix = v[i], viy = v[nf + i], viz = v[2 * nf + i];
-  const Real rs = rho[i];
-  const Real rhoi = rho_abs<P>(S, rs);
-  const Real pi = press<P>(S, rs);
+  const Real4 vi = vrn[i];
+  const Real rhoi = rho_abs<P>(S, vi.w);
+  const Real pi = press<P>(S, vi.w);
   Real sum = 0;
   const int lane = i & (WAVE - 1);
   const int64_t slice = i >> 6;
   {
     const int n = (int)S.nfc[i];
     const int64_t base = slice * (int64_t)S.kf * WAVE + lane;
-    const Real* R = (const Real*)S.nr;
-    const Real* F = (const Real*)S.nF;
-    const int64_t L = S.rowlen_f;
-    for (int k = 0; k < n; ++k) {
-      const int64_t o = base + (int64_t)k * WAVE;
-      const uint32_t j = S.nj[o];
-      const Real rx = R[o], ry = R[L + o], rz = R[2 * L + o], Fk = F[o];
-      const Real r2 = rx * rx + ry * ry + rz * rz;
-      if (r2 == (Real)0) continue;
-      const Real rr = r2 * rsq(r2);
-      const Real rsj = rho[j];
-      const Real rhoj = rho_abs<P>(S, rsj);
-      const Real pj = press<P>(S, rsj);
-      // (U* - U_L) dW = [ (v_i - v_j) . r / 2 + (p_i - p_j) r / (c0 (rho_i + rho_j)) ] F
-      const Real vr = (vix - v[j]) * rx + (viy - v[nf + j]) * ry + (viz - v[2 * nf + j]) * rz;
-      const Real dv = (Real)0.5 * vr + (pi - pj) * rr * rcp(c0 * (rhoi + rhoj));
-      sum += (m * rcp(rhoj)) * dv * Fk;
+    const GLB Real4* R = gpc<Real4>(S.nrec) + base;
+    const Real inv_h = (Real)(1.0 / S.h), kF = (Real)S.kF;
+    for (int k = 0; k < n; k += ROW_UNROLL) {
+      uint32_t j[ROW_UNROLL];
+      Real4 g[ROW_UNROLL];
+#pragma unroll
+      for (int u = 0; u < ROW_UNROLL; ++u) {
+        const Real4 gr = ldnt(R + (int64_t)(k + u) * WAVE);
+        const bool ok = k + u < n;
+        j[u] = ok ? unpack_index(gr.w) : (uint32_t)i;
+        g[u] = ok ? gr : Real4(0);
+      }
+      Real4 vj[ROW_UNROLL];
+#pragma unroll
+      for (int u = 0; u < ROW_UNROLL; ++u) vj[u] = vrn[j[u]];
+#pragma unroll
+      for (int u = 0; u < ROW_UNROLL; ++u) {
+        const Real r2 = g[u].x * g[u].x + g[u].y * g[u].y + g[u].z * g[u].z;
+        const Real rr = r2 > (Real)0 ? r2 * rsq(r2) : (Real)0;
+        const Real Fk = k + u < n ? kernel_F(r2, inv_h, kF) : (Real)0;
+        const Real rhoj = rho_abs<P>(S, vj[u].w);
+        const Real pj = press<P>(S, vj[u].w);
+        // (U* - U_L) dW = [ (v_i - v_j) . r / 2 + (p_i - p_j) r / (c0 (rho_i + rho_j)) ] F
+        const Real vr_ = (vi.x - vj[u].x) * g[u].x + (vi.y - vj[u].y) * g[u].y + (vi.z - vj[u].z) * g[u].z;
+        const Real dv = (Real)0.5 * vr_ + (pi - pj) * rr * rcp(c0 * (rhoi + rhoj));
+        sum += (m * rcp(rhoj)) * dv * Fk;
+      }
     }
   }
   {
     const int n = (int)S.nsc[i];
     const int64_t base = slice * (int64_t)S.ks * WAVE + lane;
-    const Real* R = (const Real*)S.sr;
-    const Real* F = (const Real*)S.sF;
-    const Real* nw = (const Real*)S.nw;
-    const Real* vw = (const Real*)S.vw;
-    const int64_t L = S.rowlen_s;
+    const GLB Real4* R = gpc<Real4>(S.srec) + base;
+    const Real inv_h = (Real)(1.0 / S.h), kF = (Real)S.kF;
+    const GLB Real4* nw = gpc<Real4>(S.nw);
+    const GLB Real4* vw = gpc<Real4>(S.vw);
     const Real gx = (Real)S.g[0], gy = (Real)S.g[1], gz = (Real)S.g[2];
     const Real rho0 = (Real)S.rho0;
     const Real ic02 = (Real)(1.0 / (S.c0 * S.c0));
     const Real Vw = (Real)S.vol_w;
     for (int k = 0; k < n; ++k) {
-      const int64_t o = base + (int64_t)k * WAVE;
-      const uint32_t w = S.sj[o];
-      const Real rx = R[o], ry = R[L + o], rz = R[2 * L + o], Fk = F[o];
-      const Real nx = nw[w], ny = nw[ns + w], nz = nw[2 * ns + w];
-      const Real PR = pi - rhoi * (gx * rx + gy * ry + gz * rz);
+      const Real4 g = ldnt(R + (int64_t)k * WAVE);
+      const uint32_t w = unpack_index(g.w);
+      const Real Fk = kernel_F(g.x * g.x + g.y * g.y + g.z * g.z, inv_h, kF);
+      const Real4 nq = nw[w];
+      const Real4 vq = vw[w];
+      const Real PR = pi - rhoi * (gx * g.x + gy * g.y + gz * g.z);
       const Real rhoR = rho0 + PR * ic02;
-      const Real UL = -(nx * vix + ny * viy + nz * viz);
-      const Real uw = -(nx * vw[w] + ny * vw[ns + w] + nz * vw[2 * ns + w]);
+      const Real UL = -(nq.x * vi.x + nq.y * vi.y + nq.z * vi.z);
+      const Real uw = -(nq.x * vq.x + nq.y * vq.y + nq.z * vq.z);
       const Real Us = uw + (pi - PR) * rcp(c0 * (rhoi + rhoR));
-      sum += Vw * (Us - UL) * (nx * rx + ny * ry + nz * rz) * Fk;
+      sum += Vw * (Us - UL) * (nq.x * g.x + nq.y * g.y + nq.z * g.z) * Fk;
     }
   }
-  ((Real*)S.drho)[i] = (Real)2 * rhoi * sum;
-  Real* vc = (Real*)S.v;
-  vc[i] = vix;
-  vc[nf + i] = viy;
-  vc[2 * nf + i] = viz;
+  gp<Real>(S.drho)[i] = (Real)2 * rhoi * sum;
+  gp<Real4>(S.vr)[i] = vi;
 }
 
 // ---------------------------------------------------------------------------
@@ -988,12 +1178,15 @@ __global__ __launch_bounds__(BLOCK) void k_continuity(const SlotDesc* table, Lau
 template <class P>
 __global__ __launch_bounds__(BLOCK) void k_half_b(const SlotDesc* table, LaunchTab tab, int sub) {
   typedef typename P::Real Real;
+  typedef typename P::Real4 Real4;
   SLOT_PROLOGUE(DOM_FLUID);
   if (sub >= S.ctl->n_ac) return;
   const int i = lb * BLOCK + threadIdx.x;
   if (i >= S.nf) return;
-  Real* rho = (Real*)S.rho;
-  rho[i] += (Real)(0.5 * S.ctl->dt) * ((const Real*)S.drho)[i];
+  GLB Real4* vr = gp<Real4>(S.vr);
+  Real4 v = vr[i];
+  v.w += (Real)(0.5 * S.ctl->dt) * gpc<Real>(S.drho)[i];
+  vr[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -1002,21 +1195,20 @@ __global__ __launch_bounds__(BLOCK) void k_half_b(const SlotDesc* table, LaunchT
 // ---------------------------------------------------------------------------
 template <class P>
 __global__ __launch_bounds__(BLOCK) void k_end(const SlotDesc* table, LaunchTab tab) {
-  typedef typename P::Real Real;
   typedef typename P::Temp Temp;
+  typedef typename P::Real4 Real4;
   __shared__ double lds[BLOCK / WAVE][NGLOB];
   SLOT_PROLOGUE(DOM_FLUID);
-  const int nf = S.nf;
   const int i = lb * BLOCK + threadIdx.x;
   double q[NGLOB] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if (i < nf) {
-    Temp* T = (Temp*)S.T;
-    const Temp Tn = T[i] + (Temp)S.ctl->dt_ad * (Temp)((const Real*)S.dTdt)[i];
+  if (i < S.nf) {
+    GLB Temp* T = gp<Temp>(S.T);
+    const Temp Tn = T[i] + (Temp)S.ctl->dt_ad * (Temp)gpc<Real4>(S.ah)[i].w;
     T[i] = Tn;
-    const Real* v = (const Real*)S.v;
-    const double vx = v[i], vy = v[nf + i], vz = v[2 * nf + i];
+    const Real4 v = gpc<Real4>(S.vr)[i];
+    const double vx = v.x, vy = v.y, vz = v.z;
     const double v2 = vx * vx + vy * vy + vz * vz;
-    const double r = P::kRel ? S.rho0 + (double)((const Real*)S.rho)[i] : (double)((const Real*)S.rho)[i];
+    const double r = P::kRel ? S.rho0 + (double)v.w : (double)v.w;
     q[0] = S.mass;
     q[1] = 0.5 * S.mass * v2;
     q[2] = S.mass * S.cp_f * (double)Tn;
@@ -1051,14 +1243,15 @@ __global__ __launch_bounds__(BLOCK) void k_end(const SlotDesc* table, LaunchTab 
 // per-body force, torque, axial torque, power and heat flow; time integrals;
 // advance t and the step counter.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void k_final(const SlotDesc* table, LaunchTab tab) {
+constexpr int FINAL_BLOCK = 1024;
+__global__ __launch_bounds__(FINAL_BLOCK) void k_final(const SlotDesc* table, LaunchTab tab) {
   __shared__ double res[NGLOB + NB * 13];
   SLOT_PROLOGUE(DOM_SLOT);
   (void)lb;
   const int nblk = S.nblk[DOM_FLUID];
   const int nq = NGLOB + S.nbody * 13;
   const int wv = threadIdx.x / WAVE, ln = threadIdx.x % WAVE;
-  for (int qi = wv; qi < nq; qi += BLOCK / WAVE) {
+  for (int qi = wv; qi < nq; qi += FINAL_BLOCK / WAVE) {
     // quantity qi: global k, or body b component c (7 viscous then 6 pressure)
     // partials are quantity-major: src[q * nblk + block]
     const double* src;
@@ -1070,15 +1263,26 @@ __global__ __launch_bounds__(BLOCK) void k_final(const SlotDesc* table, LaunchTa
       const int b = (qi - NGLOB) / 13, c = (qi - NGLOB) % 13;
       src = c < 7 ? S.visc_part + (size_t)(b * 7 + c) * nblk : S.press_part + (size_t)(b * 6 + c - 7) * nblk;
     }
+    const GLB double* q = gpc<double>(src);
     if (is_max) {
       double m = 0.0;
-      for (int k = ln; k < nblk; k += WAVE) m = fmax(m, src[k]);
+      for (int k = ln; k < nblk; k += WAVE) m = fmax(m, q[k]);
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, WAVE));
       if (ln == 0) res[qi] = m;
     } else {
+      // eight independent loads in flight per lane, then added in order
       KS ks = {0.0, 0.0};
-      for (int k = ln; k < nblk; k += WAVE) ks_add(ks, src[k]);
+      for (int k0 = 0; k0 < nblk; k0 += 8 * WAVE) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int k = k0 + u * WAVE + ln;
+          x[u] = k < nblk ? q[k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) ks_add(ks, x[u]);
+      }
       ks = wave_ks(ks);
       if (ln == 0) res[qi] = ks.s + ks.c;
     }
@@ -1184,7 +1388,7 @@ static hipError_t launch_p(int kid, int which, int sub, const SlotDesc* T, const
     case SPH_K_CONTINUITY: hipLaunchKernelGGL(k_continuity<P>, g, b, 0, st, T, L, sub); break;
     case SPH_K_HALF_B: hipLaunchKernelGGL(k_half_b<P>, g, b, 0, st, T, L, sub); break;
     case SPH_K_END: hipLaunchKernelGGL(k_end<P>, g, b, 0, st, T, L); break;
-    case SPH_K_FINAL: hipLaunchKernelGGL(k_final, g, b, 0, st, T, L); break;
+    case SPH_K_FINAL: hipLaunchKernelGGL(k_final, g, dim3(FINAL_BLOCK), 0, st, T, L); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -74,11 +74,17 @@ class Server:
         self.peak_bytes = 0
         self.peak_active = 0
 
-    def run(self, requests: List[Request], clock=time.perf_counter):
-        """Serve every request; fills admitted/finished/report on each."""
+    def run(self, requests: List[Request], clock=time.perf_counter, max_in_flight: int = 2):
+        """Serve every request; fills admitted/finished/report on each.
+
+        At most `max_in_flight` pool-step calls are queued on the device, so
+        admissions and completions are seen within a few calls.
+        """
+        torch = self.pool.torch
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         queue: collections.deque = collections.deque()
         active = {}
+        inflight: collections.deque = collections.deque()
         t0 = clock()
         while pending or queue or active:
             now = clock() - t0
@@ -100,6 +106,11 @@ class Server:
             self.peak_active = max(self.peak_active, nact)
             if active:
                 self.pool.step(self.k)
+                ev = torch.cuda.Event()
+                ev.record(self.pool.stream)
+                inflight.append(ev)
+                while len(inflight) > max_in_flight:
+                    inflight.popleft().synchronize()
                 # finished slots (their work has completed on the device)
                 for slot in list(active):
                     done, rep = self.pool.poll(slot)

@@ -129,7 +129,10 @@ class TorchAllocator:
                 return None
 
         def _free(ptr, stream, user):
-            torch.cuda.caching_allocator_delete(int(ptr))
+            try:
+                torch.cuda.caching_allocator_delete(int(ptr))
+            except Exception:  # interpreter shutdown: torch already torn down
+                pass
 
         self._a = ALLOC_FN(_alloc)
         self._f = FREE_FN(_free)
