@@ -65,8 +65,9 @@ class Server:
     """Admits requests by HBM budget and free slots; steps all active slots together."""
 
     def __init__(self, hbm_budget: int, max_slots: int = 16, precision: str = "mixed",
-                 steps_per_call: int = 10, graph: bool = True):
-        self.pool = sph.Pool(hbm_budget, max_slots=max_slots, precision=precision, graph=graph)
+                 steps_per_call: int = 10, graph: bool = True, pool=None):
+        self.pool = pool if pool is not None else sph.Pool(hbm_budget, max_slots=max_slots,
+                                                           precision=precision, graph=graph)
         self.precision = precision
         self.k = steps_per_call
         self.max_slots = max_slots
@@ -74,13 +75,13 @@ class Server:
         self.peak_bytes = 0
         self.peak_active = 0
 
-    def run(self, requests: List[Request], clock=time.perf_counter, max_in_flight: int = 2):
+    def run(self, requests: List[Request], clock=time.perf_counter, max_in_flight: int = 2, progress=None):
         """Serve every request; fills admitted/finished/report on each.
 
         At most `max_in_flight` pool-step calls are queued on the device, so
         admissions and completions are seen within a few calls.
         """
-        torch = self.pool.torch
+        torch = getattr(self.pool, "torch", None)
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         queue: collections.deque = collections.deque()
         active = {}
@@ -92,7 +93,7 @@ class Server:
                 queue.append(pending.popleft())
             while queue:
                 r = queue[0]
-                if sph.Pool.bytes_required(r.case, self.precision) > self.budget:
+                if self.pool.bytes_required(r.case, self.precision) > self.budget:
                     raise ValueError(f"request {r.rid} can never fit the HBM budget")
                 slot = self.pool.admit(r.case, r.steps)
                 if slot is None:
@@ -106,11 +107,12 @@ class Server:
             self.peak_active = max(self.peak_active, nact)
             if active:
                 self.pool.step(self.k)
-                ev = torch.cuda.Event()
-                ev.record(self.pool.stream)
-                inflight.append(ev)
-                while len(inflight) > max_in_flight:
-                    inflight.popleft().synchronize()
+                if torch is not None:
+                    ev = torch.cuda.Event()
+                    ev.record(self.pool.stream)
+                    inflight.append(ev)
+                    while len(inflight) > max_in_flight:
+                        inflight.popleft().synchronize()
                 # finished slots (their work has completed on the device)
                 for slot in list(active):
                     done, rep = self.pool.poll(slot)
@@ -120,9 +122,12 @@ class Server:
                         r.report = rep
                         r.final = self.pool.get_fluid(slot) if getattr(r, "keep_state", False) else None
                         self.pool.release(slot)
+                        if progress is not None:
+                            progress(r, len(active), len(queue), len(pending))
             elif pending:
                 time.sleep(max(0.0, min(0.01, pending[0].arrival - (clock() - t0))))
-        self.pool.stream.synchronize()
+        if torch is not None:
+            self.pool.stream.synchronize()
         return requests
 
     def close(self):
