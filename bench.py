@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_2512_09904_amd", "csrc", "sph_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "momentum_gearbox_c2_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gearbox_c2.json")
 
 
 def log(*a):
@@ -45,24 +45,41 @@ def pair_counts(s, nf):
     return int(cnt[0].sum()), int(cnt[1].sum())
 
 
-def sweep_bytes(kernel, nf, ns, pf, ps, prec="mixed"):
+def sweep_bytes(kernel, nf, nsr, pf, ps, prec="mixed"):
     """Algorithmic HBM bytes of one launch: each array touched once, rows streamed.
 
-    Rows hold 20 B per pair (index, r_ij, F) in mixed precision; the
+    `nsr` is the number of distinct solid particles that appear in some
+    fluid particle's row (the wall arrays read).  A row record is four reals
+    (r_ij and the packed neighbour index): 16 B in mixed precision.  The
     neighbour-state gathers re-read arrays already counted once.
     """
-    rb = 4 if prec != "fp64" else 8
-    rec = 4 + 4 * rb
+    rb = 8 if prec == "fp64" else 4          # Real
+    pb = 4 if prec == "fp32" else 8          # Pos, Temp
+    v4 = 4 * rb
+    rows = (pf + ps) * v4
+    cnt = 8                                  # fluid and solid row lengths
     if kernel == "momentum":
-        own = nf * (3 * rb + rb + 3 * rb + 2 * 3 * rb + 3 * rb + 8)   # v, rho, a_visc, drift rw, v_new, counts
-        return own + (pf + ps) * rec + ns * (4 + 3 * rb)              # + rows, solid body and lever arm
+        # vr, ah, counts read; vrn written; drift read and written; wall lever arms
+        return nf * (v4 + v4 + cnt + v4 + 2 * v4) + rows + nsr * v4
     if kernel == "continuity":
-        own = nf * (3 * rb + rb + rb + 3 * rb + 8)                     # v_new, rho, drho, v, counts
-        return own + (pf + ps) * rec + ns * (4 * 0 + 6 * rb)           # + rows, solid normal and velocity
+        # vrn, counts read; drho and vr written; wall normals and velocities
+        return nf * (v4 + cnt + rb + v4) + rows + nsr * 2 * v4
     if kernel == "visc_heat":
-        own = nf * (3 * rb + rb + 8 + 3 * rb + rb + 8)                  # v, rho, T, a_visc, dTdt, counts
-        return own + (pf + ps) * (4 + rb) + ns * (4 + 6 * rb)          # index and F only
+        # vr, T, counts read; ah written; staged records read, SELL rows written
+        return nf * (v4 + pb + cnt + v4) + 2 * rows + nsr * 2 * v4
+    if kernel == "build":
+        # positions; counts, sum W written; vr read and written; records written
+        return nf * (4 * pb + cnt + 8 + 2 * v4) + rows + nsr * 4 * pb
     raise KeyError(kernel)
+
+
+def distinct_wall_particles(s, nf):
+    """Solid particles referenced by at least one fluid particle's row."""
+    cnt = s.dump("nbr_count").reshape(2, nf)[1].astype(np.int64)
+    ks = len(s.dump("nbr_solid")) // nf
+    rows = s.dump("nbr_solid").reshape(nf, ks)
+    mask = np.arange(ks)[None, :] < cnt[:, None]
+    return int(np.unique(rows[mask]).size)
 
 
 def pct(a, q):
@@ -124,6 +141,8 @@ def serve_bench(args):
             time.sleep(0.0005)
         svc.append(time.perf_counter() - a)
         r.alone = rep
+        if len(svc) % 8 == 0:
+            log(f"alone: {len(svc)}/{len(reqs)} requests, last {svc[-1]:.3f} s (nf {r.case.nf})")
         pool.release(slot)
         pool.close()
     svc = np.array(svc)
@@ -148,7 +167,14 @@ def serve_bench(args):
             r.admitted = r.finished = r.report = None
         srv = serve.Server(budget, max_slots=args.serve_slots)
         a = time.perf_counter()
-        srv.run(reqs)
+        ndone = [0]
+
+        def progress(r, nact, nq, npend):
+            ndone[0] += 1
+            if ndone[0] % 8 == 0:
+                log(f"batched: {ndone[0]} done, {nact} active, {nq} queued, {npend} not arrived")
+
+        srv.run(reqs, progress=progress)
         wall = time.perf_counter() - a
         summ = serve.summarize(reqs, wall)
         same = all(np.array_equal(r.report["bodies"][1]["torque_axis"], r.alone["bodies"][1]["torque_axis"]) and
@@ -173,6 +199,70 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def precision_study(args):
+    """All-FP32 vs mixed FP32/FP64 vs FP64 on the churning tank (C1 geometry).
+
+    Each mode runs the same advection steps from the same state; the FP64
+    GPU run is the reference.  Reported per mode: relative drift of the
+    mass proxy sum(rho dp^3), heat-balance residual (thermal energy change
+    minus the integrated heat inflow, relative to the inflow), mean oil
+    temperature rise, time-mean disk torque and the field differences to
+    the reference.
+    """
+    from paper_2512_09904_amd import cases, sph
+    c = cases.tank_c1(dp=args.ps_dp, omega=450.0)
+    log(f"precision study: nf={c.nf} ns={c.ns} steps={args.ps_steps}")
+    m = c.params["rho0"] * c.params["dp"] ** 3
+    cp = c.params["cp_f"]
+    out = {}
+    final = {}
+    for mode in ("fp64", "mixed", "fp32"):
+        s = sph.Solver(c, precision=mode)
+        r0 = None
+        tq = 0.0
+        t0 = time.perf_counter()
+        chunk = 100
+        done = 0
+        while done < args.ps_steps:
+            n = min(chunk, args.ps_steps - done)
+            s.step(n)
+            r = s.reduce(raise_on_fault=False)
+            if r["rc"]:
+                log(f"{mode}: fault {r['rc']} at step {r['step']}")
+                break
+            r0 = r0 or r
+            done += n
+            if done % 5000 == 0:
+                log(f"{mode}: {done} steps, t={r['t']:.4f} s, vmax={r['vmax']:.2f}")
+        wall = time.perf_counter() - t0
+        g = s.get_fluid()
+        s.close()
+        dE = float(np.sum(m * cp * (g["T"] - c.Tf)))
+        out[mode] = {"steps": int(r["step"]), "t": r["t"], "wall_s": wall,
+                     "mass_proxy_drift": r["mass_proxy"] / r["mass"] - 1.0,
+                     "heat_in_J": r["heat_total"], "thermal_change_J": dE,
+                     "heat_balance_residual": (dE - r["heat_total"]) / abs(r["heat_total"]),
+                     "mean_T_rise_K": float(np.mean(g["T"] - c.Tf)),
+                     "disk_torque_mean_Nm": r["bodies"][1]["torque_axis_int"] / r["t"],
+                     "disk_heat_mean_W": r["bodies"][1]["heat_int"] / r["t"]}
+        final[mode] = g
+        log(f"{mode}: {json.dumps(out[mode])}")
+    ref = final["fp64"]
+    umax = c.meta["umax"]
+    for mode in ("mixed", "fp32"):
+        g = final[mode]
+        out[mode]["vs_fp64"] = {
+            "v_rms_over_umax": float(np.sqrt(np.mean(np.sum((g["v"] - ref["v"]) ** 2, axis=1))) / umax),
+            "rho_rms_over_rho0": float(np.sqrt(np.mean((g["rho"] - ref["rho"]) ** 2)) / c.params["rho0"]),
+            "T_rise_rel": (out[mode]["mean_T_rise_K"] - out["fp64"]["mean_T_rise_K"]) /
+                          abs(out["fp64"]["mean_T_rise_K"]),
+            "torque_rel": (out[mode]["disk_torque_mean_Nm"] - out["fp64"]["disk_torque_mean_Nm"]) /
+                          abs(out["fp64"]["disk_torque_mean_Nm"])}
+    print(json.dumps({"metric": "precision study: drift vs FP64 GPU reference", "config": {
+        "workload": f"churning tank dp={args.ps_dp * 1e3:.3f} mm, disk 450 rad/s, {args.ps_steps} steps",
+        "n_fluid": c.nf, "n_solid": c.ns}, "modes": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -191,6 +281,10 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=24.0)
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-seeds", type=int, default=1, help="arrival seeds (64, 65, ...)")
+    ap.add_argument("--precision-study", action="store_true",
+                    help="churning tank in fp32 / mixed / fp64: drift of the conserved quantities")
+    ap.add_argument("--ps-steps", type=int, default=20000)
+    ap.add_argument("--ps-dp", type=float, default=0.788e-3)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -215,6 +309,9 @@ def main():
 
     if args.serve:
         serve_bench(args)
+        return
+    if args.precision_study:
+        precision_study(args)
         return
 
     t0 = time.perf_counter()
@@ -256,7 +353,7 @@ def main():
     s.set_timing(False)
     # sub-step kernels are launched for the bound on n_ac; launches past a
     # step's n_ac exit at once and are dropped from the per-launch statistics
-    for k in ("half_a", "momentum", "continuity", "half_b"):
+    for k in ("momentum", "continuity", "half_b"):
         nl = len(kt[k]) // args.timed_steps
         kt[k + "_all"] = kt[k]
         kt[k] = np.concatenate([kt[k][q * nl: q * nl + nac_steps[q]] for q in range(args.timed_steps)])
@@ -264,26 +361,32 @@ def main():
     per_step_kernel_ms = {k: float(kt[k + "_all" if k + "_all" in kt else k].sum() / args.timed_steps)
                           for k in sph.KERNELS if len(kt[k])}
     log("per-step kernel ms:", json.dumps({k: round(v, 4) for k, v in per_step_kernel_ms.items()}))
-    dom = "momentum"
-    avg_ms = float(np.mean(kt[dom]))
-    bytes_launch = sweep_bytes(dom, case.nf, case.ns, pf2, ps2, args.precision)
-    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    nsr = distinct_wall_particles(s, case.nf)
+    kern = {}
+    for k in ("build", "visc_heat", "momentum", "continuity"):
+        b = sweep_bytes(k, case.nf, nsr, pf2, ps2, args.precision)
+        ms = float(np.mean(kt[k]))
+        kern[k] = {"bytes_per_launch": int(b), "avg_launch_ms": round(ms, 5),
+                   "achieved_GBs": round(b / (ms * 1e-3) / 1e9, 1),
+                   "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                   "ms_per_step": round(per_step_kernel_ms[k], 4)}
+    # the dominant kernel: the largest share of the step's device time
+    dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
+    avg_ms = kern[dom]["avg_launch_ms"]
+    bytes_launch = kern[dom]["bytes_per_launch"]
+    achieved = kern[dom]["achieved_GBs"]
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
+        ent = tr.get(dom, {})
         if tr.get("kernel_sha") == kernel_hash() and tr.get("precision") == args.precision:
-            traffic = tr.get("bytes_per_launch")
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": "k_momentum",
-                "bytes_per_launch": int(bytes_launch), "avg_launch_ms": round(avg_ms, 5)}
+            traffic = ent.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": "k_" + dom,
+                "bytes_per_launch": int(bytes_launch), "avg_launch_ms": avg_ms}
     sweep_lat = {k: {"p50_ms": round(pct(kt[k], 50), 5), "p99_ms": round(pct(kt[k], 99), 5), "n": len(kt[k])}
                  for k in ("build", "visc_heat", "momentum", "continuity") if len(kt[k])}
-    others = {}
-    for k in ("continuity", "visc_heat"):
-        b = sweep_bytes(k, case.nf, case.ns, pf2, ps2, args.precision)
-        gbs = b / (float(np.mean(kt[k])) * 1e-3) / 1e9
-        others[k] = {"achieved_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -313,7 +416,7 @@ def main():
         "sweep_latency": sweep_lat,
         "event_timed": {"steps": args.timed_steps, "ms_per_step": 1e3 * wall2 / args.timed_steps,
                         "kernel_ms_per_step": {k: round(v, 4) for k, v in per_step_kernel_ms.items()},
-                        "other_sweeps": others},
+                        "kernels": kern, "wall_particles_in_rows": nsr},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

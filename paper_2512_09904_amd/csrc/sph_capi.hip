@@ -150,7 +150,7 @@ static size_t carve(const Plan& P, void* base, SlotDesc* d) {
   C.take(D.fid2, nf * 4);
   C.take(D.nfc, nf * 4);
   C.take(D.nsc, nf * 4);
-  C.take(D.jstage, nf * (size_t)(P.kf + P.ks) * 4);
+  C.takev(D.rstage, nf * (size_t)(P.kf + P.ks) * 4 * rs);
   C.takev(D.nrec, 4 * (size_t)P.rowlen_f * rs);
   C.takev(D.srec, 4 * (size_t)P.rowlen_s * rs);
   C.takev(D.x0, ns * 32);
@@ -379,8 +379,10 @@ static int enqueue_step(sph_pool* P, const LaunchTab& T, int nac) {
   LCHK(enqueue_sort_build(P, T));
   LCHK(launch(P, T, SPH_K_DT, 0, 0));
   LCHK(launch(P, T, SPH_K_VISC_HEAT, 0, 0));
+  // sub-step s: momentum, continuity, then close s and open s + 1 (the first
+  // opening half update is its own launch)
+  LCHK(launch(P, T, SPH_K_HALF_A, 0, 0));
   for (int s = 0; s < nac; ++s) {
-    LCHK(launch(P, T, SPH_K_HALF_A, 0, s));
     LCHK(launch(P, T, SPH_K_MOMENTUM, 0, s));
     LCHK(launch(P, T, SPH_K_CONTINUITY, 0, s));
     LCHK(launch(P, T, SPH_K_HALF_B, 0, s));

@@ -66,7 +66,7 @@ struct SlotDesc {
   uint32_t *fid2;
   // neighbour rows (SELL, slice height 64) of records (rx, ry, rz, j)
   uint32_t *nfc, *nsc;
-  uint32_t *jstage;     // build output: per particle kf fluid then ks solid indices
+  void *rstage;         // build output: per particle kf fluid then ks solid records
   void *nrec;
   void *srec;
   // solids: FP64 reference pose (x, y, z, 0) and normal, body; current pose

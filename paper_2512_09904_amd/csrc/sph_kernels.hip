@@ -486,7 +486,31 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(const SlotDesc* table, Launch
   perm[pos] = (uint32_t)i;
 }
 
-__device__ __forceinline__ void sort_run(uint32_t* perm, uint32_t b, uint32_t e, const uint32_t* id) {
+// Insertion sort of one cell's run by original id.  Runs of up to RUN_LDS
+// entries are sorted in this thread's LDS slots (keys loaded once, in
+// parallel); longer runs are sorted in place in global memory.
+constexpr int RUN_LDS = 32;
+__device__ __forceinline__ void sort_run_strided(uint32_t* perm, uint32_t b, uint32_t e, const uint32_t* id,
+                                                 uint2* buf) {
+  const uint32_t n = e - b;
+  if (n < 2) return;
+  if (n <= (uint32_t)RUN_LDS) {
+    for (uint32_t k = 0; k < n; ++k) {
+      const uint32_t p = perm[b + k];
+      buf[k * BLOCK] = make_uint2(id[p], p);
+    }
+    for (uint32_t k = 1; k < n; ++k) {
+      const uint2 key = buf[k * BLOCK];
+      uint32_t m = k;
+      while (m > 0 && buf[(m - 1) * BLOCK].x > key.x) {
+        buf[m * BLOCK] = buf[(m - 1) * BLOCK];
+        --m;
+      }
+      buf[m * BLOCK] = key;
+    }
+    for (uint32_t k = 0; k < n; ++k) perm[b + k] = buf[k * BLOCK].y;
+    return;
+  }
   for (uint32_t k = b + 1; k < e; ++k) {
     const uint32_t key = perm[k];
     const uint32_t kid = id[key];
@@ -500,11 +524,14 @@ __device__ __forceinline__ void sort_run(uint32_t* perm, uint32_t b, uint32_t e,
 }
 
 __global__ __launch_bounds__(BLOCK) void k_cellsort(const SlotDesc* table, LaunchTab tab) {
+  __shared__ uint2 lds[BLOCK * RUN_LDS];
   SLOT_PROLOGUE(DOM_CELL);
   const int c = lb * BLOCK + threadIdx.x;
   if (c >= S.ncells) return;
-  sort_run(S.fperm, S.start_f[c], S.start_f[c + 1], S.fid);
-  sort_run(S.sperm, S.start_s[c], S.start_s[c + 1], S.sid);
+  // slot k of this thread is lds[k * BLOCK + thread]: the k-th entries of a
+  // wave are adjacent (no bank conflicts)
+  sort_run_strided(S.fperm, S.start_f[c], S.start_f[c + 1], S.fid, lds + threadIdx.x);
+  sort_run_strided(S.sperm, S.start_s[c], S.start_s[c + 1], S.sid, lds + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -544,8 +571,8 @@ __global__ __launch_bounds__(BLOCK) void k_reorder(const SlotDesc* table, Launch
 // K: neighbour rows (Section 2.8: neighbour lists and kernel quantities are
 // refreshed once per advection step).  The cutoff test d^2 < (2h)^2 is FP64
 // with d^2 = (dx dx + dy dy) + dz dz and no contraction.  Each hit stores the
-// neighbour index (the pair geometry r_ij, F is written by the first sweep,
-// whose stores are coalesced).  The kernel sum (self, fluid, solid) drives the
+// record (r_ij, j) in a per-particle staging row; the first sweep moves it
+// into the SELL rows with coalesced stores.  The kernel sum (self, fluid, solid) drives the
 // density re-initialisation of Section 2.4 (eq. 14 with a free surface, eq. 15
 // without), against the perfect-lattice sum S0.
 //
@@ -555,8 +582,8 @@ __global__ __launch_bounds__(BLOCK) void k_reorder(const SlotDesc* table, Launch
 // stencil's cell ranges are fetched lane-parallel).  A cell's candidates are
 // staged with one coalesced load per 64 into the wave's LDS slots, and each
 // lane tests them (those of its own stencil) into a hit mask, without branches
-// or stores per candidate.  The kernel sum is then taken over each lane's own
-// hits.
+// or stores per candidate; each hit then adds its kernel weight and stages its
+// record (r_ij, j).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int wave_min_i(int v) {
 #pragma unroll
@@ -604,10 +631,10 @@ __global__ __launch_bounds__(BLOCK) void k_build(const SlotDesc* table, LaunchTa
   const Pos xi = xi4.x, yi = xi4.y, zi = xi4.z;
   int c[3];
   cell_coords<Pos>(S, xi, yi, zi, c);
-  // indices go to per-particle contiguous staging rows (the first sweep moves
+  // records go to per-particle contiguous staging rows (the first sweep moves
   // them into the SELL rows): a lane's successive stores fill whole lines
-  GLB uint32_t* nj = gp<uint32_t>(S.jstage) + (int64_t)ii * (S.kf + S.ks);
-  GLB uint32_t* sj = nj + S.kf;
+  GLB Real4* nj = gp<Real4>(S.rstage) + (int64_t)ii * (S.kf + S.ks);
+  GLB Real4* sj = nj + S.kf;
   const double h = S.h, cut2 = S.cut2, kW = S.kW;
   const int kf = S.kf, ks = S.ks;
   const GLB uint32_t* rank = gpc<uint32_t>(S.rank);
@@ -683,7 +710,21 @@ __global__ __launch_bounds__(BLOCK) void k_build(const SlotDesc* table, LaunchTa
         while (hits) {
           const int e = __builtin_ctzll(hits);
           hits &= hits - 1;
-          if (cf < kf) nj[cf] = jb + (uint32_t)e;
+          const Pos4 xq = stage[e];
+          const Pos ddx = xi - xq.x, ddy = yi - xq.y, ddz = zi - xq.z;
+          const Pos s2 = ddx * ddx + ddy * ddy;
+          const Pos d2 = s2 + ddz * ddz;
+          const double qq = sqrt((double)d2) * inv_h;
+          const double tt = 1.0 - 0.5 * qq;
+          sw += kW * tt * tt * tt * tt * (1.0 + 2.0 * qq);
+          if (cf < kf) {
+            Real4 rec;
+            rec.x = (Real)ddx;
+            rec.y = (Real)ddy;
+            rec.z = (Real)ddz;
+            rec.w = pack_index(jb + (uint32_t)e, (Real)0);
+            nj[cf] = rec;
+          }
           ++cf;
         }
         __builtin_amdgcn_wave_barrier();
@@ -708,33 +749,25 @@ __global__ __launch_bounds__(BLOCK) void k_build(const SlotDesc* table, LaunchTa
         while (hits) {
           const int e = __builtin_ctzll(hits);
           hits &= hits - 1;
-          if (cs < ks) sj[cs] = wb + (uint32_t)e;
+          const Pos4 xq = stage[e];
+          const Pos ddx = xi - xq.x, ddy = yi - xq.y, ddz = zi - xq.z;
+          const Pos s2 = ddx * ddx + ddy * ddy;
+          const Pos d2 = s2 + ddz * ddz;
+          const double qq = sqrt((double)d2) * inv_h;
+          const double tt = 1.0 - 0.5 * qq;
+          sw += kW * tt * tt * tt * tt * (1.0 + 2.0 * qq);
+          if (cs < ks) {
+            Real4 rec;
+            rec.x = (Real)ddx;
+            rec.y = (Real)ddy;
+            rec.z = (Real)ddz;
+            rec.w = pack_index(wb + (uint32_t)e, (Real)0);
+            sj[cs] = rec;
+          }
           ++cs;
         }
         __builtin_amdgcn_wave_barrier();
       }
-    }
-  }
-  // kernel sum over this particle's own hits (self, fluid, solid)
-  if (act) {
-    const int nfh = min(cf, kf), nsh = min(cs, ks);
-    for (int k = 0; k < nfh; ++k) {
-      const Pos4 xj = xa[nj[k]];
-      const Pos ddx = xi - xj.x, ddy = yi - xj.y, ddz = zi - xj.z;
-      const Pos s2 = ddx * ddx + ddy * ddy;
-      const Pos d2 = s2 + ddz * ddz;
-      const double qq = sqrt((double)d2) * inv_h;
-      const double tt = 1.0 - 0.5 * qq;
-      sw += kW * tt * tt * tt * tt * (1.0 + 2.0 * qq);
-    }
-    for (int k = 0; k < nsh; ++k) {
-      const Pos4 xq = xw[sj[k]];
-      const Pos ddx = xi - xq.x, ddy = yi - xq.y, ddz = zi - xq.z;
-      const Pos s2 = ddx * ddx + ddy * ddy;
-      const Pos d2 = s2 + ddz * ddz;
-      const double qq = sqrt((double)d2) * inv_h;
-      const double tt = 1.0 - 0.5 * qq;
-      sw += kW * tt * tt * tt * tt * (1.0 + 2.0 * qq);
     }
   }
   if (!act) return;
@@ -801,26 +834,6 @@ __global__ __launch_bounds__(BLOCK) void k_dt(const SlotDesc* table, LaunchTab t
   C->n_ac = nac;
 }
 
-// Frozen pair geometry of a row entry: r_ij = x_i - x_j from the FP64 anchors
-// (rounded to the interaction type) and F = (dW/dr)/r = kF (1 - q/2)^3 from
-// the FP64 distance, evaluated exactly as in the build's cutoff test.
-template <class Pos, class Real4>
-__device__ __forceinline__ Real4 pair_geom(const SlotDesc& S, Pos xi, Pos yi, Pos zi, Pos xj, Pos yj, Pos zj) {
-#pragma clang fp contract(off)
-  typedef decltype(Real4().x) Real;
-  const Pos ddx = xi - xj, ddy = yi - yj, ddz = zi - zj;
-  const Pos s2 = ddx * ddx + ddy * ddy;
-  const Pos d2 = s2 + ddz * ddz;
-  const double q = sqrt((double)d2) / S.h;
-  const double t = 1.0 - 0.5 * q;
-  Real4 r;
-  r.x = (Real)ddx;
-  r.y = (Real)ddy;
-  r.z = (Real)ddz;
-  r.w = (Real)(S.kF * t * t * t);
-  return r;
-}
-
 // Rows are walked four entries at a time; entries past a row's count are
 // loaded from the row's capacity (always in bounds, capacities are multiples
 // of four) and replaced by a null entry: own index, r = 0, F = 0, which adds
@@ -830,17 +843,15 @@ __device__ __forceinline__ Real4 pair_geom(const SlotDesc& S, Pos xi, Pos yi, Po
 // ---------------------------------------------------------------------------
 // K: viscous acceleration (eq. 10 fluid-fluid, eq. 18 fluid-wall) and heat
 // conduction rate (eq. 22), both frozen for the advection step.  As the first
-// sweep over fresh rows it moves the build's indices into the SELL rows as
-// records (r_ij, j).
-// Per-block partials: viscous force and torque on each body and its heat flow
-// into the fluid.  Also clears this block's pressure-force accumulators.
+// sweep over fresh rows it moves the build's staged records (r_ij, j) into the
+// SELL rows.  Per-block partials: viscous force and torque on each body and
+// its heat flow into the fluid.  Also clears this block's pressure-force
+// accumulators.
 // ---------------------------------------------------------------------------
 template <class P>
 __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, LaunchTab tab) {
-  typedef typename P::Pos Pos;
   typedef typename P::Real Real;
   typedef typename P::Temp Temp;
-  typedef typename P::Pos4 Pos4;
   typedef typename P::Real4 Real4;
   __shared__ double lds[4 * NB * 7];
   SLOT_PROLOGUE(DOM_FLUID);
@@ -852,11 +863,11 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
   acc.init();
   bool wall = false;
   if (i < nf) {
-    const GLB Pos4* xa = gpc<Pos4>(S.xa);
     const GLB Real4* vr = gpc<Real4>(S.vr);
     const GLB Temp* T = gpc<Temp>(S.T);
+    const GLB Real4* RS = gpc<Real4>(S.rstage) + (int64_t)i * (S.kf + S.ks);
     const Real m = (Real)S.mass;
-    const Pos4 xi = xa[i];
+    const Real inv_h = (Real)(1.0 / S.h), kF = (Real)S.kF;
     const Real4 vi = vr[i];
     const Real rhoi = rho_abs<P>(S, vi.w);
     const Temp Ti = T[i];
@@ -867,67 +878,61 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
     const int64_t slice = i >> 6;
     {
       const int n = (int)S.nfc[i];
-      const int64_t base = slice * (int64_t)S.kf * WAVE + lane;
-      const GLB u4* JS = gpc<u4>(S.jstage) + (int64_t)i * ((S.kf + S.ks) / 4);
-      GLB Real4* R = gp<Real4>(S.nrec) + base;
+      GLB Real4* R = gp<Real4>(S.nrec) + slice * (int64_t)S.kf * WAVE + lane;
       for (int k = 0; k < n; k += ROW_UNROLL) {
+        Real4 g[ROW_UNROLL];
         uint32_t j[ROW_UNROLL];
-        const u4 js = JS[k / 4];
 #pragma unroll
-        for (int u = 0; u < ROW_UNROLL; ++u) j[u] = k + u < n ? js[u] : (uint32_t)i;
-        Pos4 xj[ROW_UNROLL];
+        for (int u = 0; u < ROW_UNROLL; ++u) {
+          const Real4 gr = RS[k + u];
+          const bool ok = k + u < n;
+          g[u] = ok ? gr : Real4(0);
+          j[u] = ok ? unpack_index(gr.w) : (uint32_t)i;
+        }
         Real4 vj[ROW_UNROLL];
         Temp Tj[ROW_UNROLL];
 #pragma unroll
         for (int u = 0; u < ROW_UNROLL; ++u) {
-          xj[u] = xa[j[u]];
           vj[u] = vr[j[u]];
           Tj[u] = T[j[u]];
         }
 #pragma unroll
         for (int u = 0; u < ROW_UNROLL; ++u) {
           if (k + u >= n) continue;
-          const Real4 g = pair_geom<Pos, Real4>(S, xi.x, xi.y, xi.z, xj[u].x, xj[u].y, xj[u].z);
-          Real4 rec = g;
-          rec.w = pack_index(j[u], (Real)0);
-          R[(int64_t)(k + u) * WAVE] = rec;
+          R[(int64_t)(k + u) * WAVE] = g[u];
+          const Real Fk = kernel_F(g[u].x * g[u].x + g[u].y * g[u].y + g[u].z * g[u].z, inv_h, kF);
           const Real Vj = m * rcp(rho_abs<P>(S, vj[u].w));
-          const Real cv = c2 * Vj * g.w;
+          const Real cv = c2 * Vj * Fk;
           ax += cv * (vi.x - vj[u].x);
           ay += cv * (vi.y - vj[u].y);
           az += cv * (vi.z - vj[u].z);
-          hs += Vj * Kff * (Real)(Ti - Tj[u]) * g.w;
+          hs += Vj * Kff * (Real)(Ti - Tj[u]) * Fk;
         }
       }
     }
     {
       const int n = (int)S.nsc[i];
       wall = n > 0;
-      const int64_t base = slice * (int64_t)S.ks * WAVE + lane;
-      const GLB uint32_t* JS = gpc<uint32_t>(S.jstage) + (int64_t)i * (S.kf + S.ks) + S.kf;
-      GLB Real4* R = gp<Real4>(S.srec) + base;
-      const GLB Pos4* xw = gpc<Pos4>(S.xw);
+      GLB Real4* R = gp<Real4>(S.srec) + slice * (int64_t)S.ks * WAVE + lane;
       const GLB Real4* vw = gpc<Real4>(S.vw);
       const GLB Real4* lv = gpc<Real4>(S.lev);
       const Real Vw = (Real)S.vol_w;
       const Real rc = rcp(rhoi * (Real)S.cp_f);
       for (int k = 0; k < n; ++k) {
-        const uint32_t w = JS[k];
-        const Pos4 xq = xw[w];
+        const Real4 g = RS[S.kf + k];
+        const uint32_t w = unpack_index(g.w);
         const Real4 vq = vw[w];
         const Real4 lq = lv[w];
-        const Real4 g = pair_geom<Pos, Real4>(S, xi.x, xi.y, xi.z, xq.x, xq.y, xq.z);
-        Real4 rec = g;
-        rec.w = pack_index(w, (Real)0);
-        R[(int64_t)k * WAVE] = rec;
+        R[(int64_t)k * WAVE] = g;
+        const Real Fk = kernel_F(g.x * g.x + g.y * g.y + g.z * g.z, inv_h, kF);
         const int b = (int)lq.w;
-        const Real cv = c2 * Vw * g.w;
+        const Real cv = c2 * Vw * Fk;
         const Real fx = cv * (vi.x - vq.x), fy = cv * (vi.y - vq.y), fz = cv * (vi.z - vq.z);
         ax += fx;
         ay += fy;
         az += fz;
         const Real Kiw = (Real)(4.0 * S.k_f * S.bk[b] / (S.k_f + S.bk[b]));
-        const Real term = Vw * Kiw * (Real)(Ti - (Temp)S.bT[b]) * g.w;
+        const Real term = Vw * Kiw * (Real)(Ti - (Temp)S.bT[b]) * Fk;
         hs += term;
         // force of the fluid on the body is -m_i times this pair's acceleration
         const double gx = -(double)m * fx, gy = -(double)m * fy, gz = -(double)m * fz;
@@ -1173,19 +1178,32 @@ __global__ __launch_bounds__(BLOCK) void k_continuity(const SlotDesc* table, Lau
 }
 
 // ---------------------------------------------------------------------------
-// K: second half of the density update: rho += dt/2 Drho
+// K: close sub-step `sub` (rho += dt/2 Drho) and, unless it is the step's
+// last, open the next one (rho += dt/2 Drho again, x += dt/2 v)
 // ---------------------------------------------------------------------------
 template <class P>
 __global__ __launch_bounds__(BLOCK) void k_half_b(const SlotDesc* table, LaunchTab tab, int sub) {
   typedef typename P::Real Real;
   typedef typename P::Real4 Real4;
   SLOT_PROLOGUE(DOM_FLUID);
-  if (sub >= S.ctl->n_ac) return;
+  const int nac = S.ctl->n_ac;
+  if (sub >= nac) return;
   const int i = lb * BLOCK + threadIdx.x;
   if (i >= S.nf) return;
+  const Real hdt = (Real)(0.5 * S.ctl->dt);
+  const Real dr = gpc<Real>(S.drho)[i];
   GLB Real4* vr = gp<Real4>(S.vr);
   Real4 v = vr[i];
-  v.w += (Real)(0.5 * S.ctl->dt) * gpc<Real>(S.drho)[i];
+  v.w += hdt * dr;
+  if (sub + 1 < nac) {
+    v.w += hdt * dr;
+    GLB Real4* dp = gp<Real4>(S.drift);
+    Real4 d = dp[i];
+    d.x += hdt * v.x;
+    d.y += hdt * v.y;
+    d.z += hdt * v.z;
+    dp[i] = d;
+  }
   vr[i] = v;
 }
 

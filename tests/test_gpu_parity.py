@@ -192,20 +192,29 @@ def test_neighbour_sets_after_motion(sph, ora):
 # ---------------------------------------------------------------------------
 
 def test_multi_step_tank(sph, ora):
+    """200 steps of the tank with the disk at 150 rad/s, GPU (mixed) and oracle
+    each on their own time steps: n_ac and mass identical every step; time-mean
+    disk torque over steps 100-200 and the mean oil temperature rise within 1 %;
+    the GPU's heat balance closes; the growth of the state error is printed."""
     c = cases.tank_c1(seed=0)
-    steps = 40
+    steps = 200
     say("multi-step tank", steps)
     o = ora.State(c)
     s = sph.Solver(c, precision="mixed")
     tq_o, tq_g = [], []
+    umax = c.meta["umax"]
     for k in range(steps):
         ro = o.step()
         s.step(1)
         rg = s.reduce()
         tq_o.append(ro["bodies"][1]["torque_axis"])
         tq_g.append(rg["bodies"][1]["torque_axis"])
-        assert rg["n_ac"] == ro["n_ac"]
+        assert rg["n_ac"] == ro["n_ac"], k
         assert rg["mass"] == pytest.approx(ro["mass"], rel=1e-12)
+        if k in (0, 9, 49, 99, 199):
+            g = s.get_fluid()
+            say(f"e(t) step {k + 1}: x/dp {np.abs(g['x'] - o.x).max() / c.params['dp']:.3e} "
+                f"v/Umax {np.abs(g['v'] - o.v).max() / umax:.3e} T {np.abs(g['T'] - o.T).max() / 20.0:.3e}")
     assert rg["t"] == pytest.approx(ro["t"], rel=1e-6)
     dT_o = ro["thermal"] - o.cum["heat"]
     assert abs(rg["thermal"] - rg["heat_total"] - dT_o) <= 1e-6 * abs(ro["thermal"])
@@ -214,9 +223,14 @@ def test_multi_step_tank(sph, ora):
     cp, m = c.params["cp_f"], c.params["rho0"] * c.params["dp"] ** 3
     dE = math.fsum(m * cp * (g["T"] - c.Tf))
     assert abs(dE - rg["heat_total"]) <= 1e-5 * abs(rg["heat_total"])
-    # mean disk torque over the run agrees with the oracle
-    mo, mg = np.mean(tq_o), np.mean(tq_g)
-    assert abs(mg - mo) <= 0.02 * np.mean(np.abs(tq_o)), (mg, mo)
+    # mean oil temperature rise
+    rise_g, rise_o = np.mean(g["T"] - c.Tf), np.mean(o.T - c.Tf)
+    say("mean T rise gpu / oracle", rise_g, rise_o)
+    assert abs(rise_g - rise_o) <= 0.01 * abs(rise_o)
+    # time-mean disk torque over steps 100-200
+    mo, mg = np.mean(tq_o[100:]), np.mean(tq_g[100:])
+    say("mean disk torque gpu / oracle", mg, mo)
+    assert abs(mg - mo) <= 0.01 * abs(mo), (mg, mo)
     s.close()
 
 
