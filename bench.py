@@ -49,27 +49,28 @@ def sweep_bytes(kernel, nf, nsr, pf, ps, prec="mixed"):
     """Algorithmic HBM bytes of one launch: each array touched once, rows streamed.
 
     `nsr` is the number of distinct solid particles that appear in some
-    fluid particle's row (the wall arrays read).  A row record is four reals
-    (r_ij and the packed neighbour index): 16 B in mixed precision.  The
-    neighbour-state gathers re-read arrays already counted once.
+    fluid particle's row (the wall arrays read).  A row entry is the
+    neighbour's 4-byte index; the pair vector comes from the cell-relative
+    positions (one 4-wide record per particle).  The neighbour-state gathers
+    re-read arrays already counted once.
     """
     rb = 8 if prec == "fp64" else 4          # Real
     pb = 4 if prec == "fp32" else 8          # Pos, Temp
     v4 = 4 * rb
-    rows = (pf + ps) * v4
+    rows = (pf + ps) * 4
     cnt = 8                                  # fluid and solid row lengths
     if kernel == "momentum":
-        # vr, ah, counts read; vrn written; drift read and written; wall lever arms
-        return nf * (v4 + v4 + cnt + v4 + 2 * v4) + rows + nsr * v4
+        # vr, offsets, ah, counts read; vrn written; drift read and written; wall offsets, lever arms
+        return nf * (v4 + v4 + v4 + cnt + v4 + 2 * v4) + rows + nsr * 2 * v4
     if kernel == "continuity":
-        # vrn, counts read; drho and vr written; wall normals and velocities
-        return nf * (v4 + cnt + rb + v4) + rows + nsr * 2 * v4
+        # vrn, offsets, counts read; drho and vr written; wall offsets, normals, velocities
+        return nf * (v4 + v4 + cnt + rb + v4) + rows + nsr * 3 * v4
     if kernel == "visc_heat":
-        # vr, T, counts read; ah written; staged records read, SELL rows written
-        return nf * (v4 + pb + cnt + v4) + 2 * rows + nsr * 2 * v4
+        # vr, offsets, T, counts read; ah written; wall offsets, velocities, lever arms
+        return nf * (v4 + v4 + pb + cnt + v4) + rows + nsr * 3 * v4
     if kernel == "build":
-        # positions; counts, sum W written; vr read and written; records written
-        return nf * (4 * pb + cnt + 8 + 2 * v4) + rows + nsr * 4 * pb
+        # anchors read; offsets, counts, sum W written; vr read and written; rows written; wall positions
+        return nf * (4 * pb + v4 + cnt + 8 + 2 * v4) + rows + nsr * 4 * pb
     raise KeyError(kernel)
 
 

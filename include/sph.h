@@ -182,8 +182,8 @@ enum {
   SPH_DUMP_NBR_COUNT = 4,   /* uint32[2*nf]: fluid counts then solid counts */
   SPH_DUMP_NBR_FLUID = 5,   /* uint32 rows: [nf][kf] sorted index of fluid neighbours (padded) */
   SPH_DUMP_NBR_SOLID = 6,   /* uint32 rows: [nf][ks] sorted index of solid neighbours */
-  SPH_DUMP_GEOM_FLUID = 7,  /* double rows [nf][kf][4]: r_ij (3) as stored, then 0 */
-  SPH_DUMP_GEOM_SOLID = 8,  /* double rows [nf][ks][4] */
+  SPH_DUMP_FLUID_OFFSET = 7,/* double [nf][4]: cell-relative position (3) as stored, packed cell */
+  SPH_DUMP_SOLID_OFFSET = 8,/* double [ns][4]: the same for the sorted solids */
   SPH_DUMP_FLUID_STATE = 9, /* double [nf][16]: anchor(3) drift(3) v(3) rho drho T a_visc(3) dTdt */
   SPH_DUMP_SOLID_STATE = 10,/* double [ns][13]: x(3) n(3) v(3) lever(3) body */
   SPH_DUMP_SUMW = 11        /* double [nf]: kernel sum of the last build */

@@ -150,9 +150,10 @@ static size_t carve(const Plan& P, void* base, SlotDesc* d) {
   C.take(D.fid2, nf * 4);
   C.take(D.nfc, nf * 4);
   C.take(D.nsc, nf * 4);
-  C.takev(D.rstage, nf * (size_t)(P.kf + P.ks) * 4 * rs);
-  C.takev(D.nrec, 4 * (size_t)P.rowlen_f * rs);
-  C.takev(D.srec, 4 * (size_t)P.rowlen_s * rs);
+  C.take(D.nrec, 4 * (size_t)P.rowlen_f);
+  C.take(D.srec, 4 * (size_t)P.rowlen_s);
+  C.takev(D.xo, 4 * nf * rs);
+  C.takev(D.so, 4 * ns * rs);
   C.takev(D.x0, ns * 32);
   C.takev(D.n0, ns * 32);
   C.take(D.body, ns * 4);
@@ -595,6 +596,7 @@ static int admit(sph_pool* P, const sph_params* p, int32_t nbody, const sph_body
     const double two_h = 2.0 * D.h;
     D.cut2 = two_h * two_h;
     D.cs = 2.0 * D.h;
+    D.cs_r = pl.real_sz == 8 ? D.cs : (double)(float)D.cs;
   }
   D.cfl_ad = p->cfl_ad;
   D.cfl_ac = p->cfl_ac;
@@ -1004,8 +1006,8 @@ static size_t dump_bytes(const SlotHost& S, int what) {
     case SPH_DUMP_NBR_COUNT: return 2 * nf * 4;
     case SPH_DUMP_NBR_FLUID: return nf * (size_t)pl.kf * 4;
     case SPH_DUMP_NBR_SOLID: return nf * (size_t)pl.ks * 4;
-    case SPH_DUMP_GEOM_FLUID: return nf * (size_t)pl.kf * 4 * 8;
-    case SPH_DUMP_GEOM_SOLID: return nf * (size_t)pl.ks * 4 * 8;
+    case SPH_DUMP_FLUID_OFFSET: return nf * 4 * 8;
+    case SPH_DUMP_SOLID_OFFSET: return ns * 4 * 8;
     case SPH_DUMP_FLUID_STATE: return nf * 16 * 8;
     case SPH_DUMP_SOLID_STATE: return ns * 13 * 8;
     case SPH_DUMP_SUMW: return nf * 8;
@@ -1060,39 +1062,35 @@ extern "C" int sph_debug_dump(sph_solver* s, int32_t what, void* buf, size_t byt
     }
     case SPH_DUMP_NBR_FLUID:
     case SPH_DUMP_NBR_SOLID: {
-      // the index lives in the fourth lane of each row record
       const bool sol = what == SPH_DUMP_NBR_SOLID;
       const int K = sol ? pl.ks : pl.kf;
       const size_t L = (size_t)(sol ? pl.rowlen_s : pl.rowlen_f);
-      std::vector<char> r(4 * L * rs);
-      LCHK(d2h(r.data(), sol ? D.srec : D.nrec, r.size()));
+      std::vector<uint32_t> r(L);
+      LCHK(d2h(r.data(), sol ? D.srec : D.nrec, r.size() * 4));
       uint32_t* o = (uint32_t*)buf;
-      unsell(pl, K, [&](size_t i, int k, size_t src) {
-        uint32_t j;
-        if (rs == 8) {
-          double d;
-          std::memcpy(&d, r.data() + (4 * src + 3) * 8, 8);
-          j = (uint32_t)d;
-        } else {
-          std::memcpy(&j, r.data() + (4 * src + 3) * 4, 4);
-        }
-        o[i * (size_t)K + (size_t)k] = j;
-      });
+      unsell(pl, K, [&](size_t i, int k, size_t src) { o[i * (size_t)K + (size_t)k] = r[src]; });
       return SPH_OK;
     }
-    case SPH_DUMP_GEOM_FLUID:
-    case SPH_DUMP_GEOM_SOLID: {
-      const bool sol = what == SPH_DUMP_GEOM_SOLID;
-      const int K = sol ? pl.ks : pl.kf;
-      const size_t L = (size_t)(sol ? pl.rowlen_s : pl.rowlen_f);
-      std::vector<char> r(4 * L * rs);
-      LCHK(d2h(r.data(), sol ? D.srec : D.nrec, r.size()));
+    case SPH_DUMP_FLUID_OFFSET:
+    case SPH_DUMP_SOLID_OFFSET: {
+      // (ox, oy, oz) as stored, then the packed cell coordinates as a number
+      const bool sol = what == SPH_DUMP_SOLID_OFFSET;
+      const size_t n = sol ? ns : nf;
+      std::vector<char> r(4 * n * rs);
+      LCHK(d2h(r.data(), sol ? D.so : D.xo, r.size()));
       double* o = (double*)buf;
-      unsell(pl, K, [&](size_t i, int k, size_t src) {
-        double* e = o + (i * (size_t)K + (size_t)k) * 4;
-        for (size_t a = 0; a < 3; ++a) e[a] = get_as_double(r.data(), 4 * src + a, rs);
-        e[3] = 0.0;
-      });
+      for (size_t i = 0; i < n; ++i) {
+        for (size_t a = 0; a < 3; ++a) o[4 * i + a] = get_as_double(r.data(), 4 * i + a, rs);
+        uint32_t c;
+        if (rs == 8) {
+          double d;
+          std::memcpy(&d, r.data() + (4 * i + 3) * 8, 8);
+          c = (uint32_t)d;
+        } else {
+          std::memcpy(&c, r.data() + (4 * i + 3) * 4, 4);
+        }
+        o[4 * i + 3] = (double)c;
+      }
       return SPH_OK;
     }
     case SPH_DUMP_FLUID_STATE: {

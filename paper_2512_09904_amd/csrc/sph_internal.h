@@ -42,8 +42,11 @@ struct SlotCtl {
 // cell-sorted order.  Vectors are stored as 4-wide records (16 B in FP32,
 // 32 B in FP64) so that one load or one gather moves a whole record:
 //   anchor x (x, y, z, 0)          velocity state (vx, vy, vz, delta-rho)
-//   rates (ax, ay, az, dT/dt)       row entry (rx, ry, rz, F)
-//   solid lever arm (lx, ly, lz, body index)
+//   rates (ax, ay, az, dT/dt)       solid lever arm (lx, ly, lz, body index)
+//   cell-relative position (ox, oy, oz, packed cell coordinates), frozen at
+//   the build: x = lo + c cs_r + o, so r_ij = (o_i - o_j) + (c_i - c_j) cs_r
+//   with c_i - c_j in {-1, 0, 1} per axis for every pair
+// A neighbour row entry is the neighbour's sorted index (4 B).
 struct SlotDesc {
   int32_t nf, ns, ncells, nslices;
   int32_t kf, ks, nbody, nac_bound;
@@ -52,6 +55,7 @@ struct SlotDesc {
   int32_t nblk[NDOM];
   int64_t rowlen_f, rowlen_s;          // nslices * k * 64
   double dp, h, rho0, c0, eta, k_f, cp_f, mass, vol_w, S0, cut2, cs;
+  double cs_r;                         // cs rounded to the interaction type (frame of the offsets)
   double cfl_ad, cfl_ac, fixed_dt_ad, nu;
   double g[3], lo[3];
   double kW, kF;                       // W = kW (1-q/2)^4 (1+2q);  F = kF (1-q/2)^3
@@ -64,11 +68,11 @@ struct SlotDesc {
   uint32_t *fcell, *fperm;
   void *xa2, *vr2, *drho2, *T2;
   uint32_t *fid2;
-  // neighbour rows (SELL, slice height 64) of records (rx, ry, rz, j)
+  // neighbour rows (SELL, slice height 64) of sorted neighbour indices, and
+  // the cell-relative positions the sweeps take r_ij from
   uint32_t *nfc, *nsc;
-  void *rstage;         // build output: per particle kf fluid then ks solid records
-  void *nrec;
-  void *srec;
+  uint32_t *nrec, *srec;
+  void *xo, *so;
   // solids: FP64 reference pose (x, y, z, 0) and normal, body; current pose
   void *x0, *n0;
   int32_t *body;

@@ -178,13 +178,45 @@ __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
 
-// A row entry is one 4-wide record (rx, ry, rz, j): the pair vector of the
-// build, rounded to the interaction type, with the neighbour index in the
-// fourth lane (bit pattern in FP32, exact value in FP64).
+// A 32-bit integer in the fourth lane of a 4-wide record: its bit pattern in
+// FP32 (never a NaN: values stay below 2^30), its exact value in FP64.
 __device__ __forceinline__ float pack_index(uint32_t j, float) { return __builtin_bit_cast(float, j); }
 __device__ __forceinline__ double pack_index(uint32_t j, double) { return (double)j; }
 __device__ __forceinline__ uint32_t unpack_index(float w) { return __builtin_bit_cast(uint32_t, w); }
 __device__ __forceinline__ uint32_t unpack_index(double w) { return (uint32_t)w; }
+
+// Cell-relative positions.  At the build every particle stores
+// o = x - (lo + c cs_r) rounded to the interaction type, with its cell c
+// packed as 10 bits per axis.  A pair's vector is then
+//   r_ij = (o_i - o_j) + (c_i - c_j) cs_r,
+// where c_i - c_j is -1, 0 or 1 per axis, so the second term is exact and
+// r_ij carries only the offsets' roundings (a few ulp of cs_r), however far
+// the particles are from the grid origin.
+__device__ __forceinline__ uint32_t pack_cell(const int c[3]) {
+  return (uint32_t)c[0] | (uint32_t)c[1] << 10 | (uint32_t)c[2] << 20;
+}
+template <class Real, class Real4>
+__device__ __forceinline__ void pair_vec(const Real4 a, uint32_t ca, const Real4 b, Real csr, Real& rx, Real& ry,
+                                         Real& rz) {
+  const uint32_t cb = unpack_index(b.w);
+  const int dx = (int)(ca & 1023u) - (int)(cb & 1023u);
+  const int dy = (int)((ca >> 10) & 1023u) - (int)((cb >> 10) & 1023u);
+  const int dz = (int)(ca >> 20) - (int)(cb >> 20);
+  rx = (a.x - b.x) + (Real)dx * csr;
+  ry = (a.y - b.y) + (Real)dy * csr;
+  rz = (a.z - b.z) + (Real)dz * csr;
+}
+template <class P, class Pos>
+__device__ __forceinline__ typename P::Real4 cell_offset(const SlotDesc& S, Pos x, Pos y, Pos z, const int c[3]) {
+#pragma clang fp contract(off)
+  typedef typename P::Real Real;
+  typename P::Real4 o;
+  o.x = (Real)((double)x - (S.lo[0] + (double)c[0] * S.cs_r));
+  o.y = (Real)((double)y - (S.lo[1] + (double)c[1] * S.cs_r));
+  o.z = (Real)((double)z - (S.lo[2] + (double)c[2] * S.cs_r));
+  o.w = pack_index(pack_cell(c), (Real)0);
+  return o;
+}
 
 // F = (dW/dr)/r = kF (1 - q/2)^3 of the Wendland C2 kernel from |r|^2
 template <class Real>
@@ -558,7 +590,11 @@ __global__ __launch_bounds__(BLOCK) void k_reorder(const SlotDesc* table, Launch
     const uint32_t s = S.sperm[k];
     gp<d4>(S.x0)[k] = gpc<d4>(S.x0b)[s];
     gp<d4>(S.n0)[k] = gpc<d4>(S.n0b)[s];
-    gp<Pos4>(S.xw)[k] = gpc<Pos4>(S.xwb)[s];
+    const Pos4 xp = gpc<Pos4>(S.xwb)[s];
+    gp<Pos4>(S.xw)[k] = xp;
+    int c[3];
+    cell_coords<typename P::Pos>(S, xp.x, xp.y, xp.z, c);   // in the grid: checked by the pose
+    gp<Real4>(S.so)[k] = cell_offset<P>(S, xp.x, xp.y, xp.z, c);
     gp<Real4>(S.nw)[k] = gpc<Real4>(S.nwb)[s];
     gp<Real4>(S.vw)[k] = gpc<Real4>(S.vwb)[s];
     gp<Real4>(S.lev)[k] = gpc<Real4>(S.levb)[s];
@@ -571,10 +607,11 @@ __global__ __launch_bounds__(BLOCK) void k_reorder(const SlotDesc* table, Launch
 // K: neighbour rows (Section 2.8: neighbour lists and kernel quantities are
 // refreshed once per advection step).  The cutoff test d^2 < (2h)^2 is FP64
 // with d^2 = (dx dx + dy dy) + dz dz and no contraction.  Each hit stores the
-// record (r_ij, j) in a per-particle staging row; the first sweep moves it
-// into the SELL rows with coalesced stores.  The kernel sum (self, fluid, solid) drives the
-// density re-initialisation of Section 2.4 (eq. 14 with a free surface, eq. 15
-// without), against the perfect-lattice sum S0.
+// neighbour's sorted index in the particle's SELL row; every particle stores
+// its cell-relative position, from which the sweeps form r_ij.  The kernel
+// sum (self, fluid, solid) drives the density re-initialisation of Section
+// 2.4 (eq. 14 with a free surface, eq. 15 without), against the
+// perfect-lattice sum S0.
 //
 // A wavefront holds 64 consecutive particles of the Morton order, i.e. a few
 // distinct neighbouring cells.  It visits the union of their 27-cell stencils
@@ -582,8 +619,8 @@ __global__ __launch_bounds__(BLOCK) void k_reorder(const SlotDesc* table, Launch
 // stencil's cell ranges are fetched lane-parallel).  A cell's candidates are
 // staged with one coalesced load per 64 into the wave's LDS slots, and each
 // lane tests them (those of its own stencil) into a hit mask, without branches
-// or stores per candidate; each hit then adds its kernel weight and stages its
-// record (r_ij, j).
+// or stores per candidate; each hit then adds its kernel weight and writes its
+// index.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int wave_min_i(int v) {
 #pragma unroll
@@ -631,10 +668,11 @@ __global__ __launch_bounds__(BLOCK) void k_build(const SlotDesc* table, LaunchTa
   const Pos xi = xi4.x, yi = xi4.y, zi = xi4.z;
   int c[3];
   cell_coords<Pos>(S, xi, yi, zi, c);
-  // records go to per-particle contiguous staging rows (the first sweep moves
-  // them into the SELL rows): a lane's successive stores fill whole lines
-  GLB Real4* nj = gp<Real4>(S.rstage) + (int64_t)ii * (S.kf + S.ks);
-  GLB Real4* sj = nj + S.kf;
+  // row entry k of particle i sits at (i/64 * K + k) * 64 + i%64
+  const int lane_ = threadIdx.x & (WAVE - 1);
+  GLB uint32_t* nj = gp<uint32_t>(S.nrec) + (int64_t)(ii >> 6) * S.kf * WAVE + lane_;
+  GLB uint32_t* sj = gp<uint32_t>(S.srec) + (int64_t)(ii >> 6) * S.ks * WAVE + lane_;
+  if (act) gp<Real4>(S.xo)[i] = cell_offset<P>(S, xi, yi, zi, c);
   const double h = S.h, cut2 = S.cut2, kW = S.kW;
   const int kf = S.kf, ks = S.ks;
   const GLB uint32_t* rank = gpc<uint32_t>(S.rank);
@@ -717,14 +755,7 @@ __global__ __launch_bounds__(BLOCK) void k_build(const SlotDesc* table, LaunchTa
           const double qq = sqrt((double)d2) * inv_h;
           const double tt = 1.0 - 0.5 * qq;
           sw += kW * tt * tt * tt * tt * (1.0 + 2.0 * qq);
-          if (cf < kf) {
-            Real4 rec;
-            rec.x = (Real)ddx;
-            rec.y = (Real)ddy;
-            rec.z = (Real)ddz;
-            rec.w = pack_index(jb + (uint32_t)e, (Real)0);
-            nj[cf] = rec;
-          }
+          if (cf < kf) nj[(int64_t)cf * WAVE] = jb + (uint32_t)e;
           ++cf;
         }
         __builtin_amdgcn_wave_barrier();
@@ -756,14 +787,7 @@ __global__ __launch_bounds__(BLOCK) void k_build(const SlotDesc* table, LaunchTa
           const double qq = sqrt((double)d2) * inv_h;
           const double tt = 1.0 - 0.5 * qq;
           sw += kW * tt * tt * tt * tt * (1.0 + 2.0 * qq);
-          if (cs < ks) {
-            Real4 rec;
-            rec.x = (Real)ddx;
-            rec.y = (Real)ddy;
-            rec.z = (Real)ddz;
-            rec.w = pack_index(wb + (uint32_t)e, (Real)0);
-            sj[cs] = rec;
-          }
+          if (cs < ks) sj[(int64_t)cs * WAVE] = wb + (uint32_t)e;
           ++cs;
         }
         __builtin_amdgcn_wave_barrier();
@@ -842,11 +866,9 @@ __global__ __launch_bounds__(BLOCK) void k_dt(const SlotDesc* table, LaunchTab t
 
 // ---------------------------------------------------------------------------
 // K: viscous acceleration (eq. 10 fluid-fluid, eq. 18 fluid-wall) and heat
-// conduction rate (eq. 22), both frozen for the advection step.  As the first
-// sweep over fresh rows it moves the build's staged records (r_ij, j) into the
-// SELL rows.  Per-block partials: viscous force and torque on each body and
-// its heat flow into the fluid.  Also clears this block's pressure-force
-// accumulators.
+// conduction rate (eq. 22), both frozen for the advection step.  Per-block
+// partials: viscous force and torque on each body and its heat flow into the
+// fluid.  Also clears this block's pressure-force accumulators.
 // ---------------------------------------------------------------------------
 template <class P>
 __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, LaunchTab tab) {
@@ -865,10 +887,12 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
   if (i < nf) {
     const GLB Real4* vr = gpc<Real4>(S.vr);
     const GLB Temp* T = gpc<Temp>(S.T);
-    const GLB Real4* RS = gpc<Real4>(S.rstage) + (int64_t)i * (S.kf + S.ks);
+    const GLB Real4* xo = gpc<Real4>(S.xo);
     const Real m = (Real)S.mass;
-    const Real inv_h = (Real)(1.0 / S.h), kF = (Real)S.kF;
+    const Real inv_h = (Real)(1.0 / S.h), kF = (Real)S.kF, csr = (Real)S.cs_r;
     const Real4 vi = vr[i];
+    const Real4 oi = xo[i];
+    const uint32_t ci = unpack_index(oi.w);
     const Real rhoi = rho_abs<P>(S, vi.w);
     const Temp Ti = T[i];
     const Real c2 = (Real)(2.0 * S.eta) * rcp(rhoi);   // 2 eta V_i / m_i
@@ -878,29 +902,27 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
     const int64_t slice = i >> 6;
     {
       const int n = (int)S.nfc[i];
-      GLB Real4* R = gp<Real4>(S.nrec) + slice * (int64_t)S.kf * WAVE + lane;
+      const GLB uint32_t* R = gpc<uint32_t>(S.nrec) + slice * (int64_t)S.kf * WAVE + lane;
       for (int k = 0; k < n; k += ROW_UNROLL) {
-        Real4 g[ROW_UNROLL];
         uint32_t j[ROW_UNROLL];
 #pragma unroll
         for (int u = 0; u < ROW_UNROLL; ++u) {
-          const Real4 gr = RS[k + u];
-          const bool ok = k + u < n;
-          g[u] = ok ? gr : Real4(0);
-          j[u] = ok ? unpack_index(gr.w) : (uint32_t)i;
+          const uint32_t jr = ldnt(R + (int64_t)(k + u) * WAVE);
+          j[u] = k + u < n ? jr : (uint32_t)i;
         }
-        Real4 vj[ROW_UNROLL];
+        Real4 vj[ROW_UNROLL], oj[ROW_UNROLL];
         Temp Tj[ROW_UNROLL];
 #pragma unroll
         for (int u = 0; u < ROW_UNROLL; ++u) {
+          oj[u] = xo[j[u]];
           vj[u] = vr[j[u]];
           Tj[u] = T[j[u]];
         }
 #pragma unroll
         for (int u = 0; u < ROW_UNROLL; ++u) {
-          if (k + u >= n) continue;
-          R[(int64_t)(k + u) * WAVE] = g[u];
-          const Real Fk = kernel_F(g[u].x * g[u].x + g[u].y * g[u].y + g[u].z * g[u].z, inv_h, kF);
+          Real rx, ry, rz;
+          pair_vec(oi, ci, oj[u], csr, rx, ry, rz);
+          const Real Fk = k + u < n ? kernel_F(rx * rx + ry * ry + rz * rz, inv_h, kF) : (Real)0;
           const Real Vj = m * rcp(rho_abs<P>(S, vj[u].w));
           const Real cv = c2 * Vj * Fk;
           ax += cv * (vi.x - vj[u].x);
@@ -913,18 +935,20 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
     {
       const int n = (int)S.nsc[i];
       wall = n > 0;
-      GLB Real4* R = gp<Real4>(S.srec) + slice * (int64_t)S.ks * WAVE + lane;
+      const GLB uint32_t* R = gpc<uint32_t>(S.srec) + slice * (int64_t)S.ks * WAVE + lane;
+      const GLB Real4* so = gpc<Real4>(S.so);
       const GLB Real4* vw = gpc<Real4>(S.vw);
       const GLB Real4* lv = gpc<Real4>(S.lev);
       const Real Vw = (Real)S.vol_w;
       const Real rc = rcp(rhoi * (Real)S.cp_f);
       for (int k = 0; k < n; ++k) {
-        const Real4 g = RS[S.kf + k];
-        const uint32_t w = unpack_index(g.w);
+        const uint32_t w = ldnt(R + (int64_t)k * WAVE);
+        const Real4 ow = so[w];
         const Real4 vq = vw[w];
         const Real4 lq = lv[w];
-        R[(int64_t)k * WAVE] = g;
-        const Real Fk = kernel_F(g.x * g.x + g.y * g.y + g.z * g.z, inv_h, kF);
+        Real rx, ry, rz;
+        pair_vec(oi, ci, ow, csr, rx, ry, rz);
+        const Real Fk = kernel_F(rx * rx + ry * ry + rz * rz, inv_h, kF);
         const int b = (int)lq.w;
         const Real cv = c2 * Vw * Fk;
         const Real fx = cv * (vi.x - vq.x), fy = cv * (vi.y - vq.y), fz = cv * (vi.z - vq.z);
@@ -999,73 +1023,78 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(const SlotDesc* table, Launc
   bool wall = false;
   if (i < nf) {
     const GLB Real4* vr = gpc<Real4>(S.vr);
+    const GLB Real4* xo = gpc<Real4>(S.xo);
     const Real c0 = (Real)S.c0;
     const Real m = (Real)S.mass;
     const Real4 vi = vr[i];
+    const Real4 oi = xo[i];
+    const uint32_t ci = unpack_index(oi.w);
     const Real rhoi = rho_abs<P>(S, vi.w);
     const Real pi = press<P>(S, vi.w);
     const Real c2 = (Real)2 * rcp(rhoi);   // 2 V_i / m_i
+    const Real inv_h = (Real)(1.0 / S.h), kF = (Real)S.kF, csr = (Real)S.cs_r;
     Real ax = 0, ay = 0, az = 0;
     const int lane = i & (WAVE - 1);
     const int64_t slice = i >> 6;
     {
       const int n = (int)S.nfc[i];
-      const int64_t base = slice * (int64_t)S.kf * WAVE + lane;
-      const GLB Real4* R = gpc<Real4>(S.nrec) + base;
-      const Real inv_h = (Real)(1.0 / S.h), kF = (Real)S.kF;
+      const GLB uint32_t* R = gpc<uint32_t>(S.nrec) + slice * (int64_t)S.kf * WAVE + lane;
       for (int k = 0; k < n; k += ROW_UNROLL) {
         uint32_t j[ROW_UNROLL];
-        Real4 g[ROW_UNROLL];
 #pragma unroll
         for (int u = 0; u < ROW_UNROLL; ++u) {
-          const Real4 gr = ldnt(R + (int64_t)(k + u) * WAVE);
-          const bool ok = k + u < n;
-          j[u] = ok ? unpack_index(gr.w) : (uint32_t)i;
-          g[u] = ok ? gr : Real4(0);
+          const uint32_t jr = ldnt(R + (int64_t)(k + u) * WAVE);
+          j[u] = k + u < n ? jr : (uint32_t)i;
         }
-        Real4 vj[ROW_UNROLL];
-#pragma unroll
-        for (int u = 0; u < ROW_UNROLL; ++u) vj[u] = vr[j[u]];
+        Real4 vj[ROW_UNROLL], oj[ROW_UNROLL];
 #pragma unroll
         for (int u = 0; u < ROW_UNROLL; ++u) {
-          const Real r2 = g[u].x * g[u].x + g[u].y * g[u].y + g[u].z * g[u].z;
+          oj[u] = xo[j[u]];
+          vj[u] = vr[j[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < ROW_UNROLL; ++u) {
+          Real rx, ry, rz;
+          pair_vec(oi, ci, oj[u], csr, rx, ry, rz);
+          const Real r2 = rx * rx + ry * ry + rz * rz;
           const Real inv = r2 > (Real)0 ? rsq(r2) : (Real)0;
           const Real Fk = k + u < n ? kernel_F(r2, inv_h, kF) : (Real)0;
           const Real rhoj = rho_abs<P>(S, vj[u].w);
           const Real pj = press<P>(S, vj[u].w);
           // U_L - U_R = -(v_i - v_j) . e_ij
-          const Real dU = -((vi.x - vj[u].x) * g[u].x + (vi.y - vj[u].y) * g[u].y + (vi.z - vj[u].z) * g[u].z) * inv;
+          const Real dU = -((vi.x - vj[u].x) * rx + (vi.y - vj[u].y) * ry + (vi.z - vj[u].z) * rz) * inv;
           const Real beta = fmin((Real)3 * fmax(dU, (Real)0), c0);
           const Real ps = (Real)0.5 * (pi + pj) + rhoi * rhoj * beta * dU * rcp(rhoi + rhoj);
           const Real s = -c2 * (m * rcp(rhoj)) * ps * Fk;
-          ax += s * g[u].x;
-          ay += s * g[u].y;
-          az += s * g[u].z;
+          ax += s * rx;
+          ay += s * ry;
+          az += s * rz;
         }
       }
     }
     {
       const int n = (int)S.nsc[i];
       wall = n > 0;
-      const int64_t base = slice * (int64_t)S.ks * WAVE + lane;
-      const GLB Real4* R = gpc<Real4>(S.srec) + base;
+      const GLB uint32_t* R = gpc<uint32_t>(S.srec) + slice * (int64_t)S.ks * WAVE + lane;
+      const GLB Real4* so = gpc<Real4>(S.so);
       const GLB Real4* lv = gpc<Real4>(S.lev);
-      const Real inv_h = (Real)(1.0 / S.h), kF = (Real)S.kF;
       const Real gx = (Real)S.g[0], gy = (Real)S.g[1], gz = (Real)S.g[2];
       const Real rho0 = (Real)S.rho0;
       const Real ic02 = (Real)(1.0 / (S.c0 * S.c0));
       const Real Vw = (Real)S.vol_w;
       for (int k = 0; k < n; ++k) {
-        const Real4 g = ldnt(R + (int64_t)k * WAVE);
-        const uint32_t w = unpack_index(g.w);
-        const Real Fk = kernel_F(g.x * g.x + g.y * g.y + g.z * g.z, inv_h, kF);
+        const uint32_t w = ldnt(R + (int64_t)k * WAVE);
+        const Real4 ow = so[w];
         const Real4 lq = lv[w];
+        Real rx, ry, rz;
+        pair_vec(oi, ci, ow, csr, rx, ry, rz);
+        const Real Fk = kernel_F(rx * rx + ry * ry + rz * rz, inv_h, kF);
         // right state of eq. 17: P_R = P_L + rho_f g . (x_w - x_f), rho_R from the EoS
-        const Real PR = pi - rhoi * (gx * g.x + gy * g.y + gz * g.z);
+        const Real PR = pi - rhoi * (gx * rx + gy * ry + gz * rz);
         const Real rhoR = rho0 + PR * ic02;
         const Real ps = (rhoi * PR + rhoR * pi) * rcp(rhoi + rhoR);   // eq. 19
         const Real s = -c2 * Vw * ps * Fk;
-        const Real fx = s * g.x, fy = s * g.y, fz = s * g.z;
+        const Real fx = s * rx, fy = s * ry, fz = s * rz;
         ax += fx;
         ay += fy;
         az += fz;
@@ -1108,41 +1137,45 @@ __global__ __launch_bounds__(BLOCK) void k_continuity(const SlotDesc* table, Lau
   const int i = lb * BLOCK + threadIdx.x;
   if (i >= S.nf) return;
   const GLB Real4* vrn = gpc<Real4>(S.vrn);
+  const GLB Real4* xo = gpc<Real4>(S.xo);
   const Real c0 = (Real)S.c0;
   const Real m = (Real)S.mass;
   const Real4 vi = vrn[i];
+  const Real4 oi = xo[i];
+  const uint32_t ci = unpack_index(oi.w);
   const Real rhoi = rho_abs<P>(S, vi.w);
   const Real pi = press<P>(S, vi.w);
+  const Real inv_h = (Real)(1.0 / S.h), kF = (Real)S.kF, csr = (Real)S.cs_r;
   Real sum = 0;
   const int lane = i & (WAVE - 1);
   const int64_t slice = i >> 6;
   {
     const int n = (int)S.nfc[i];
-    const int64_t base = slice * (int64_t)S.kf * WAVE + lane;
-    const GLB Real4* R = gpc<Real4>(S.nrec) + base;
-    const Real inv_h = (Real)(1.0 / S.h), kF = (Real)S.kF;
+    const GLB uint32_t* R = gpc<uint32_t>(S.nrec) + slice * (int64_t)S.kf * WAVE + lane;
     for (int k = 0; k < n; k += ROW_UNROLL) {
       uint32_t j[ROW_UNROLL];
-      Real4 g[ROW_UNROLL];
 #pragma unroll
       for (int u = 0; u < ROW_UNROLL; ++u) {
-        const Real4 gr = ldnt(R + (int64_t)(k + u) * WAVE);
-        const bool ok = k + u < n;
-        j[u] = ok ? unpack_index(gr.w) : (uint32_t)i;
-        g[u] = ok ? gr : Real4(0);
+        const uint32_t jr = ldnt(R + (int64_t)(k + u) * WAVE);
+        j[u] = k + u < n ? jr : (uint32_t)i;
       }
-      Real4 vj[ROW_UNROLL];
-#pragma unroll
-      for (int u = 0; u < ROW_UNROLL; ++u) vj[u] = vrn[j[u]];
+      Real4 vj[ROW_UNROLL], oj[ROW_UNROLL];
 #pragma unroll
       for (int u = 0; u < ROW_UNROLL; ++u) {
-        const Real r2 = g[u].x * g[u].x + g[u].y * g[u].y + g[u].z * g[u].z;
+        oj[u] = xo[j[u]];
+        vj[u] = vrn[j[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < ROW_UNROLL; ++u) {
+        Real rx, ry, rz;
+        pair_vec(oi, ci, oj[u], csr, rx, ry, rz);
+        const Real r2 = rx * rx + ry * ry + rz * rz;
         const Real rr = r2 > (Real)0 ? r2 * rsq(r2) : (Real)0;
         const Real Fk = k + u < n ? kernel_F(r2, inv_h, kF) : (Real)0;
         const Real rhoj = rho_abs<P>(S, vj[u].w);
         const Real pj = press<P>(S, vj[u].w);
         // (U* - U_L) dW = [ (v_i - v_j) . r / 2 + (p_i - p_j) r / (c0 (rho_i + rho_j)) ] F
-        const Real vr_ = (vi.x - vj[u].x) * g[u].x + (vi.y - vj[u].y) * g[u].y + (vi.z - vj[u].z) * g[u].z;
+        const Real vr_ = (vi.x - vj[u].x) * rx + (vi.y - vj[u].y) * ry + (vi.z - vj[u].z) * rz;
         const Real dv = (Real)0.5 * vr_ + (pi - pj) * rr * rcp(c0 * (rhoi + rhoj));
         sum += (m * rcp(rhoj)) * dv * Fk;
       }
@@ -1150,9 +1183,8 @@ __global__ __launch_bounds__(BLOCK) void k_continuity(const SlotDesc* table, Lau
   }
   {
     const int n = (int)S.nsc[i];
-    const int64_t base = slice * (int64_t)S.ks * WAVE + lane;
-    const GLB Real4* R = gpc<Real4>(S.srec) + base;
-    const Real inv_h = (Real)(1.0 / S.h), kF = (Real)S.kF;
+    const GLB uint32_t* R = gpc<uint32_t>(S.srec) + slice * (int64_t)S.ks * WAVE + lane;
+    const GLB Real4* so = gpc<Real4>(S.so);
     const GLB Real4* nw = gpc<Real4>(S.nw);
     const GLB Real4* vw = gpc<Real4>(S.vw);
     const Real gx = (Real)S.g[0], gy = (Real)S.g[1], gz = (Real)S.g[2];
@@ -1160,17 +1192,19 @@ __global__ __launch_bounds__(BLOCK) void k_continuity(const SlotDesc* table, Lau
     const Real ic02 = (Real)(1.0 / (S.c0 * S.c0));
     const Real Vw = (Real)S.vol_w;
     for (int k = 0; k < n; ++k) {
-      const Real4 g = ldnt(R + (int64_t)k * WAVE);
-      const uint32_t w = unpack_index(g.w);
-      const Real Fk = kernel_F(g.x * g.x + g.y * g.y + g.z * g.z, inv_h, kF);
+      const uint32_t w = ldnt(R + (int64_t)k * WAVE);
+      const Real4 ow = so[w];
       const Real4 nq = nw[w];
       const Real4 vq = vw[w];
-      const Real PR = pi - rhoi * (gx * g.x + gy * g.y + gz * g.z);
+      Real rx, ry, rz;
+      pair_vec(oi, ci, ow, csr, rx, ry, rz);
+      const Real Fk = kernel_F(rx * rx + ry * ry + rz * rz, inv_h, kF);
+      const Real PR = pi - rhoi * (gx * rx + gy * ry + gz * rz);
       const Real rhoR = rho0 + PR * ic02;
       const Real UL = -(nq.x * vi.x + nq.y * vi.y + nq.z * vi.z);
       const Real uw = -(nq.x * vq.x + nq.y * vq.y + nq.z * vq.z);
       const Real Us = uw + (pi - PR) * rcp(c0 * (rhoi + rhoR));
-      sum += Vw * (Us - UL) * (nq.x * g.x + nq.y * g.y + nq.z * g.z) * Fk;
+      sum += Vw * (Us - UL) * (nq.x * rx + nq.y * ry + nq.z * rz) * Fk;
     }
   }
   gp<Real>(S.drho)[i] = (Real)2 * rhoi * sum;

@@ -24,8 +24,8 @@ KERNELS = ["clear", "pose", "fold", "scan1", "scan2", "scan3", "scatter", "cells
            "dt", "visc_heat", "half_a", "momentum", "continuity", "half_b", "end", "final"]
 K = {n: i for i, n in enumerate(KERNELS)}
 
-DUMP = dict(fluid_ids=1, solid_ids=2, fluid_cell=3, nbr_count=4, nbr_fluid=5, nbr_solid=6, geom_fluid=7,
-            geom_solid=8, fluid_state=9, solid_state=10, sumw=11)
+DUMP = dict(fluid_ids=1, solid_ids=2, fluid_cell=3, nbr_count=4, nbr_fluid=5, nbr_solid=6, fluid_offset=7,
+            solid_offset=8, fluid_state=9, solid_state=10, sumw=11)
 
 
 class SphError(RuntimeError):

@@ -130,3 +130,29 @@ def test_full_size_c3_one_step_after_motion(sph, ora):
         ts = np.abs(bo["torque"]).max()
         if ts > 0:
             assert np.max(np.abs(bg["torque"] - bo["torque"])) <= 1e-3 * ts
+
+
+@pytest.mark.timeout(600)
+def test_fp64_mode_tracks_oracle_on_precision_tank(sph, ora):
+    """The FP64 GPU mode, reference of the long precision runs, against the
+    oracle on the precision-stress tank (dp 0.788 mm, about 200 k fluid
+    particles, disk at 450 rad/s): 40 steps, each side on its own time steps;
+    n_ac identical every step, normalised state errors <= 1e-9 at the end."""
+    c = cases.tank_c1(dp=0.788e-3, omega=450.0)
+    say("fp64 vs oracle, precision tank", c.nf, c.ns)
+    o = ora.State(c)
+    s = sph.Solver(c, precision="fp64")
+    for k in range(40):
+        ro = o.step()
+        s.step(1)
+        rg = s.reduce()
+        assert rg["n_ac"] == ro["n_ac"], k
+    g = s.get_fluid()
+    s.close()
+    umax, c0, rho0 = c.meta["umax"], c.params["c0"], c.params["rho0"]
+    e = dict(x=np.max(np.abs(g["x"] - o.x)) / c.params["dp"], v=np.max(np.abs(g["v"] - o.v)) / umax,
+             rho=np.max(np.abs(g["rho"] - o.rho)) / (rho0 * (umax / c0) ** 2),
+             T=np.max(np.abs(g["T"] - o.T)) / 20.0)
+    say("fp64 vs oracle after 40 steps", e)
+    assert max(e.values()) <= 1e-9, e
+    assert rg["t"] == pytest.approx(ro["t"], rel=1e-13)
