@@ -13,6 +13,8 @@
 // the only atomics are integer counters of the cell sort and fault flags.
 #include <math.h>
 
+#include <type_traits>
+
 #include "sph_internal.h"
 
 namespace sphk {
@@ -622,6 +624,66 @@ __global__ __launch_bounds__(BLOCK) void k_reorder(const SlotDesc* table, Launch
 // or stores per candidate; each hit then adds its kernel weight and writes its
 // index.
 // ---------------------------------------------------------------------------
+// Hit mask of this lane against the wave's staged candidates [0, m4): bit e
+// is set when d^2 = (dx dx + dy dy) + dz dz < (2h)^2, FP64, no contraction.
+// m4 is the candidate count rounded up to four; the padding slots hold a far
+// sentinel that never hits.
+template <class Pos, class Pos4>
+__device__ __forceinline__ uint64_t test_staged(const Pos4* stage, int m4, Pos xi, Pos yi, Pos zi, double cut2) {
+#pragma clang fp contract(off)
+  uint64_t hits = 0;
+  for (int e0 = 0; e0 < m4; e0 += 4) {
+    uint32_t b = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const Pos4 xj = stage[e0 + u];
+      const Pos ddx = xi - xj.x, ddy = yi - xj.y, ddz = zi - xj.z;
+      const Pos s2 = ddx * ddx + ddy * ddy;
+      const Pos d2 = s2 + ddz * ddz;
+      b |= ((double)d2 < cut2 ? 1u : 0u) << u;
+    }
+    hits |= (uint64_t)b << e0;
+  }
+  return hits;
+}
+
+// Wendland C2 weight W = kW (1 - q/2)^4 (1 + 2q), q = |r|/h, from d^2 in FP64.
+// |r| comes from the hardware reciprocal square root refined by coupled
+// Newton steps for sqrt(x) and 1/(2 sqrt(x)) (Goldschmidt's iteration) and a
+// final residual correction, which leaves an error of about one ulp.
+__device__ __forceinline__ double kernel_W_d2(double d2, double inv_h, double kW) {
+  const double x = d2 > 0.0 ? d2 : 1.0;
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, hh = 0.5 * y;
+  const double e = fma(-hh, g, 0.5);
+  g = fma(g, e, g);
+  hh = fma(hh, e, hh);
+  const double res = fma(-g, g, x);
+  g = fma(res, hh, g);
+  const double q = (d2 > 0.0 ? g : 0.0) * inv_h;
+  const double t = 1.0 - 0.5 * q;
+  return kW * t * t * t * t * (1.0 + 2.0 * q);
+}
+
+// Stage up to 64 candidates of a cell into the wave's LDS slots (one
+// coalesced load), padding to a multiple of four with a far sentinel.
+template <class Pos4>
+__device__ __forceinline__ int stage_candidates(Pos4* stage, const GLB Pos4* src, uint32_t base, int m, int lane) {
+  const int m4 = (m + 3) & ~3;
+  if (lane < m) {
+    stage[lane] = src[base + lane];
+  } else if (lane < m4) {
+    Pos4 far;
+    far.x = far.y = far.z = (typename std::remove_reference<decltype(far.x)>::type)1e30;
+    far.w = far.x;
+    stage[lane] = far;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  return m4;
+}
+
 __device__ __forceinline__ int wave_min_i(int v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, WAVE));
@@ -730,19 +792,10 @@ __global__ __launch_bounds__(BLOCK) void k_build(const SlotDesc* table, LaunchTa
       const uint32_t a0 = rl_u(f0, t), a1 = rl_u(f1, t);
       for (uint32_t jb = a0; jb < a1; jb += WAVE) {
         const int m = (int)min((uint32_t)WAVE, a1 - jb);
-        if (lane < m) stage[lane] = xa[jb + lane];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int m4 = stage_candidates(stage, xa, jb, m, lane);
         uint64_t hits = 0;
         if (need) {
-          for (int e = 0; e < m; ++e) {
-            const Pos4 xj = stage[e];
-            const Pos ddx = xi - xj.x, ddy = yi - xj.y, ddz = zi - xj.z;
-            const Pos s2 = ddx * ddx + ddy * ddy;
-            const Pos d2 = s2 + ddz * ddz;
-            hits |= (uint64_t)((double)d2 < cut2) << e;
-          }
+          hits = test_staged<Pos>(stage, m4, xi, yi, zi, cut2);
           if ((uint32_t)i - jb < (uint32_t)m) hits &= ~(1ull << ((uint32_t)i - jb));
         }
         while (hits) {
@@ -752,9 +805,7 @@ __global__ __launch_bounds__(BLOCK) void k_build(const SlotDesc* table, LaunchTa
           const Pos ddx = xi - xq.x, ddy = yi - xq.y, ddz = zi - xq.z;
           const Pos s2 = ddx * ddx + ddy * ddy;
           const Pos d2 = s2 + ddz * ddz;
-          const double qq = sqrt((double)d2) * inv_h;
-          const double tt = 1.0 - 0.5 * qq;
-          sw += kW * tt * tt * tt * tt * (1.0 + 2.0 * qq);
+          sw += kernel_W_d2((double)d2, inv_h, kW);
           if (cf < kf) nj[(int64_t)cf * WAVE] = jb + (uint32_t)e;
           ++cf;
         }
@@ -763,20 +814,9 @@ __global__ __launch_bounds__(BLOCK) void k_build(const SlotDesc* table, LaunchTa
       const uint32_t b0 = rl_u(s0, t), b1 = rl_u(s1, t);
       for (uint32_t wb = b0; wb < b1; wb += WAVE) {
         const int m = (int)min((uint32_t)WAVE, b1 - wb);
-        if (lane < m) stage[lane] = xw[wb + lane];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int m4 = stage_candidates(stage, xw, wb, m, lane);
         uint64_t hits = 0;
-        if (need) {
-          for (int e = 0; e < m; ++e) {
-            const Pos4 xq = stage[e];
-            const Pos ddx = xi - xq.x, ddy = yi - xq.y, ddz = zi - xq.z;
-            const Pos s2 = ddx * ddx + ddy * ddy;
-            const Pos d2 = s2 + ddz * ddz;
-            hits |= (uint64_t)((double)d2 < cut2) << e;
-          }
-        }
+        if (need) hits = test_staged<Pos>(stage, m4, xi, yi, zi, cut2);
         while (hits) {
           const int e = __builtin_ctzll(hits);
           hits &= hits - 1;
@@ -784,9 +824,7 @@ __global__ __launch_bounds__(BLOCK) void k_build(const SlotDesc* table, LaunchTa
           const Pos ddx = xi - xq.x, ddy = yi - xq.y, ddz = zi - xq.z;
           const Pos s2 = ddx * ddx + ddy * ddy;
           const Pos d2 = s2 + ddz * ddz;
-          const double qq = sqrt((double)d2) * inv_h;
-          const double tt = 1.0 - 0.5 * qq;
-          sw += kW * tt * tt * tt * tt * (1.0 + 2.0 * qq);
+          sw += kernel_W_d2((double)d2, inv_h, kW);
           if (cs < ks) sj[(int64_t)cs * WAVE] = wb + (uint32_t)e;
           ++cs;
         }
@@ -858,11 +896,15 @@ __global__ __launch_bounds__(BLOCK) void k_dt(const SlotDesc* table, LaunchTab t
   C->n_ac = nac;
 }
 
-// Rows are walked four entries at a time; entries past a row's count are
-// loaded from the row's capacity (always in bounds, capacities are multiples
-// of four) and replaced by a null entry: own index, r = 0, F = 0, which adds
-// exactly zero to every sum.
-#define ROW_UNROLL 4
+// Rows are walked ROW_UNROLL entries at a time (SOLID_UNROLL for the wall
+// rows), and the next group's indices are loaded before the current group's
+// gathers are consumed, so a wavefront keeps two dependent loads in flight.
+// Entries past a row's count are loaded from the row's capacity (always in
+// bounds: capacities are multiples of eight, and a group beyond the first is
+// loaded only when it starts below the count) and replaced by a null entry:
+// own index, F = 0, which adds exactly zero to every sum.
+#define ROW_UNROLL 8
+#define SOLID_UNROLL 4
 
 // ---------------------------------------------------------------------------
 // K: viscous acceleration (eq. 10 fluid-fluid, eq. 18 fluid-wall) and heat
@@ -903,13 +945,13 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
     {
       const int n = (int)S.nfc[i];
       const GLB uint32_t* R = gpc<uint32_t>(S.nrec) + slice * (int64_t)S.kf * WAVE + lane;
+      uint32_t jn[ROW_UNROLL];
+#pragma unroll
+      for (int u = 0; u < ROW_UNROLL; ++u) jn[u] = ldnt(R + (int64_t)u * WAVE);
       for (int k = 0; k < n; k += ROW_UNROLL) {
         uint32_t j[ROW_UNROLL];
 #pragma unroll
-        for (int u = 0; u < ROW_UNROLL; ++u) {
-          const uint32_t jr = ldnt(R + (int64_t)(k + u) * WAVE);
-          j[u] = k + u < n ? jr : (uint32_t)i;
-        }
+        for (int u = 0; u < ROW_UNROLL; ++u) j[u] = k + u < n ? jn[u] : (uint32_t)i;
         Real4 vj[ROW_UNROLL], oj[ROW_UNROLL];
         Temp Tj[ROW_UNROLL];
 #pragma unroll
@@ -917,6 +959,10 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
           oj[u] = xo[j[u]];
           vj[u] = vr[j[u]];
           Tj[u] = T[j[u]];
+        }
+        if (k + ROW_UNROLL < n) {
+#pragma unroll
+          for (int u = 0; u < ROW_UNROLL; ++u) jn[u] = ldnt(R + (int64_t)(k + ROW_UNROLL + u) * WAVE);
         }
 #pragma unroll
         for (int u = 0; u < ROW_UNROLL; ++u) {
@@ -941,11 +987,26 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
       const GLB Real4* lv = gpc<Real4>(S.lev);
       const Real Vw = (Real)S.vol_w;
       const Real rc = rcp(rhoi * (Real)S.cp_f);
-      for (int k = 0; k < n; ++k) {
-        const uint32_t w = ldnt(R + (int64_t)k * WAVE);
-        const Real4 ow = so[w];
-        const Real4 vq = vw[w];
-        const Real4 lq = lv[w];
+      uint32_t wn[SOLID_UNROLL];
+#pragma unroll
+      for (int u = 0; u < SOLID_UNROLL; ++u) wn[u] = ldnt(R + (int64_t)u * WAVE);
+      for (int k0 = 0; k0 < n; k0 += SOLID_UNROLL) {
+        Real4 owu[SOLID_UNROLL], vqu[SOLID_UNROLL], lqu[SOLID_UNROLL];
+#pragma unroll
+        for (int u = 0; u < SOLID_UNROLL; ++u) {
+          const uint32_t w = k0 + u < n ? wn[u] : 0u;
+          owu[u] = so[w];
+          vqu[u] = vw[w];
+          lqu[u] = lv[w];
+        }
+        if (k0 + SOLID_UNROLL < n) {
+#pragma unroll
+          for (int u = 0; u < SOLID_UNROLL; ++u) wn[u] = ldnt(R + (int64_t)(k0 + SOLID_UNROLL + u) * WAVE);
+        }
+#pragma unroll
+        for (int u = 0; u < SOLID_UNROLL; ++u) {
+        if (k0 + u >= n) break;
+        const Real4 ow = owu[u], vq = vqu[u], lq = lqu[u];
         Real rx, ry, rz;
         pair_vec(oi, ci, ow, csr, rx, ry, rz);
         const Real Fk = kernel_F(rx * rx + ry * ry + rz * rz, inv_h, kF);
@@ -964,6 +1025,7 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
         const double contrib[7] = {gx, gy, gz, ly * gz - lz * gy, lz * gx - lx * gz, lx * gy - ly * gx,
                                    (double)m * (double)S.cp_f * (double)(rc * term)};
         if (!acc.add(b, contrib)) raise_flag(S, F_CAPACITY);
+        }
       }
       Real4 a;
       a.x = ax;
@@ -1039,18 +1101,22 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(const SlotDesc* table, Launc
     {
       const int n = (int)S.nfc[i];
       const GLB uint32_t* R = gpc<uint32_t>(S.nrec) + slice * (int64_t)S.kf * WAVE + lane;
+      uint32_t jn[ROW_UNROLL];
+#pragma unroll
+      for (int u = 0; u < ROW_UNROLL; ++u) jn[u] = ldnt(R + (int64_t)u * WAVE);
       for (int k = 0; k < n; k += ROW_UNROLL) {
         uint32_t j[ROW_UNROLL];
 #pragma unroll
-        for (int u = 0; u < ROW_UNROLL; ++u) {
-          const uint32_t jr = ldnt(R + (int64_t)(k + u) * WAVE);
-          j[u] = k + u < n ? jr : (uint32_t)i;
-        }
+        for (int u = 0; u < ROW_UNROLL; ++u) j[u] = k + u < n ? jn[u] : (uint32_t)i;
         Real4 vj[ROW_UNROLL], oj[ROW_UNROLL];
 #pragma unroll
         for (int u = 0; u < ROW_UNROLL; ++u) {
           oj[u] = xo[j[u]];
           vj[u] = vr[j[u]];
+        }
+        if (k + ROW_UNROLL < n) {
+#pragma unroll
+          for (int u = 0; u < ROW_UNROLL; ++u) jn[u] = ldnt(R + (int64_t)(k + ROW_UNROLL + u) * WAVE);
         }
 #pragma unroll
         for (int u = 0; u < ROW_UNROLL; ++u) {
@@ -1082,10 +1148,25 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(const SlotDesc* table, Launc
       const Real rho0 = (Real)S.rho0;
       const Real ic02 = (Real)(1.0 / (S.c0 * S.c0));
       const Real Vw = (Real)S.vol_w;
-      for (int k = 0; k < n; ++k) {
-        const uint32_t w = ldnt(R + (int64_t)k * WAVE);
-        const Real4 ow = so[w];
-        const Real4 lq = lv[w];
+      uint32_t wn[SOLID_UNROLL];
+#pragma unroll
+      for (int u = 0; u < SOLID_UNROLL; ++u) wn[u] = ldnt(R + (int64_t)u * WAVE);
+      for (int k0 = 0; k0 < n; k0 += SOLID_UNROLL) {
+        Real4 owu[SOLID_UNROLL], lqu[SOLID_UNROLL];
+#pragma unroll
+        for (int u = 0; u < SOLID_UNROLL; ++u) {
+          const uint32_t w = k0 + u < n ? wn[u] : 0u;
+          owu[u] = so[w];
+          lqu[u] = lv[w];
+        }
+        if (k0 + SOLID_UNROLL < n) {
+#pragma unroll
+          for (int u = 0; u < SOLID_UNROLL; ++u) wn[u] = ldnt(R + (int64_t)(k0 + SOLID_UNROLL + u) * WAVE);
+        }
+#pragma unroll
+        for (int u = 0; u < SOLID_UNROLL; ++u) {
+        if (k0 + u >= n) break;
+        const Real4 ow = owu[u], lq = lqu[u];
         Real rx, ry, rz;
         pair_vec(oi, ci, ow, csr, rx, ry, rz);
         const Real Fk = kernel_F(rx * rx + ry * ry + rz * rz, inv_h, kF);
@@ -1102,6 +1183,7 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(const SlotDesc* table, Launc
         const double lx = lq.x, ly = lq.y, lz = lq.z;
         const double contrib[6] = {hx, hy, hz, ly * hz - lz * hy, lz * hx - lx * hz, lx * hy - ly * hx};
         if (!acc.add((int)lq.w, contrib)) raise_flag(S, F_CAPACITY);
+        }
       }
     }
     const Real dt = (Real)S.ctl->dt;
@@ -1152,18 +1234,22 @@ __global__ __launch_bounds__(BLOCK) void k_continuity(const SlotDesc* table, Lau
   {
     const int n = (int)S.nfc[i];
     const GLB uint32_t* R = gpc<uint32_t>(S.nrec) + slice * (int64_t)S.kf * WAVE + lane;
+    uint32_t jn[ROW_UNROLL];
+#pragma unroll
+    for (int u = 0; u < ROW_UNROLL; ++u) jn[u] = ldnt(R + (int64_t)u * WAVE);
     for (int k = 0; k < n; k += ROW_UNROLL) {
       uint32_t j[ROW_UNROLL];
 #pragma unroll
-      for (int u = 0; u < ROW_UNROLL; ++u) {
-        const uint32_t jr = ldnt(R + (int64_t)(k + u) * WAVE);
-        j[u] = k + u < n ? jr : (uint32_t)i;
-      }
+      for (int u = 0; u < ROW_UNROLL; ++u) j[u] = k + u < n ? jn[u] : (uint32_t)i;
       Real4 vj[ROW_UNROLL], oj[ROW_UNROLL];
 #pragma unroll
       for (int u = 0; u < ROW_UNROLL; ++u) {
         oj[u] = xo[j[u]];
         vj[u] = vrn[j[u]];
+      }
+      if (k + ROW_UNROLL < n) {
+#pragma unroll
+        for (int u = 0; u < ROW_UNROLL; ++u) jn[u] = ldnt(R + (int64_t)(k + ROW_UNROLL + u) * WAVE);
       }
 #pragma unroll
       for (int u = 0; u < ROW_UNROLL; ++u) {
@@ -1191,11 +1277,26 @@ __global__ __launch_bounds__(BLOCK) void k_continuity(const SlotDesc* table, Lau
     const Real rho0 = (Real)S.rho0;
     const Real ic02 = (Real)(1.0 / (S.c0 * S.c0));
     const Real Vw = (Real)S.vol_w;
-    for (int k = 0; k < n; ++k) {
-      const uint32_t w = ldnt(R + (int64_t)k * WAVE);
-      const Real4 ow = so[w];
-      const Real4 nq = nw[w];
-      const Real4 vq = vw[w];
+    uint32_t wn[SOLID_UNROLL];
+#pragma unroll
+    for (int u = 0; u < SOLID_UNROLL; ++u) wn[u] = ldnt(R + (int64_t)u * WAVE);
+    for (int k0 = 0; k0 < n; k0 += SOLID_UNROLL) {
+      Real4 owu[SOLID_UNROLL], nqu[SOLID_UNROLL], vqu[SOLID_UNROLL];
+#pragma unroll
+      for (int u = 0; u < SOLID_UNROLL; ++u) {
+        const uint32_t w = k0 + u < n ? wn[u] : 0u;
+        owu[u] = so[w];
+        nqu[u] = nw[w];
+        vqu[u] = vw[w];
+      }
+      if (k0 + SOLID_UNROLL < n) {
+#pragma unroll
+        for (int u = 0; u < SOLID_UNROLL; ++u) wn[u] = ldnt(R + (int64_t)(k0 + SOLID_UNROLL + u) * WAVE);
+      }
+#pragma unroll
+      for (int u = 0; u < SOLID_UNROLL; ++u) {
+      if (k0 + u >= n) break;
+      const Real4 ow = owu[u], nq = nqu[u], vq = vqu[u];
       Real rx, ry, rz;
       pair_vec(oi, ci, ow, csr, rx, ry, rz);
       const Real Fk = kernel_F(rx * rx + ry * ry + rz * rz, inv_h, kF);
@@ -1205,6 +1306,7 @@ __global__ __launch_bounds__(BLOCK) void k_continuity(const SlotDesc* table, Lau
       const Real uw = -(nq.x * vq.x + nq.y * vq.y + nq.z * vq.z);
       const Real Us = uw + (pi - PR) * rcp(c0 * (rhoi + rhoR));
       sum += Vw * (Us - UL) * (nq.x * rx + nq.y * ry + nq.z * rz) * Fk;
+      }
     }
   }
   gp<Real>(S.drho)[i] = (Real)2 * rhoi * sum;
