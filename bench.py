@@ -17,6 +17,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -203,62 +204,70 @@ def serve_bench(args):
 def precision_study(args):
     """All-FP32 vs mixed FP32/FP64 vs FP64 on the churning tank (C1 geometry).
 
-    Each mode runs the same advection steps from the same state; the FP64
-    GPU run is the reference.  Reported per mode: relative drift of the
-    mass proxy sum(rho dp^3), heat-balance residual (thermal energy change
-    minus the integrated heat inflow, relative to the inflow), mean oil
-    temperature rise, time-mean disk torque and the field differences to
-    the reference.
+    Each mode runs the same advection steps (its own adaptive time steps)
+    from the same state; the FP64 GPU run is the reference.  At checkpoints
+    every `ps_ckpt` steps each mode reports: simulated time, drift of the
+    mass proxy sum(rho dp^3) against the exact mass, the heat-balance
+    residual (thermal energy change minus the integrated heat inflow, over
+    the inflow), the mean oil temperature rise and the time-mean disk torque;
+    the comparison with FP64 is made at equal step counts.  A mode that
+    faults (a particle leaving the grid, a non-finite value) stops there.
     """
     from paper_2512_09904_amd import cases, sph
     c = cases.tank_c1(dp=args.ps_dp, omega=450.0)
     log(f"precision study: nf={c.nf} ns={c.ns} steps={args.ps_steps}")
     m = c.params["rho0"] * c.params["dp"] ** 3
     cp = c.params["cp_f"]
+    E0 = math.fsum(m * cp * c.Tf)
     out = {}
     final = {}
     for mode in ("fp64", "mixed", "fp32"):
         s = sph.Solver(c, precision=mode)
-        r0 = None
-        tq = 0.0
         t0 = time.perf_counter()
-        chunk = 100
         done = 0
+        series = []
+        fault = None
         while done < args.ps_steps:
-            n = min(chunk, args.ps_steps - done)
+            n = min(args.ps_ckpt, args.ps_steps - done)
             s.step(n)
             r = s.reduce(raise_on_fault=False)
             if r["rc"]:
+                fault = {"rc": r["rc"], "step": int(r["step"])}
                 log(f"{mode}: fault {r['rc']} at step {r['step']}")
                 break
-            r0 = r0 or r
             done += n
-            if done % 5000 == 0:
-                log(f"{mode}: {done} steps, t={r['t']:.4f} s, vmax={r['vmax']:.2f}")
+            dE = r["thermal"] - E0
+            series.append({"step": done, "t": r["t"], "mass_proxy_drift": r["mass_proxy"] / r["mass"] - 1.0,
+                           "heat_balance_residual": (dE - r["heat_total"]) / abs(r["heat_total"]),
+                           "mean_T_rise_K": dE / (m * cp * c.nf),
+                           "disk_torque_mean_Nm": r["bodies"][1]["torque_axis_int"] / r["t"]})
+            log(f"{mode}: {done} steps, t={r['t']:.4f} s, vmax={r['vmax']:.2f}, "
+                f"heat residual {series[-1]['heat_balance_residual']:.2e}")
         wall = time.perf_counter() - t0
-        g = s.get_fluid()
+        g = s.get_fluid() if fault is None else None
         s.close()
-        dE = float(np.sum(m * cp * (g["T"] - c.Tf)))
-        out[mode] = {"steps": int(r["step"]), "t": r["t"], "wall_s": wall,
-                     "mass_proxy_drift": r["mass_proxy"] / r["mass"] - 1.0,
-                     "heat_in_J": r["heat_total"], "thermal_change_J": dE,
-                     "heat_balance_residual": (dE - r["heat_total"]) / abs(r["heat_total"]),
-                     "mean_T_rise_K": float(np.mean(g["T"] - c.Tf)),
-                     "disk_torque_mean_Nm": r["bodies"][1]["torque_axis_int"] / r["t"],
-                     "disk_heat_mean_W": r["bodies"][1]["heat_int"] / r["t"]}
+        out[mode] = {"steps_done": done, "wall_s": wall, "fault": fault, "series": series}
         final[mode] = g
-        log(f"{mode}: {json.dumps(out[mode])}")
-    ref = final["fp64"]
-    umax = c.meta["umax"]
+        if series:
+            log(f"{mode}: {json.dumps(series[-1])}")
+    ref = {e["step"]: e for e in out["fp64"]["series"]}
     for mode in ("mixed", "fp32"):
-        g = final[mode]
-        out[mode]["vs_fp64"] = {
-            "v_rms_over_umax": float(np.sqrt(np.mean(np.sum((g["v"] - ref["v"]) ** 2, axis=1))) / umax),
-            "rho_rms_over_rho0": float(np.sqrt(np.mean((g["rho"] - ref["rho"]) ** 2)) / c.params["rho0"]),
-            "T_rise_rel": (out[mode]["mean_T_rise_K"] - out["fp64"]["mean_T_rise_K"]) /
-                          abs(out["fp64"]["mean_T_rise_K"]),
-            "torque_rel": (out[mode]["disk_torque_mean_Nm"] - out["fp64"]["disk_torque_mean_Nm"]) /
-                          abs(out["fp64"]["disk_torque_mean_Nm"])}
+        cmp = []
+        for e in out[mode]["series"]:
+            f = ref.get(e["step"])
+            if f is None:
+                continue
+            cmp.append({"step": e["step"], "t_rel": e["t"] / f["t"] - 1.0,
+                        "T_rise_rel": (e["mean_T_rise_K"] - f["mean_T_rise_K"]) / abs(f["mean_T_rise_K"]),
+                        "torque_rel": (e["disk_torque_mean_Nm"] - f["disk_torque_mean_Nm"]) / abs(f["disk_torque_mean_Nm"]),
+                        "mass_proxy_drift_diff": e["mass_proxy_drift"] - f["mass_proxy_drift"]})
+        out[mode]["vs_fp64"] = cmp
+    if final.get("mixed") is not None and final.get("fp64") is not None:
+        umax = c.meta["umax"]
+        g, f = final["mixed"], final["fp64"]
+        out["mixed"]["final_field_rms_vs_fp64"] = {
+            "v_over_umax": float(np.sqrt(np.mean(np.sum((g["v"] - f["v"]) ** 2, axis=1))) / umax),
+            "rho_over_rho0": float(np.sqrt(np.mean((g["rho"] - f["rho"]) ** 2)) / c.params["rho0"])}
     print(json.dumps({"metric": "precision study: drift vs FP64 GPU reference", "config": {
         "workload": f"churning tank dp={args.ps_dp * 1e3:.3f} mm, disk 450 rad/s, {args.ps_steps} steps",
         "n_fluid": c.nf, "n_solid": c.ns}, "modes": out}), flush=True)
@@ -284,8 +293,9 @@ def main():
     ap.add_argument("--serve-seeds", type=int, default=1, help="arrival seeds (64, 65, ...)")
     ap.add_argument("--precision-study", action="store_true",
                     help="churning tank in fp32 / mixed / fp64: drift of the conserved quantities")
-    ap.add_argument("--ps-steps", type=int, default=20000)
+    ap.add_argument("--ps-steps", type=int, default=100000)
     ap.add_argument("--ps-dp", type=float, default=0.788e-3)
+    ap.add_argument("--ps-ckpt", type=int, default=5000, help="steps between precision-study checkpoints")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))

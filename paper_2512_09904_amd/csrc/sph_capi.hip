@@ -143,6 +143,7 @@ static size_t carve(const Plan& P, void* base, SlotDesc* d) {
   C.take(D.sumW, nf * 8);
   C.take(D.fcell, nf * 4);
   C.take(D.fperm, nf * 4);
+  C.take(D.fkey, nf * 8);
   C.takev(D.xa2, 4 * nf * ps);
   C.takev(D.vr2, 4 * nf * rs);
   C.takev(D.drho2, nf * rs);
@@ -172,6 +173,7 @@ static size_t carve(const Plan& P, void* base, SlotDesc* d) {
   C.takev(D.levb, 4 * ns * rs);
   C.take(D.scell, ns * 4);
   C.take(D.sperm, ns * 4);
+  C.take(D.skey, ns * 8);
   C.take(D.rank, nc * 4);
   C.take(D.cnt_f, nc * 4);
   C.take(D.cnt_s, nc * 4);

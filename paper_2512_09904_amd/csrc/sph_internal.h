@@ -66,6 +66,7 @@ struct SlotDesc {
   uint32_t *fid;
   double *sumW;
   uint32_t *fcell, *fperm;
+  uint64_t *fkey;       // scatter output: (original id << 32) | staged index, per sorted slot
   void *xa2, *vr2, *drho2, *T2;
   uint32_t *fid2;
   // neighbour rows (SELL, slice height 64) of sorted neighbour indices, and
@@ -83,6 +84,7 @@ struct SlotDesc {
   uint32_t *sidb;
   void *xwb, *nwb, *vwb, *levb;
   uint32_t *scell, *sperm;
+  uint64_t *skey;
   // cells
   uint32_t *rank, *cnt_f, *cnt_s, *start_f, *start_s, *bsum_f, *bsum_s;
   // per fluid-block partials, quantity-major ([quantity][block])

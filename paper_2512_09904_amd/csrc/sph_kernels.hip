@@ -290,6 +290,27 @@ __device__ __forceinline__ void block_body_reduce(const BodyAcc<W> acc, int nbod
   }
 }
 
+// Counter increments of a wavefront whose lanes mostly share counters in
+// runs (particles in last step's cell order): each run of consecutive active
+// lanes with the same counter index does one atomic add of its length, and
+// its lanes take consecutive values.  Inactive lanes form the wave's tail.
+// Returns this lane's value of the counter before its own increment.
+__device__ __forceinline__ uint32_t run_atomic_inc(uint32_t* cnt, uint32_t r, bool act) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const uint32_t prev = (uint32_t)__shfl_up((int)r, 1, WAVE);
+  const uint64_t heads = __ballot(act && (lane == 0 || prev != r));
+  const int nact = __popcll(__ballot(act));
+  const uint64_t below = lane == WAVE - 1 ? ~0ull : ((2ull << lane) - 1);
+  const uint64_t upto = heads & below;
+  const int h = upto ? 63 - __builtin_clzll(upto) : 0;
+  const uint64_t above = heads & ~below;
+  const int next = above ? __builtin_ctzll(above) : nact;
+  uint32_t old = 0;
+  if (act && h == lane) old = atomicAdd(&cnt[r], (uint32_t)(next - lane));
+  old = (uint32_t)__shfl((int)old, h, WAVE);
+  return old + (uint32_t)(lane - h);
+}
+
 // ---------------------------------------------------------------------------
 // K: clear per-cell counters
 // ---------------------------------------------------------------------------
@@ -317,7 +338,9 @@ __global__ __launch_bounds__(BLOCK) void k_pose(const SlotDesc* table, LaunchTab
   typedef typename P::Real4 Real4;
   SLOT_PROLOGUE(DOM_SOLID);
   const int w = lb * BLOCK + threadIdx.x;
-  if (w >= S.ns) return;
+  const bool act = w < S.ns;
+  uint32_t r = 0;
+  if (act) {
   const int b = S.body[w];
   const double th = S.bom[b] * S.ctl->t;
   double sn, cs;
@@ -362,9 +385,10 @@ __global__ __launch_bounds__(BLOCK) void k_pose(const SlotDesc* table, LaunchTab
   S.sidb[w] = S.sid[w];
   int c[3];
   if (!cell_coords<Pos>(S, xp.x, xp.y, xp.z, c)) raise_flag(S, F_DOMAIN);
-  const uint32_t r = S.rank[cell_linear(S, c[0], c[1], c[2])];
+  r = S.rank[cell_linear(S, c[0], c[1], c[2])];
   S.scell[w] = r;
-  atomicAdd(&S.cnt_s[r], 1u);
+  }
+  run_atomic_inc(S.cnt_s, r, act);
 }
 
 // ---------------------------------------------------------------------------
@@ -382,6 +406,7 @@ __global__ __launch_bounds__(BLOCK) void k_fold(const SlotDesc* table, LaunchTab
   SLOT_PROLOGUE(DOM_FLUID);
   const int i = lb * BLOCK + threadIdx.x;
   float vm = 0.0f;
+  uint32_t r = 0;
   if (i < S.nf) {
     Pos4 x = gpc<Pos4>(S.xa)[i];
     const Real4 d = gpc<Real4>(S.drift)[i];
@@ -404,10 +429,10 @@ __global__ __launch_bounds__(BLOCK) void k_fold(const SlotDesc* table, LaunchTab
     vm = sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
     int c[3];
     if (!cell_coords<Pos>(S, x.x, x.y, x.z, c)) raise_flag(S, F_DOMAIN);
-    const uint32_t r = S.rank[cell_linear(S, c[0], c[1], c[2])];
+    r = S.rank[cell_linear(S, c[0], c[1], c[2])];
     S.fcell[i] = r;
-    atomicAdd(&S.cnt_f[r], 1u);
   }
+  run_atomic_inc(S.cnt_f, r, i < S.nf);
   vm = wave_max(vm);
   if (threadIdx.x % WAVE == 0) red[threadIdx.x / WAVE] = vm;
   __syncthreads();
@@ -510,62 +535,69 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(const SlotDesc* table, Launch
   SLOT_PROLOGUE(which ? DOM_SOLID : DOM_FLUID);
   const int n = which ? S.ns : S.nf;
   const int i = lb * BLOCK + threadIdx.x;
-  if (i >= n) return;
+  const bool act = i < n;
   const uint32_t* cell = which ? S.scell : S.fcell;
   const uint32_t* start = which ? S.start_s : S.start_f;
+  const uint32_t* id = which ? S.sidb : S.fid2;
   uint32_t* cnt = which ? S.cnt_s : S.cnt_f;
-  uint32_t* perm = which ? S.sperm : S.fperm;
-  const uint32_t r = cell[i];
-  const uint32_t pos = start[r] + atomicAdd(&cnt[r], 1u);
-  perm[pos] = (uint32_t)i;
+  uint64_t* key = which ? S.skey : S.fkey;
+  const uint32_t r = act ? cell[i] : 0u;
+  const uint32_t k = run_atomic_inc(cnt, r, act);
+  if (act) key[start[r] + k] = (uint64_t)id[i] << 32 | (uint32_t)i;
 }
 
-// Insertion sort of one cell's run by original id.  Runs of up to RUN_LDS
-// entries are sorted in this thread's LDS slots (keys loaded once, in
-// parallel); longer runs are sorted in place in global memory.
+// Sorts one cell's run of keys (original id << 32 | staged index) and writes
+// the staged indices in id order.  Runs of up to RUN_LDS entries are sorted
+// in this thread's LDS slots (loaded once; a run found in order is written
+// as is); longer runs are insertion-sorted in place in global memory.
 constexpr int RUN_LDS = 32;
-__device__ __forceinline__ void sort_run_strided(uint32_t* perm, uint32_t b, uint32_t e, const uint32_t* id,
-                                                 uint2* buf) {
+__device__ __forceinline__ void sort_run_keys(uint64_t* key, uint32_t* perm, uint32_t b, uint32_t e, uint64_t* buf) {
   const uint32_t n = e - b;
-  if (n < 2) return;
+  if (n == 0) return;
   if (n <= (uint32_t)RUN_LDS) {
+    bool sorted = true;
+    uint64_t last = 0;
     for (uint32_t k = 0; k < n; ++k) {
-      const uint32_t p = perm[b + k];
-      buf[k * BLOCK] = make_uint2(id[p], p);
+      const uint64_t v = key[b + k];
+      sorted = sorted && (k == 0 || v > last);
+      last = v;
+      buf[k * BLOCK] = v;
     }
-    for (uint32_t k = 1; k < n; ++k) {
-      const uint2 key = buf[k * BLOCK];
-      uint32_t m = k;
-      while (m > 0 && buf[(m - 1) * BLOCK].x > key.x) {
-        buf[m * BLOCK] = buf[(m - 1) * BLOCK];
-        --m;
+    if (!sorted) {
+      for (uint32_t k = 1; k < n; ++k) {
+        const uint64_t v = buf[k * BLOCK];
+        uint32_t m = k;
+        while (m > 0 && buf[(m - 1) * BLOCK] > v) {
+          buf[m * BLOCK] = buf[(m - 1) * BLOCK];
+          --m;
+        }
+        buf[m * BLOCK] = v;
       }
-      buf[m * BLOCK] = key;
     }
-    for (uint32_t k = 0; k < n; ++k) perm[b + k] = buf[k * BLOCK].y;
+    for (uint32_t k = 0; k < n; ++k) perm[b + k] = (uint32_t)buf[k * BLOCK];
     return;
   }
   for (uint32_t k = b + 1; k < e; ++k) {
-    const uint32_t key = perm[k];
-    const uint32_t kid = id[key];
+    const uint64_t v = key[k];
     uint32_t m = k;
-    while (m > b && id[perm[m - 1]] > kid) {
-      perm[m] = perm[m - 1];
+    while (m > b && key[m - 1] > v) {
+      key[m] = key[m - 1];
       --m;
     }
-    perm[m] = key;
+    key[m] = v;
   }
+  for (uint32_t k = b; k < e; ++k) perm[k] = (uint32_t)key[k];
 }
 
 __global__ __launch_bounds__(BLOCK) void k_cellsort(const SlotDesc* table, LaunchTab tab) {
-  __shared__ uint2 lds[BLOCK * RUN_LDS];
+  __shared__ uint64_t lds[BLOCK * RUN_LDS];
   SLOT_PROLOGUE(DOM_CELL);
   const int c = lb * BLOCK + threadIdx.x;
   if (c >= S.ncells) return;
   // slot k of this thread is lds[k * BLOCK + thread]: the k-th entries of a
-  // wave are adjacent (no bank conflicts)
-  sort_run_strided(S.fperm, S.start_f[c], S.start_f[c + 1], S.fid, lds + threadIdx.x);
-  sort_run_strided(S.sperm, S.start_s[c], S.start_s[c + 1], S.sid, lds + threadIdx.x);
+  // wave are adjacent
+  sort_run_keys(S.fkey, S.fperm, S.start_f[c], S.start_f[c + 1], lds + threadIdx.x);
+  sort_run_keys(S.skey, S.sperm, S.start_s[c], S.start_s[c + 1], lds + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
