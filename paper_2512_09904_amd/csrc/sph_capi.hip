@@ -375,6 +375,7 @@ static int enqueue_sort_build(sph_pool* P, const LaunchTab& T) {
   LCHK(launch(P, T, SPH_K_REORDER, 0, 0));
   LCHK(launch(P, T, SPH_K_REORDER, 1, 0));
   LCHK(launch(P, T, SPH_K_BUILD, 0, 0));
+  LCHK(launch(P, T, SPH_K_SUMW, 0, 0));
   return SPH_OK;
 }
 
@@ -943,7 +944,7 @@ extern "C" int sph_init(sph_solver* s) {
   tab_for(P, std::vector<int>{slot}, T);
   rc = enqueue_sort_build(P, T);
   if (rc) return rc;
-  LCHK(launch(P, T, SPH_K_VISC_HEAT, 0, 0));   // writes the rows' pair geometry
+  LCHK(launch(P, T, SPH_K_VISC_HEAT, 0, 0));   // frozen rates for the first step
   SlotCtl c;
   LCHK(read_ctl(P, P->slots[slot], &c, true));
   s->inited = true;

@@ -235,6 +235,16 @@ __device__ __forceinline__ T ldnt(const GLB T* p) {
   return __builtin_nontemporal_load(p);
 }
 
+// Rows are walked ROW_UNROLL entries at a time (SOLID_UNROLL for the wall
+// rows), and the next group's indices are loaded before the current group's
+// gathers are consumed, so a wavefront keeps two dependent loads in flight.
+// Entries past a row's count are loaded from the row's capacity (always in
+// bounds: capacities are multiples of eight, and a group beyond the first is
+// loaded only when it starts below the count) and replaced by a null entry:
+// own index, F = 0, which adds exactly zero to every sum.
+#define ROW_UNROLL 8
+#define SOLID_UNROLL 4
+
 // per-thread accumulators for up to NACC (= 2) bodies touched by one fluid
 // particle; explicit register arrays, selected by branches (no indexing by a
 // runtime value, so nothing goes to scratch)
@@ -745,7 +755,6 @@ template <class P>
 __global__ __launch_bounds__(BLOCK) void k_build(const SlotDesc* table, LaunchTab tab) {
 #pragma clang fp contract(off)
   typedef typename P::Pos Pos;
-  typedef typename P::Real Real;
   typedef typename P::Pos4 Pos4;
   typedef typename P::Real4 Real4;
   __shared__ Pos4 lds_stage[BLOCK / WAVE][WAVE];
@@ -767,15 +776,13 @@ __global__ __launch_bounds__(BLOCK) void k_build(const SlotDesc* table, LaunchTa
   GLB uint32_t* nj = gp<uint32_t>(S.nrec) + (int64_t)(ii >> 6) * S.kf * WAVE + lane_;
   GLB uint32_t* sj = gp<uint32_t>(S.srec) + (int64_t)(ii >> 6) * S.ks * WAVE + lane_;
   if (act) gp<Real4>(S.xo)[i] = cell_offset<P>(S, xi, yi, zi, c);
-  const double h = S.h, cut2 = S.cut2, kW = S.kW;
+  const double cut2 = S.cut2;
   const int kf = S.kf, ks = S.ks;
   const GLB uint32_t* rank = gpc<uint32_t>(S.rank);
   const GLB uint32_t* stf = gpc<uint32_t>(S.start_f);
   const GLB uint32_t* sts = gpc<uint32_t>(S.start_s);
   int cf = 0, cs = 0;
-  double sw = kW;  // W(0)
   const int lane = threadIdx.x & (WAVE - 1);
-  const double inv_h = 1.0 / h;
   // distinct cells of the wave: runs of equal cells in the sorted order
   const uint32_t myr = rank[cell_linear(S, c[0], c[1], c[2])];
   const uint32_t prevr = (uint32_t)__shfl_up((int)myr, 1, WAVE);
@@ -833,11 +840,6 @@ __global__ __launch_bounds__(BLOCK) void k_build(const SlotDesc* table, LaunchTa
         while (hits) {
           const int e = __builtin_ctzll(hits);
           hits &= hits - 1;
-          const Pos4 xq = stage[e];
-          const Pos ddx = xi - xq.x, ddy = yi - xq.y, ddz = zi - xq.z;
-          const Pos s2 = ddx * ddx + ddy * ddy;
-          const Pos d2 = s2 + ddz * ddz;
-          sw += kernel_W_d2((double)d2, inv_h, kW);
           if (cf < kf) nj[(int64_t)cf * WAVE] = jb + (uint32_t)e;
           ++cf;
         }
@@ -852,11 +854,6 @@ __global__ __launch_bounds__(BLOCK) void k_build(const SlotDesc* table, LaunchTa
         while (hits) {
           const int e = __builtin_ctzll(hits);
           hits &= hits - 1;
-          const Pos4 xq = stage[e];
-          const Pos ddx = xi - xq.x, ddy = yi - xq.y, ddz = zi - xq.z;
-          const Pos s2 = ddx * ddx + ddy * ddy;
-          const Pos d2 = s2 + ddz * ddz;
-          sw += kernel_W_d2((double)d2, inv_h, kW);
           if (cs < ks) sj[(int64_t)cs * WAVE] = wb + (uint32_t)e;
           ++cs;
         }
@@ -872,8 +869,82 @@ __global__ __launch_bounds__(BLOCK) void k_build(const SlotDesc* table, LaunchTa
   }
   S.nfc[i] = (uint32_t)cf;
   S.nsc[i] = (uint32_t)cs;
+}
+
+// ---------------------------------------------------------------------------
+// K: kernel sum over the fresh rows, self included (Section 2.4), in FP64
+// from the anchors, and the density re-initialisation against the
+// perfect-lattice sum S0 (eq. 14 with a free surface, eq. 15 without).  Each
+// pair's d^2 is formed exactly as in the cutoff test; the rows are walked in
+// order (fluid, then solid) so the sum is reproducible.
+// ---------------------------------------------------------------------------
+template <class P>
+__global__ __launch_bounds__(BLOCK) void k_sumw(const SlotDesc* table, LaunchTab tab) {
+#pragma clang fp contract(off)
+  typedef typename P::Pos Pos;
+  typedef typename P::Real Real;
+  typedef typename P::Pos4 Pos4;
+  typedef typename P::Real4 Real4;
+  SLOT_PROLOGUE(DOM_FLUID);
+  const int i = lb * BLOCK + threadIdx.x;
+  if (i >= S.nf) return;
+  const GLB Pos4* xa = gpc<Pos4>(S.xa);
+  const Pos4 xi4 = xa[i];
+  const Pos xi = xi4.x, yi = xi4.y, zi = xi4.z;
+  const double inv_h = 1.0 / S.h, kW = S.kW;
+  double sw = kW;   // W(0)
+  const int lane = i & (WAVE - 1);
+  const int64_t slice = i >> 6;
+  {
+    const int n = (int)S.nfc[i];
+    const GLB uint32_t* R = gpc<uint32_t>(S.nrec) + slice * (int64_t)S.kf * WAVE + lane;
+    uint32_t jn[ROW_UNROLL];
+#pragma unroll
+    for (int u = 0; u < ROW_UNROLL; ++u) jn[u] = ldnt(R + (int64_t)u * WAVE);
+    for (int k = 0; k < n; k += ROW_UNROLL) {
+      Pos4 xj[ROW_UNROLL];
+#pragma unroll
+      for (int u = 0; u < ROW_UNROLL; ++u) xj[u] = xa[k + u < n ? jn[u] : (uint32_t)i];
+      if (k + ROW_UNROLL < n) {
+#pragma unroll
+        for (int u = 0; u < ROW_UNROLL; ++u) jn[u] = ldnt(R + (int64_t)(k + ROW_UNROLL + u) * WAVE);
+      }
+#pragma unroll
+      for (int u = 0; u < ROW_UNROLL; ++u) {
+        const Pos ddx = xi - xj[u].x, ddy = yi - xj[u].y, ddz = zi - xj[u].z;
+        const Pos s2 = ddx * ddx + ddy * ddy;
+        const Pos d2 = s2 + ddz * ddz;
+        const double w = kernel_W_d2((double)d2, inv_h, kW);
+        if (k + u < n) sw += w;
+      }
+    }
+  }
+  {
+    const int n = (int)S.nsc[i];
+    const GLB uint32_t* R = gpc<uint32_t>(S.srec) + slice * (int64_t)S.ks * WAVE + lane;
+    const GLB Pos4* xw = gpc<Pos4>(S.xw);
+    uint32_t wn[SOLID_UNROLL];
+#pragma unroll
+    for (int u = 0; u < SOLID_UNROLL; ++u) wn[u] = ldnt(R + (int64_t)u * WAVE);
+    for (int k = 0; k < n; k += SOLID_UNROLL) {
+      Pos4 xq[SOLID_UNROLL];
+#pragma unroll
+      for (int u = 0; u < SOLID_UNROLL; ++u) xq[u] = xw[k + u < n ? wn[u] : 0u];
+      if (k + SOLID_UNROLL < n) {
+#pragma unroll
+        for (int u = 0; u < SOLID_UNROLL; ++u) wn[u] = ldnt(R + (int64_t)(k + SOLID_UNROLL + u) * WAVE);
+      }
+#pragma unroll
+      for (int u = 0; u < SOLID_UNROLL; ++u) {
+        const Pos ddx = xi - xq[u].x, ddy = yi - xq[u].y, ddz = zi - xq[u].z;
+        const Pos s2 = ddx * ddx + ddy * ddy;
+        const Pos d2 = s2 + ddz * ddz;
+        const double w = kernel_W_d2((double)d2, inv_h, kW);
+        if (k + u < n) sw += w;
+      }
+    }
+  }
   S.sumW[i] = sw;
-  // density re-initialisation
   GLB Real4* vr = gp<Real4>(S.vr);
   Real4 v = vr[i];
   const double dp3 = S.dp * S.dp * S.dp;
@@ -928,15 +999,6 @@ __global__ __launch_bounds__(BLOCK) void k_dt(const SlotDesc* table, LaunchTab t
   C->n_ac = nac;
 }
 
-// Rows are walked ROW_UNROLL entries at a time (SOLID_UNROLL for the wall
-// rows), and the next group's indices are loaded before the current group's
-// gathers are consumed, so a wavefront keeps two dependent loads in flight.
-// Entries past a row's count are loaded from the row's capacity (always in
-// bounds: capacities are multiples of eight, and a group beyond the first is
-// loaded only when it starts below the count) and replaced by a null entry:
-// own index, F = 0, which adds exactly zero to every sum.
-#define ROW_UNROLL 8
-#define SOLID_UNROLL 4
 
 // ---------------------------------------------------------------------------
 // K: viscous acceleration (eq. 10 fluid-fluid, eq. 18 fluid-wall) and heat
@@ -1567,6 +1629,7 @@ static hipError_t launch_p(int kid, int which, int sub, const SlotDesc* T, const
     case SPH_K_CELLSORT: hipLaunchKernelGGL(k_cellsort, g, b, 0, st, T, L); break;
     case SPH_K_REORDER: hipLaunchKernelGGL(k_reorder<P>, g, b, 0, st, T, L, which); break;
     case SPH_K_BUILD: hipLaunchKernelGGL(k_build<P>, g, b, 0, st, T, L); break;
+    case SPH_K_SUMW: hipLaunchKernelGGL(k_sumw<P>, g, b, 0, st, T, L); break;
     case SPH_K_DT: hipLaunchKernelGGL(k_dt, g, b, 0, st, T, L); break;
     case SPH_K_VISC_HEAT: hipLaunchKernelGGL(k_visc_heat<P>, g, b, 0, st, T, L); break;
     case SPH_K_HALF_A: hipLaunchKernelGGL(k_half_a<P>, g, b, 0, st, T, L, sub); break;
