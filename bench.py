@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 KERNEL_SRC = os.path.join(ROOT, "paper_2512_09904_amd", "csrc", "sph_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gearbox_c2.json")
 
@@ -70,9 +71,40 @@ def sweep_bytes(kernel, nf, nsr, pf, ps, prec="mixed"):
         # vr, offsets, T, counts read; ah written; wall offsets, velocities, lever arms
         return nf * (v4 + v4 + pb + cnt + v4) + rows + nsr * 3 * v4
     if kernel == "build":
-        # anchors read; offsets, counts, sum W written; vr read and written; rows written; wall positions
-        return nf * (4 * pb + v4 + cnt + 8 + 2 * v4) + rows + nsr * 4 * pb
+        # anchors read; offsets and counts written; rows written; wall positions
+        return nf * (4 * pb + v4 + cnt) + rows + nsr * 4 * pb
+    if kernel == "sumw":
+        # anchors, counts read; sum W written; vr read and written; rows read; wall positions
+        return nf * (4 * pb + cnt + 8 + 2 * v4) + rows + nsr * 4 * pb
     raise KeyError(kernel)
+
+
+def build_candidates(s, case):
+    """Candidate pairs of a 27-cell stencil search: for every fluid particle,
+    the fluid and solid particles in its own and the 26 adjacent cells of
+    edge 2h (the minimum the cell-list method tests, whatever the kernel's
+    traversal).  Cells from the current FP64 positions."""
+    p = case.params
+    cs = 2.0 * p["h_over_dp"] * p["dp"]
+    lo = np.asarray(p["grid_lo"], dtype=np.float64)
+    hi = np.asarray(p["grid_hi"], dtype=np.float64)
+    dims = np.floor((hi - lo) / cs).astype(np.int64) + 1
+    xf = s.get_fluid()["x"]
+    xs = s.dump("solid_state").reshape(case.ns, 13)[:, 0:3]
+
+    def occupancy(x):
+        c = np.clip(np.floor((x - lo) / cs).astype(np.int64), 0, dims - 1)
+        g = np.zeros(tuple(dims[::-1]), dtype=np.int64)
+        np.add.at(g, (c[:, 2], c[:, 1], c[:, 0]), 1)
+        return g, c
+
+    gf, cf = occupancy(xf)
+    gs, _ = occupancy(xs)
+    tot = gf + gs
+    pad = np.pad(tot, 1)
+    nb = sum(pad[1 + dz:1 + dz + tot.shape[0], 1 + dy:1 + dy + tot.shape[1], 1 + dx:1 + dx + tot.shape[2]]
+             for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1))
+    return int(nb[cf[:, 2], cf[:, 1], cf[:, 0]].sum())
 
 
 def distinct_wall_particles(s, nf):
@@ -374,18 +406,24 @@ def main():
     log("per-step kernel ms:", json.dumps({k: round(v, 4) for k, v in per_step_kernel_ms.items()}))
     nsr = distinct_wall_particles(s, case.nf)
     kern = {}
-    for k in ("build", "visc_heat", "momentum", "continuity"):
+    for k in ("build", "sumw", "visc_heat", "momentum", "continuity"):
         b = sweep_bytes(k, case.nf, nsr, pf2, ps2, args.precision)
         ms = float(np.mean(kt[k]))
         kern[k] = {"bytes_per_launch": int(b), "avg_launch_ms": round(ms, 5),
                    "achieved_GBs": round(b / (ms * 1e-3) / 1e9, 1),
                    "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                    "ms_per_step": round(per_step_kernel_ms[k], 4)}
+    # the build is a search, bound by vector FP64 arithmetic: its algorithmic
+    # work is 8 FP64 flops (three differences, three squares, two sums) per
+    # candidate of the 27-cell stencil
+    cand = build_candidates(s, case)
+    b_flops = 8.0 * cand
+    kern["build"]["candidates"] = cand
+    kern["build"]["fp64_tflops"] = round(b_flops / (kern["build"]["avg_launch_ms"] * 1e-3) / 1e12, 3)
+    kern["build"]["fp64_frac"] = round(kern["build"]["fp64_tflops"] / FP64_PEAK_TFLOPS, 4)
     # the dominant kernel: the largest share of the step's device time
     dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
     avg_ms = kern[dom]["avg_launch_ms"]
-    bytes_launch = kern[dom]["bytes_per_launch"]
-    achieved = kern[dom]["achieved_GBs"]
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
@@ -393,9 +431,15 @@ def main():
         ent = tr.get(dom, {})
         if tr.get("kernel_sha") == kernel_hash() and tr.get("precision") == args.precision:
             traffic = ent.get("bytes_per_launch")
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": "k_" + dom,
-                "bytes_per_launch": int(bytes_launch), "avg_launch_ms": avg_ms}
+    if dom == "build":
+        roofline = {"bound": "alu", "achieved": kern["build"]["fp64_tflops"], "peak": FP64_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": kern["build"]["fp64_frac"], "traffic": traffic, "kernel": "k_build",
+                    "flops_per_launch": b_flops, "avg_launch_ms": avg_ms}
+    else:
+        achieved = kern[dom]["achieved_GBs"]
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": "k_" + dom,
+                    "bytes_per_launch": int(kern[dom]["bytes_per_launch"]), "avg_launch_ms": avg_ms}
     sweep_lat = {k: {"p50_ms": round(pct(kt[k], 50), 5), "p99_ms": round(pct(kt[k], 99), 5), "n": len(kt[k])}
                  for k in ("build", "visc_heat", "momentum", "continuity") if len(kt[k])}
 
