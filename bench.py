@@ -396,7 +396,7 @@ def main():
     s.set_timing(False)
     # sub-step kernels are launched for the bound on n_ac; launches past a
     # step's n_ac exit at once and are dropped from the per-launch statistics
-    for k in ("momentum", "continuity", "half_b"):
+    for k in ("momentum", "continuity"):
         nl = len(kt[k]) // args.timed_steps
         kt[k + "_all"] = kt[k]
         kt[k] = np.concatenate([kt[k][q * nl: q * nl + nac_steps[q]] for q in range(args.timed_steps)])

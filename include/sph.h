@@ -171,7 +171,7 @@ int sph_destroy(sph_solver* s);
 enum {
   SPH_K_CLEAR = 0, SPH_K_POSE, SPH_K_FOLD, SPH_K_SCAN1, SPH_K_SCAN2, SPH_K_SCAN3, SPH_K_SCATTER,
   SPH_K_CELLSORT, SPH_K_REORDER, SPH_K_BUILD, SPH_K_DT, SPH_K_VISC_HEAT, SPH_K_HALF_A,
-  SPH_K_MOMENTUM, SPH_K_CONTINUITY, SPH_K_HALF_B, SPH_K_END, SPH_K_FINAL, SPH_K_SUMW, SPH_K_COUNT
+  SPH_K_MOMENTUM, SPH_K_CONTINUITY, SPH_K_END, SPH_K_FINAL, SPH_K_SUMW, SPH_K_COUNT
 };
 
 /* dump selectors; arrays are in the device's cell-sorted order unless noted */

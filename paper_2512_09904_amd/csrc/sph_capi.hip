@@ -383,13 +383,12 @@ static int enqueue_step(sph_pool* P, const LaunchTab& T, int nac) {
   LCHK(enqueue_sort_build(P, T));
   LCHK(launch(P, T, SPH_K_DT, 0, 0));
   LCHK(launch(P, T, SPH_K_VISC_HEAT, 0, 0));
-  // sub-step s: momentum, continuity, then close s and open s + 1 (the first
-  // opening half update is its own launch)
+  // sub-step s: momentum, then continuity, which also closes s and opens
+  // s + 1 (the first opening half update is its own launch)
   LCHK(launch(P, T, SPH_K_HALF_A, 0, 0));
   for (int s = 0; s < nac; ++s) {
     LCHK(launch(P, T, SPH_K_MOMENTUM, 0, s));
     LCHK(launch(P, T, SPH_K_CONTINUITY, 0, s));
-    LCHK(launch(P, T, SPH_K_HALF_B, 0, s));
   }
   LCHK(launch(P, T, SPH_K_END, 0, 0));
   LCHK(launch(P, T, SPH_K_FINAL, 0, 0));

@@ -1,7 +1,7 @@
 // sph_kernels.hip -- gfx950 kernels of the WCSPH thermo-fluid hot path
 // (arXiv 2512.09904, Section 2).  One advection step is the launch sequence
 // clear -> pose -> fold -> scan1..3 -> scatter -> cellsort -> reorder -> build
-// -> dt -> visc_heat -> n_ac x (half_a, momentum, continuity, half_b) -> end
+// -> sumw -> dt -> visc_heat -> half_a -> n_ac x (momentum, continuity) -> end
 // -> final.  Every kernel covers all slots of a launch table: block b of the
 // grid belongs to the slot whose block range contains b, so one launch
 // steps many independent solves (continuous batching) and a solve's result
@@ -244,6 +244,34 @@ __device__ __forceinline__ T ldnt(const GLB T* p) {
 // own index, F = 0, which adds exactly zero to every sum.
 #define ROW_UNROLL 8
 #define SOLID_UNROLL 4
+
+// A block's window of the fluid anchors: the WIN particles around the
+// block's own BLOCK (clamped to the array), staged in LDS with coalesced
+// loads.  In the Morton order most neighbours of the block's particles fall
+// inside it, so their 32-byte gathers become LDS reads; the rest are gathered
+// from global memory.  Used by the FP64 kernel-sum sweep, whose anchor
+// gathers (two 16-byte requests per pair) otherwise bound it by the vector
+// memory unit's rate of one scattered lane per clock.
+constexpr int WIN = 1024;
+struct Window {
+  uint32_t w0, wn;
+};
+__device__ __forceinline__ Window window_of(int lb, int nf) {
+  Window w;
+  w.wn = (uint32_t)min(WIN, nf);
+  const int lo = lb * BLOCK - (WIN - BLOCK) / 2;
+  w.w0 = (uint32_t)max(0, min(lo, nf - (int)w.wn));
+  return w;
+}
+template <class T>
+__device__ __forceinline__ void stage_window(T* lds, const GLB T* g, const Window& w) {
+  for (uint32_t q = threadIdx.x; q < w.wn; q += BLOCK) lds[q] = g[w.w0 + q];
+}
+template <class T>
+__device__ __forceinline__ T win_get(const T* lds, const GLB T* g, uint32_t j, const Window& w) {
+  const uint32_t d = j - w.w0;
+  return d < w.wn ? lds[d] : g[j];
+}
 
 // per-thread accumulators for up to NACC (= 2) bodies touched by one fluid
 // particle; explicit register arrays, selected by branches (no indexing by a
@@ -885,10 +913,14 @@ __global__ __launch_bounds__(BLOCK) void k_sumw(const SlotDesc* table, LaunchTab
   typedef typename P::Real Real;
   typedef typename P::Pos4 Pos4;
   typedef typename P::Real4 Real4;
+  __shared__ Pos4 wxa[WIN];
   SLOT_PROLOGUE(DOM_FLUID);
   const int i = lb * BLOCK + threadIdx.x;
-  if (i >= S.nf) return;
   const GLB Pos4* xa = gpc<Pos4>(S.xa);
+  const Window win = window_of(lb, S.nf);
+  stage_window(wxa, xa, win);
+  __syncthreads();
+  if (i >= S.nf) return;
   const Pos4 xi4 = xa[i];
   const Pos xi = xi4.x, yi = xi4.y, zi = xi4.z;
   const double inv_h = 1.0 / S.h, kW = S.kW;
@@ -904,7 +936,7 @@ __global__ __launch_bounds__(BLOCK) void k_sumw(const SlotDesc* table, LaunchTab
     for (int k = 0; k < n; k += ROW_UNROLL) {
       Pos4 xj[ROW_UNROLL];
 #pragma unroll
-      for (int u = 0; u < ROW_UNROLL; ++u) xj[u] = xa[k + u < n ? jn[u] : (uint32_t)i];
+      for (int u = 0; u < ROW_UNROLL; ++u) xj[u] = win_get(wxa, xa, k + u < n ? jn[u] : (uint32_t)i, win);
       if (k + ROW_UNROLL < n) {
 #pragma unroll
         for (int u = 0; u < ROW_UNROLL; ++u) jn[u] = ldnt(R + (int64_t)(k + ROW_UNROLL + u) * WAVE);
@@ -1174,12 +1206,12 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(const SlotDesc* table, Launc
   if (sub >= S.ctl->n_ac) return;
   const int nf = S.nf;
   const int i = lb * BLOCK + threadIdx.x;
+  const GLB Real4* vr = gpc<Real4>(S.vr);
+  const GLB Real4* xo = gpc<Real4>(S.xo);
   BodyAcc<6> acc;
   acc.init();
   bool wall = false;
   if (i < nf) {
-    const GLB Real4* vr = gpc<Real4>(S.vr);
-    const GLB Real4* xo = gpc<Real4>(S.xo);
     const Real c0 = (Real)S.c0;
     const Real m = (Real)S.mass;
     const Real4 vi = vr[i];
@@ -1302,7 +1334,8 @@ __global__ __launch_bounds__(BLOCK) void k_momentum(const SlotDesc* table, Launc
 
 // ---------------------------------------------------------------------------
 // K: Riemann continuity (eq. 10, 11-13) with (v_i - v*) . e_ij = U* - U_L, and
-// the wall's mirror state; writes Drho and commits v <- v_new.
+// the wall's mirror state; writes Drho, commits v <- v_new and applies the
+// half updates that close this sub-step and open the next.
 // ---------------------------------------------------------------------------
 template <class P>
 __global__ __launch_bounds__(BLOCK) void k_continuity(const SlotDesc* table, LaunchTab tab, int sub) {
@@ -1403,29 +1436,15 @@ __global__ __launch_bounds__(BLOCK) void k_continuity(const SlotDesc* table, Lau
       }
     }
   }
-  gp<Real>(S.drho)[i] = (Real)2 * rhoi * sum;
-  gp<Real4>(S.vr)[i] = vi;
-}
-
-// ---------------------------------------------------------------------------
-// K: close sub-step `sub` (rho += dt/2 Drho) and, unless it is the step's
-// last, open the next one (rho += dt/2 Drho again, x += dt/2 v)
-// ---------------------------------------------------------------------------
-template <class P>
-__global__ __launch_bounds__(BLOCK) void k_half_b(const SlotDesc* table, LaunchTab tab, int sub) {
-  typedef typename P::Real Real;
-  typedef typename P::Real4 Real4;
-  SLOT_PROLOGUE(DOM_FLUID);
-  const int nac = S.ctl->n_ac;
-  if (sub >= nac) return;
-  const int i = lb * BLOCK + threadIdx.x;
-  if (i >= S.nf) return;
+  // commit v <- v_new and close the sub-step (rho += dt/2 Drho); unless it is
+  // the step's last, open the next one (rho += dt/2 Drho, x += dt/2 v).  No
+  // thread of this sweep reads vr, so the update is in place.
+  const Real dr = (Real)2 * rhoi * sum;
+  gp<Real>(S.drho)[i] = dr;
   const Real hdt = (Real)(0.5 * S.ctl->dt);
-  const Real dr = gpc<Real>(S.drho)[i];
-  GLB Real4* vr = gp<Real4>(S.vr);
-  Real4 v = vr[i];
+  Real4 v = vi;
   v.w += hdt * dr;
-  if (sub + 1 < nac) {
+  if (sub + 1 < S.ctl->n_ac) {
     v.w += hdt * dr;
     GLB Real4* dp = gp<Real4>(S.drift);
     Real4 d = dp[i];
@@ -1434,7 +1453,7 @@ __global__ __launch_bounds__(BLOCK) void k_half_b(const SlotDesc* table, LaunchT
     d.z += hdt * v.z;
     dp[i] = d;
   }
-  vr[i] = v;
+  gp<Real4>(S.vr)[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -1635,7 +1654,6 @@ static hipError_t launch_p(int kid, int which, int sub, const SlotDesc* T, const
     case SPH_K_HALF_A: hipLaunchKernelGGL(k_half_a<P>, g, b, 0, st, T, L, sub); break;
     case SPH_K_MOMENTUM: hipLaunchKernelGGL(k_momentum<P>, g, b, 0, st, T, L, sub); break;
     case SPH_K_CONTINUITY: hipLaunchKernelGGL(k_continuity<P>, g, b, 0, st, T, L, sub); break;
-    case SPH_K_HALF_B: hipLaunchKernelGGL(k_half_b<P>, g, b, 0, st, T, L, sub); break;
     case SPH_K_END: hipLaunchKernelGGL(k_end<P>, g, b, 0, st, T, L); break;
     case SPH_K_FINAL: hipLaunchKernelGGL(k_final, g, dim3(FINAL_BLOCK), 0, st, T, L); break;
     default: return hipErrorInvalidValue;

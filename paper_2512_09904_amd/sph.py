@@ -21,7 +21,7 @@ PREC = {"mixed": 0, "fp64": 1, "fp32": 2}
 MAX_BODIES = 8
 
 KERNELS = ["clear", "pose", "fold", "scan1", "scan2", "scan3", "scatter", "cellsort", "reorder", "build",
-           "dt", "visc_heat", "half_a", "momentum", "continuity", "half_b", "end", "final", "sumw"]
+           "dt", "visc_heat", "half_a", "momentum", "continuity", "end", "final", "sumw"]
 K = {n: i for i, n in enumerate(KERNELS)}
 
 DUMP = dict(fluid_ids=1, solid_ids=2, fluid_cell=3, nbr_count=4, nbr_fluid=5, nbr_solid=6, fluid_offset=7,
