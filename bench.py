@@ -312,7 +312,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--timed-steps", type=int, default=20, help="steps of the per-kernel event-timed pass")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64", "fp32"])
-    ap.add_argument("--dp", type=float, default=1.5e-3)
+    ap.add_argument("--dp", type=float, default=1.5e-3, help="particle spacing of the gearbox proxy")
+    ap.add_argument("--workload", default="gearbox", choices=["gearbox", "full"],
+                    help="gearbox: the 1.5 mm proxy at 300 rad/s (default); full: the 1 mm proxy at 600 rad/s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--calib-copy", action="store_true", help="run one 1 GiB device copy (counter calibration)")
@@ -358,7 +360,12 @@ def main():
         return
 
     t0 = time.perf_counter()
-    case = cases.gearbox(seed=0, dp=args.dp, omega_big=300.0, immersion=0.030, nu=1e-4)
+    if args.workload == "full":
+        # the 1 mm proxy: 40-tooth gear at 600 rad/s, 50 mm immersion, nu = 2.2e-4
+        om, imm, nu, dp = 600.0, 0.050, 2.2e-4, 1e-3
+    else:
+        om, imm, nu, dp = 300.0, 0.030, 1e-4, args.dp
+    case = cases.gearbox(seed=0, dp=dp, omega_big=om, immersion=imm, nu=nu)
     log(f"case: nf={case.nf} ns={case.ns} generated in {time.perf_counter() - t0:.1f} s")
     s = sph.Solver(case, precision=args.precision)
     log("initialised")
@@ -464,8 +471,8 @@ def main():
         "vs_baseline": None,
         "dtype": {"mixed": "f32+f64", "fp64": "f64", "fp32": "f32"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"gearbox proxy dp={args.dp * 1e3:.2f} mm, two toothed disks 20/40 teeth at "
-                               f"-600/300 rad/s, 30 mm immersion, nu=1e-4",
+        "config": {"workload": f"gearbox proxy dp={dp * 1e3:.2f} mm, two toothed disks 20/40 teeth at "
+                               f"-{2 * om:.0f}/{om:.0f} rad/s, {imm * 1e3:.0f} mm immersion, nu={nu:g}",
                    "n_fluid": case.nf, "n_solid": case.ns, "n_ac_last": n_ac, "pairs_per_sweep": int(pairs),
                    "pair_sweeps_per_step": round(sweeps, 3), "precision": args.precision, "parallelism": "single GPU"},
         "sweep_latency": sweep_lat,
