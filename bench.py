@@ -71,7 +71,8 @@ def sweep_bytes(kernel, nf, nsr, pf, ps, prec="mixed"):
         # vr, offsets, T, counts read; ah written; wall offsets, velocities, lever arms
         return nf * (v4 + v4 + pb + cnt + v4) + rows + nsr * 3 * v4
     if kernel == "build":
-        # anchors read; offsets and counts written; rows written; wall positions
+        # anchors read; offsets and counts written; rows written (the particle-major staging is
+        # read back from cache); wall positions
         return nf * (4 * pb + v4 + cnt) + rows + nsr * 4 * pb
     if kernel == "sumw":
         # anchors, counts read; sum W written; vr read and written; rows read; wall positions

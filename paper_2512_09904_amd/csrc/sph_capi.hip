@@ -153,6 +153,7 @@ static size_t carve(const Plan& P, void* base, SlotDesc* d) {
   C.take(D.nsc, nf * 4);
   C.take(D.nrec, 4 * (size_t)P.rowlen_f);
   C.take(D.srec, 4 * (size_t)P.rowlen_s);
+  C.take(D.rmaj, 4 * nf * (size_t)(P.kf + P.ks));
   C.takev(D.xo, 4 * nf * rs);
   C.takev(D.so, 4 * ns * rs);
   C.takev(D.x0, ns * 32);

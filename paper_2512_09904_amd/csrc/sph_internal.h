@@ -73,6 +73,7 @@ struct SlotDesc {
   // the cell-relative positions the sweeps take r_ij from
   uint32_t *nfc, *nsc;
   uint32_t *nrec, *srec;
+  uint32_t *rmaj;       // build output: per particle kf fluid then ks solid entries
   void *xo, *so;
   // solids: FP64 reference pose (x, y, z, 0) and normal, body; current pose
   void *x0, *n0;

@@ -678,45 +678,22 @@ __global__ __launch_bounds__(BLOCK) void k_reorder(const SlotDesc* table, Launch
 // ---------------------------------------------------------------------------
 // K: neighbour rows (Section 2.8: neighbour lists and kernel quantities are
 // refreshed once per advection step).  The cutoff test d^2 < (2h)^2 is FP64
-// with d^2 = (dx dx + dy dy) + dz dz and no contraction.  Each hit stores the
-// neighbour's sorted index in the particle's SELL row; every particle stores
-// its cell-relative position, from which the sweeps form r_ij.  The kernel
-// sum (self, fluid, solid) drives the density re-initialisation of Section
-// 2.4 (eq. 14 with a free surface, eq. 15 without), against the
-// perfect-lattice sum S0.
+// with d^2 = (dx dx + dy dy) + dz dz and no contraction.  Every particle also
+// stores its cell-relative position, from which the sweeps form r_ij.
 //
-// A wavefront holds 64 consecutive particles of the Morton order, i.e. a few
-// distinct neighbouring cells.  It visits the union of their 27-cell stencils
-// once (each distinct cell's stencil minus the cells already visited; the
-// stencil's cell ranges are fetched lane-parallel).  A cell's candidates are
-// staged with one coalesced load per 64 into the wave's LDS slots, and each
-// lane tests them (those of its own stencil) into a hit mask, without branches
-// or stores per candidate; each hit then adds its kernel weight and writes its
-// index.
+// A wavefront holds 64 consecutive particles of the Morton order, i.e. runs
+// of particles sharing a cell.  For each run the candidates of its 27-cell
+// stencil are spread over the lanes (up to CB per lane, loaded once); the
+// run's particles are then taken one at a time: each lane tests its
+// candidates against the particle's position (broadcast from its lane into
+// scalar registers), one ballot per candidate slot gives the hits, and the
+// hit lanes write their indices to consecutive entries of the particle's row
+// (particle-major, so a ballot's stores are contiguous).  Every test is one
+// of the particle's own stencil, and no lane waits on another's hits.  A row
+// lists the stencil's cells in a fixed order, indices ascending within a
+// cell.  At the end each lane moves its particle's row (still in cache) into
+// the SELL layout the sweeps read, with stores contiguous across the wave.
 // ---------------------------------------------------------------------------
-// Hit mask of this lane against the wave's staged candidates [0, m4): bit e
-// is set when d^2 = (dx dx + dy dy) + dz dz < (2h)^2, FP64, no contraction.
-// m4 is the candidate count rounded up to four; the padding slots hold a far
-// sentinel that never hits.
-template <class Pos, class Pos4>
-__device__ __forceinline__ uint64_t test_staged(const Pos4* stage, int m4, Pos xi, Pos yi, Pos zi, double cut2) {
-#pragma clang fp contract(off)
-  uint64_t hits = 0;
-  for (int e0 = 0; e0 < m4; e0 += 4) {
-    uint32_t b = 0;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const Pos4 xj = stage[e0 + u];
-      const Pos ddx = xi - xj.x, ddy = yi - xj.y, ddz = zi - xj.z;
-      const Pos s2 = ddx * ddx + ddy * ddy;
-      const Pos d2 = s2 + ddz * ddz;
-      b |= ((double)d2 < cut2 ? 1u : 0u) << u;
-    }
-    hits |= (uint64_t)b << e0;
-  }
-  return hits;
-}
-
 // Wendland C2 weight W = kW (1 - q/2)^4 (1 + 2q), q = |r|/h, from d^2 in FP64.
 // |r| comes from the hardware reciprocal square root refined by coupled
 // Newton steps for sqrt(x) and 1/(2 sqrt(x)) (Goldschmidt's iteration) and a
@@ -733,25 +710,6 @@ __device__ __forceinline__ double kernel_W_d2(double d2, double inv_h, double kW
   const double q = (d2 > 0.0 ? g : 0.0) * inv_h;
   const double t = 1.0 - 0.5 * q;
   return kW * t * t * t * t * (1.0 + 2.0 * q);
-}
-
-// Stage up to 64 candidates of a cell into the wave's LDS slots (one
-// coalesced load), padding to a multiple of four with a far sentinel.
-template <class Pos4>
-__device__ __forceinline__ int stage_candidates(Pos4* stage, const GLB Pos4* src, uint32_t base, int m, int lane) {
-  const int m4 = (m + 3) & ~3;
-  if (lane < m) {
-    stage[lane] = src[base + lane];
-  } else if (lane < m4) {
-    Pos4 far;
-    far.x = far.y = far.z = (typename std::remove_reference<decltype(far.x)>::type)1e30;
-    far.w = far.x;
-    stage[lane] = far;
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  return m4;
 }
 
 __device__ __forceinline__ int wave_min_i(int v) {
@@ -779,115 +737,155 @@ __device__ __forceinline__ double rl(double v, int l) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// Exclusive prefix sum over the wavefront's lanes; *total receives the sum.
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t* total) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)x, d, WAVE);
+    if (lane >= d) x += y;
+  }
+  *total = (uint32_t)__builtin_amdgcn_readlane((int)x, WAVE - 1);
+  return x - v;
+}
+
+// LDS written by some lanes of a wavefront, then read by others
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Candidates of one run's stencil against the run's particles [L, R) of the
+// wave.  pre/beg: per stencil cell (27) the prefix of candidate counts and the
+// first index.  Hits of particle p go to row[p] + off, counted in lane p's cnt.
+constexpr int CB = 8;
+template <class Pos, class Pos4>
+__device__ __forceinline__ void run_candidates(const GLB Pos4* x, const uint32_t* pre, const uint32_t* beg,
+                                               uint32_t M, int L, int R, int wbase, Pos xi, Pos yi, Pos zi,
+                                               double cut2, GLB uint32_t* rows, int kr, int off, int cap,
+                                               int& cnt, bool self) {
+#pragma clang fp contract(off)
+  const int lane = threadIdx.x & (WAVE - 1);
+  for (uint32_t b0 = 0; b0 < M; b0 += (uint32_t)(WAVE * CB)) {
+    Pos cx[CB], cy[CB], cz[CB];
+    uint32_t cj[CB];
+#pragma unroll
+    for (int u = 0; u < CB; ++u) {
+      const uint32_t m = b0 + (uint32_t)(u * WAVE + lane);
+      cj[u] = 0xffffffffu;
+      cx[u] = cy[u] = cz[u] = (Pos)1e30;   // far: never a hit
+      if (m < M) {
+        int q = 0;
+#pragma unroll
+        for (int st = 16; st > 0; st >>= 1)
+          if (q + st < 27 && pre[q + st] <= m) q += st;
+        const uint32_t j = beg[q] + (m - pre[q]);
+        const Pos4 pj = x[j];
+        cj[u] = j;
+        cx[u] = pj.x;
+        cy[u] = pj.y;
+        cz[u] = pj.z;
+      }
+    }
+    const int nu = (int)min((uint32_t)CB, (M - b0 + WAVE - 1) / WAVE);
+    for (int p = L; p < R; ++p) {
+      const Pos px = rl(xi, p), py = rl(yi, p), pz = rl(zi, p);
+      const uint32_t ip = (uint32_t)(wbase + p);
+      int c = __builtin_amdgcn_readlane(cnt, p);
+      GLB uint32_t* row = rows + (int64_t)ip * kr + off;
+#pragma unroll
+      for (int u = 0; u < CB; ++u) {
+        if (u >= nu) break;
+        const Pos ddx = px - cx[u], ddy = py - cy[u], ddz = pz - cz[u];
+        const Pos s2 = ddx * ddx + ddy * ddy;
+        const Pos d2 = s2 + ddz * ddz;
+        const bool hit = (double)d2 < cut2 && !(self && cj[u] == ip);
+        const uint64_t mask = __ballot(hit);
+        if (hit) {
+          const int k = c + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+          if (k < cap) row[k] = cj[u];
+        }
+        c += __popcll(mask);
+      }
+      if (lane == p) cnt = c;
+    }
+  }
+}
+
 template <class P>
 __global__ __launch_bounds__(BLOCK) void k_build(const SlotDesc* table, LaunchTab tab) {
 #pragma clang fp contract(off)
   typedef typename P::Pos Pos;
   typedef typename P::Pos4 Pos4;
   typedef typename P::Real4 Real4;
-  __shared__ Pos4 lds_stage[BLOCK / WAVE][WAVE];
-  __shared__ int lds_cells[BLOCK / WAVE][3 * WAVE];
+  __shared__ uint32_t lds_pre[BLOCK / WAVE][2][32];
+  __shared__ uint32_t lds_beg[BLOCK / WAVE][2][32];
   SLOT_PROLOGUE(DOM_FLUID);
   const int i = lb * BLOCK + threadIdx.x;
   const int nf = S.nf;
   const bool act = i < nf;
   const int ii = act ? i : nf - 1;
-  Pos4* stage = lds_stage[threadIdx.x / WAVE];
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
   const GLB Pos4* xa = gpc<Pos4>(S.xa);
   const GLB Pos4* xw = gpc<Pos4>(S.xw);
   const Pos4 xi4 = xa[ii];
   const Pos xi = xi4.x, yi = xi4.y, zi = xi4.z;
   int c[3];
   cell_coords<Pos>(S, xi, yi, zi, c);
-  // row entry k of particle i sits at (i/64 * K + k) * 64 + i%64
-  const int lane_ = threadIdx.x & (WAVE - 1);
-  GLB uint32_t* nj = gp<uint32_t>(S.nrec) + (int64_t)(ii >> 6) * S.kf * WAVE + lane_;
-  GLB uint32_t* sj = gp<uint32_t>(S.srec) + (int64_t)(ii >> 6) * S.ks * WAVE + lane_;
   if (act) gp<Real4>(S.xo)[i] = cell_offset<P>(S, xi, yi, zi, c);
   const double cut2 = S.cut2;
   const int kf = S.kf, ks = S.ks;
+  GLB uint32_t* rows = gp<uint32_t>(S.rmaj);
   const GLB uint32_t* rank = gpc<uint32_t>(S.rank);
   const GLB uint32_t* stf = gpc<uint32_t>(S.start_f);
   const GLB uint32_t* sts = gpc<uint32_t>(S.start_s);
+  uint32_t* preF = lds_pre[wv][0];
+  uint32_t* preS = lds_pre[wv][1];
+  uint32_t* begF = lds_beg[wv][0];
+  uint32_t* begS = lds_beg[wv][1];
   int cf = 0, cs = 0;
-  const int lane = threadIdx.x & (WAVE - 1);
-  // distinct cells of the wave: runs of equal cells in the sorted order
+  // runs of equal cells among the wave's particles
   const uint32_t myr = rank[cell_linear(S, c[0], c[1], c[2])];
   const uint32_t prevr = (uint32_t)__shfl_up((int)myr, 1, WAVE);
+  const int nact = __popcll(__ballot(act));
   uint64_t runs = __ballot(act && (lane == 0 || prevr != myr));
   // this lane's offset in a 27-cell stencil
   const int ox = lane % 3 - 1, oy = (lane / 3) % 3 - 1, oz = lane / 9 - 1;
-  int* done = lds_cells[threadIdx.x / WAVE];
-  int ndone = 0;
+  const int wbase = i - lane;
   while (runs) {
     const int L = __builtin_ctzll(runs);
     runs &= runs - 1;
+    const int R = runs ? __builtin_ctzll(runs) : nact;
     const int dx = __builtin_amdgcn_readlane(c[0], L), dy = __builtin_amdgcn_readlane(c[1], L),
               dz = __builtin_amdgcn_readlane(c[2], L);
-    // stencil cell of this lane, unless an earlier distinct cell's stencil has it
     const int nx = dx + ox, ny = dy + oy, nz = dz + oz;
-    bool take = lane < 27 && nx >= 0 && ny >= 0 && nz >= 0 && nx < S.dims[0] && ny < S.dims[1] && nz < S.dims[2];
-    for (int q = 0; q < ndone; ++q)
-      take = take && !(abs(nx - done[3 * q]) <= 1 && abs(ny - done[3 * q + 1]) <= 1 && abs(nz - done[3 * q + 2]) <= 1);
+    const bool valid = lane < 27 && nx >= 0 && ny >= 0 && nz >= 0 && nx < S.dims[0] && ny < S.dims[1] &&
+                       nz < S.dims[2];
     uint32_t f0 = 0, f1 = 0, s0 = 0, s1 = 0;
-    if (take) {
+    if (valid) {
       const uint32_t r = rank[cell_linear(S, nx, ny, nz)];
       f0 = stf[r];
       f1 = stf[r + 1];
       s0 = sts[r];
       s1 = sts[r + 1];
     }
-    uint64_t todo = __ballot(take);
-    if (lane == 0) {
-      done[3 * ndone] = dx;
-      done[3 * ndone + 1] = dy;
-      done[3 * ndone + 2] = dz;
+    uint32_t Mf, Ms;
+    const uint32_t pf = wave_excl_scan(f1 - f0, &Mf);
+    const uint32_t ps = wave_excl_scan(s1 - s0, &Ms);
+    if (lane < 27) {
+      preF[lane] = pf;
+      begF[lane] = f0;
+      preS[lane] = ps;
+      begS[lane] = s0;
     }
-    ++ndone;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    while (todo) {
-      const int t = __builtin_ctzll(todo);
-      todo &= todo - 1;
-      const int cx = __builtin_amdgcn_readlane(nx, t), cy = __builtin_amdgcn_readlane(ny, t),
-                cz = __builtin_amdgcn_readlane(nz, t);
-      const bool need = act && abs(cx - c[0]) <= 1 && abs(cy - c[1]) <= 1 && abs(cz - c[2]) <= 1;
-      // fluid candidates, 64 at a time: one coalesced load into this wave's
-      // LDS slots, a branch-free FP64 test per candidate building a hit mask,
-      // then the hits are written
-      const uint32_t a0 = rl_u(f0, t), a1 = rl_u(f1, t);
-      for (uint32_t jb = a0; jb < a1; jb += WAVE) {
-        const int m = (int)min((uint32_t)WAVE, a1 - jb);
-        const int m4 = stage_candidates(stage, xa, jb, m, lane);
-        uint64_t hits = 0;
-        if (need) {
-          hits = test_staged<Pos>(stage, m4, xi, yi, zi, cut2);
-          if ((uint32_t)i - jb < (uint32_t)m) hits &= ~(1ull << ((uint32_t)i - jb));
-        }
-        while (hits) {
-          const int e = __builtin_ctzll(hits);
-          hits &= hits - 1;
-          if (cf < kf) nj[(int64_t)cf * WAVE] = jb + (uint32_t)e;
-          ++cf;
-        }
-        __builtin_amdgcn_wave_barrier();
-      }
-      const uint32_t b0 = rl_u(s0, t), b1 = rl_u(s1, t);
-      for (uint32_t wb = b0; wb < b1; wb += WAVE) {
-        const int m = (int)min((uint32_t)WAVE, b1 - wb);
-        const int m4 = stage_candidates(stage, xw, wb, m, lane);
-        uint64_t hits = 0;
-        if (need) hits = test_staged<Pos>(stage, m4, xi, yi, zi, cut2);
-        while (hits) {
-          const int e = __builtin_ctzll(hits);
-          hits &= hits - 1;
-          if (cs < ks) sj[(int64_t)cs * WAVE] = wb + (uint32_t)e;
-          ++cs;
-        }
-        __builtin_amdgcn_wave_barrier();
-      }
-    }
+    wave_lds_sync();
+    run_candidates<Pos>(xa, preF, begF, Mf, L, R, wbase, xi, yi, zi, cut2, rows, kf + ks, 0, kf, cf, true);
+    if (Ms) run_candidates<Pos>(xw, preS, begS, Ms, L, R, wbase, xi, yi, zi, cut2, rows, kf + ks, kf, ks, cs, false);
+    wave_lds_sync();
   }
   if (!act) return;
   if (cf > kf || cs > ks) {
@@ -897,6 +895,28 @@ __global__ __launch_bounds__(BLOCK) void k_build(const SlotDesc* table, LaunchTa
   }
   S.nfc[i] = (uint32_t)cf;
   S.nsc[i] = (uint32_t)cs;
+  // move this particle's row (written by the wave's lanes, still in cache)
+  // into the SELL layout: entry k of the wave's particles lands contiguous
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  const GLB uint32_t* RM = rows + (int64_t)i * (kf + ks);
+  GLB uint32_t* RS = gp<uint32_t>(S.nrec) + (int64_t)(i >> 6) * kf * WAVE + lane;
+  for (int k = 0; k < cf; k += 4) {
+    const u4 e = *(const GLB u4*)(RM + k);
+    const uint32_t ev[4] = {e.x, e.y, e.z, e.w};
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (k + u < cf) RS[(int64_t)(k + u) * WAVE] = ev[u];
+  }
+  RM += kf;
+  RS = gp<uint32_t>(S.srec) + (int64_t)(i >> 6) * ks * WAVE + lane;
+  for (int k = 0; k < cs; k += 4) {
+    const u4 e = *(const GLB u4*)(RM + k);
+    const uint32_t ev[4] = {e.x, e.y, e.z, e.w};
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (k + u < cs) RS[(int64_t)(k + u) * WAVE] = ev[u];
+  }
 }
 
 // ---------------------------------------------------------------------------
