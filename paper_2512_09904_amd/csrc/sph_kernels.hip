@@ -595,11 +595,19 @@ __device__ __forceinline__ void sort_run_keys(uint64_t* key, uint32_t* perm, uin
   if (n <= (uint32_t)RUN_LDS) {
     bool sorted = true;
     uint64_t last = 0;
-    for (uint32_t k = 0; k < n; ++k) {
-      const uint64_t v = key[b + k];
-      sorted = sorted && (k == 0 || v > last);
-      last = v;
-      buf[k * BLOCK] = v;
+    // four independent loads in flight per step
+    for (uint32_t k0 = 0; k0 < n; k0 += 4) {
+      uint64_t v[4];
+#pragma unroll
+      for (uint32_t u = 0; u < 4; ++u) v[u] = k0 + u < n ? key[b + k0 + u] : ~0ull;
+#pragma unroll
+      for (uint32_t u = 0; u < 4; ++u) {
+        if (k0 + u < n) {
+          sorted = sorted && (k0 + u == 0 || v[u] > last);
+          last = v[u];
+          buf[(k0 + u) * BLOCK] = v[u];
+        }
+      }
     }
     if (!sorted) {
       for (uint32_t k = 1; k < n; ++k) {

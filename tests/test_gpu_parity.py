@@ -359,3 +359,24 @@ def test_nonfinite_is_latched(sph):
     assert r["rc"] == sph.SPH_ERR_NONFINITE
     assert r["step"] == 1
     s.close()
+
+
+@pytest.mark.parametrize("precision,bar", [("mixed", 1e-5), ("fp64", 1e-10)])
+def test_fluid_without_solids(sph, ora, precision, bar):
+    """Degenerate case: no solid particle at all (free fluid block under
+    gravity; the bodies carry no particles, so the time step sees no tip
+    speed and n_ac reaches its cap).  One step against the oracle."""
+    c = cases.tank_c1(seed=4)
+    c.xs0 = np.zeros((0, 3))
+    c.ns0 = np.zeros((0, 3))
+    c.body = np.zeros(0, np.int32)
+    say("fluid without solids", precision, c.nf)
+    o, ro, g, st, rg = _one_step(sph, ora, c, precision)
+    e = _normalised_errors(c, o, g)
+    say("normalised errors", e)
+    assert max(e.values()) <= bar, e
+    assert rg["n_ac"] == ro["n_ac"]
+    s = sph.Solver(c, precision=precision)
+    cnt = s.dump("nbr_count").reshape(2, c.nf)
+    s.close()
+    assert cnt[1].sum() == 0
