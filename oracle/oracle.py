@@ -76,6 +76,8 @@ def lib():
         L.ora_kernel_F.argtypes = [C.c_double, C.c_double]
         L.ora_lattice_sum0.restype = C.c_double
         L.ora_lattice_sum0.argtypes = [C.c_double]
+        L.ora_lattice_halfspace.restype = C.c_double
+        L.ora_lattice_halfspace.argtypes = [C.c_double]
         L.ora_morton3.restype = C.c_uint32
         L.ora_morton3.argtypes = [C.c_uint32] * 3
         L.ora_nbr_total.restype = C.c_int64
@@ -129,6 +131,28 @@ def F(r, h):
 
 def lattice_sum0(h_over_dp):
     return lib().ora_lattice_sum0(float(h_over_dp))
+
+
+def lattice_halfspace(h_over_dp):
+    """Kernel sum (units of dp^3) over the lattice half-space x > 0: the
+    full-immersion reference of the contact factor (eq. 24)."""
+    return lib().ora_lattice_halfspace(float(h_over_dp))
+
+
+def contact_factor(params, xf, rho, xs, ref=None):
+    """Contact factor of every solid particle at positions xs (eq. 24)."""
+    P = make_params(params)
+    xf = _c3(xf)
+    xs = _c3(xs)
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    if ref is None:
+        ref = lattice_halfspace(params["h_over_dp"])
+    z = np.zeros(len(xs))
+    rc = lib().ora_contact_factor(C.byref(P), C.c_int64(len(xf)), _p(xf), _p(rho), C.c_int64(len(xs)), _p(xs),
+                                  C.c_double(ref), _p(z))
+    if rc != 0:
+        raise RuntimeError(f"ora_contact_factor failed: {rc}")
+    return z
 
 
 def morton3(cx, cy, cz):

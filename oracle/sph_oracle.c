@@ -93,6 +93,22 @@ double ora_lattice_sum0(double h_over_dp) {
   return s;
 }
 
+/* Perfect-lattice kernel sum, in units of dp^3, over the sites of the open
+   half-space x > 0 as seen from a site on the plane x = 0: the kernel sum of
+   a wall particle whose whole outer side is filled with fluid at rho0.  It is
+   the full-immersion reference of the contact factor (Section 2.5, eq. 24). */
+double ora_lattice_halfspace(double h_over_dp) {
+  int R = (int)ceil(2.0 * h_over_dp) + 1;
+  double s = 0.0;
+  for (int i = 1; i <= R; ++i)
+    for (int j = -R; j <= R; ++j)
+      for (int k = -R; k <= R; ++k) {
+        double r = sqrt((double)(i * i + j * j + k * k));
+        s += ora_kernel_W(r, h_over_dp);
+      }
+  return s;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Cells (edge 2h) and Morton order.  The paper refreshes neighbour lists      */
 /* once per advection step (Section 2.8) but gives no search structure; a    */
@@ -371,6 +387,32 @@ void ora_sum_w(const ora_params* P, const ora_nbr* nb, double* sumW) {
 /* per-body accumulation helper: per-particle contributions, then a serial
  * compensated sum in particle order so the result is independent of threads */
 typedef struct { double* buf; int64_t nf; int32_t nbody; int32_t width; } bacc;
+/* Contact factor of every solid particle (Section 2.5, eq. 24): the sum of
+   V_j W(|x_w - x_j|) over the fluid particles j within 2h of solid w, with
+   V_j = m / rho_j, divided by the full-immersion reference ref (the same sum
+   for the fluid filling the wall's outer half-space at rho0).  The fluid
+   particles are taken in index order for each w. */
+int ora_contact_factor(const ora_params* P, int64_t nf, const double* xf, const double* rho, int64_t ns,
+                       const double* xs, double ref, double* zeta) {
+  ora_nbr* nb = NULL;
+  int rc = ora_nbr_build(P, nf, xf, ns, xs, 0, &nb);
+  if (rc) return rc;
+  double h = ora_h(P);
+  double m = P->rho0 * P->dp * P->dp * P->dp;
+  for (int64_t w = 0; w < ns; ++w) zeta[w] = 0.0;
+  for (int64_t i = 0; i < nf; ++i) {
+    double Vi = m / rho[i];
+    for (int64_t q = nb->off_s[i]; q < nb->off_s[i + 1]; ++q) {
+      int32_t w = nb->idx_s[q];
+      double r = sqrt(dist2(xf + 3 * i, xs + 3 * (size_t)w));
+      zeta[w] += Vi * ora_kernel_W(r, h);
+    }
+  }
+  for (int64_t w = 0; w < ns; ++w) zeta[w] /= ref;
+  ora_nbr_free(nb);
+  return ORA_OK;
+}
+
 static int bacc_init(bacc* a, int64_t nf, int32_t nbody, int32_t width) {
   a->nf = nf; a->nbody = nbody; a->width = width;
   a->buf = (double*)calloc((size_t)(nf > 0 ? nf : 1) * (size_t)(nbody > 0 ? nbody : 1) * (size_t)width, sizeof(double));

@@ -63,6 +63,9 @@ double ora_kernel_dW(double r, double h);   /* dW/dr */
 double ora_kernel_F(double r, double h);    /* (dW/dr)/r, finite at r = 0 */
 /* dp^3 * sum over a perfect cubic lattice of W, self included, h = h_over_dp*dp */
 double ora_lattice_sum0(double h_over_dp);
+/* Lattice kernel sum over the half-space x > 0 seen from a site on x = 0
+   (units of dp^3): full-immersion reference of the contact factor, eq. 24. */
+double ora_lattice_halfspace(double h_over_dp);
 
 /* --- cells and ordering --------------------------------------------------- */
 uint32_t ora_morton3(uint32_t cx, uint32_t cy, uint32_t cz);
@@ -82,6 +85,10 @@ void ora_nbr_free(ora_nbr* nb);
 
 /* --- sweeps over frozen neighbour sets ----------------------------------- */
 void ora_sum_w(const ora_params* P, const ora_nbr* nb, double* sumW);
+/* Contact factor per solid particle (Section 2.5, eq. 24): sum over fluid j
+   within 2h of V_j W_wj (V_j = m / rho_j) over ref; zeta[ns]. */
+int ora_contact_factor(const ora_params* P, int64_t nf, const double* xf, const double* rho, int64_t ns,
+                       const double* xs, double ref, double* zeta);
 void ora_viscous(const ora_params* P, const ora_nbr* nb, int32_t nbody, const ora_body* B,
                  const int32_t* body, const double* v, const double* rho, const double* mass,
                  const double* vs, double* a, double* S, double* bforce, double* btorque);

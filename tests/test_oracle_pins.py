@@ -470,3 +470,56 @@ def test_slab_conduction_matches_erf_solution(ora):
     exact, _ = slab_exact(xl[sel], g["t_end"], g)
     err = np.abs(T[line][sel] - exact).max()
     assert err <= g["criterion_max_abs_error_on_0.3_0.7"], err
+
+
+# --------------------------------------------------------------------------
+# contact factor (Section 2.5, eq. 24)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("hod", [1.3, 1.0])
+def test_halfspace_reference_splits_the_lattice_sum(ora, hod):
+    """The full lattice sum is the plane x = 0 plus two mirror half-spaces:
+    sum_all = 2 * half(x > 0) + sum over the plane of W (kernel values of
+    the oracle on the plane's sites)."""
+    R = int(math.ceil(2 * hod)) + 1
+    g = np.arange(-R, R + 1)
+    J, K = np.meshgrid(g, g, indexing="ij")
+    plane = sum(ora.W(float(math.sqrt(j * j + k * k)), hod) for j, k in zip(J.ravel(), K.ravel()))
+    half = ora.lattice_halfspace(hod)
+    assert ora.lattice_sum0(hod) == pytest.approx(2.0 * half + plane, rel=1e-14)
+    assert 0.0 < half < 0.5 * ora.lattice_sum0(hod)
+
+
+def _wall_under_fluid(n=12, depth=0):
+    """A flat wall site at x = depth below the plane x = 0, with fluid on a
+    perfect lattice at x = 1, 2, ... (dp = 1) filling a block wide enough to
+    cover the kernel support."""
+    g = np.arange(n) - n // 2
+    I, J, K = np.meshgrid(np.arange(1, n), g, g, indexing="ij")
+    xf = np.stack([I.ravel(), J.ravel(), K.ravel()], axis=1).astype(np.float64) + 20.0
+    xs = np.array([[20.0 - depth, 20.0, 20.0]])
+    return xf, xs
+
+
+def test_contact_factor_full_immersion_is_one(ora):
+    """A wall particle whose outer half-space is all fluid at rho0 has
+    contact factor 1: the numerator is then the reference itself."""
+    p = lattice_params(1.3, 48)
+    xf, xs = _wall_under_fluid()
+    rho = np.full(len(xf), p["rho0"])
+    z = ora.contact_factor(p, xf, rho, xs)
+    assert z[0] == pytest.approx(1.0, rel=1e-13)
+
+
+def test_contact_factor_limits(ora):
+    """No fluid within 2h: 0.  Fluid at twice the density: half (V_j = m / rho_j).
+    A wall particle one spacing deeper sees less of the kernel: 0 < zeta < 1."""
+    p = lattice_params(1.3, 48)
+    xf, xs = _wall_under_fluid()
+    rho = np.full(len(xf), p["rho0"])
+    far = xs + np.array([[-10.0, 0.0, 0.0]])
+    assert ora.contact_factor(p, xf, rho, far)[0] == 0.0
+    assert ora.contact_factor(p, xf, 2.0 * rho, xs)[0] == pytest.approx(0.5, rel=1e-13)
+    xf1, xs1 = _wall_under_fluid(depth=1)
+    z1 = ora.contact_factor(p, xf1, rho[: len(xf1)], xs1)[0]
+    assert 0.0 < z1 < 1.0
