@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+GATHER_PEAK = 256 * 2.4e9
 KERNEL_SRC = os.path.join(ROOT, "paper_2512_09904_amd", "csrc", "sph_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gearbox_c2.json")
 
@@ -448,6 +449,16 @@ def main():
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": "k_" + dom,
                     "bytes_per_launch": int(kern[dom]["bytes_per_launch"]), "avg_launch_ms": avg_ms}
+        # the sweeps are limited by scattered 16-byte gathers, which the vector
+        # memory unit serves at about one lane per clock per CU
+        gathers = {"momentum": 2 * (pf2 + ps2), "continuity": 2 * pf2 + 3 * ps2,
+                   "visc_heat": 3 * (pf2 + ps2), "sumw": 2 * (pf2 + ps2)}.get(dom)
+        if gathers:
+            rate = gathers / (avg_ms * 1e-3)
+            roofline["gather_rate"] = {"achieved": rate, "peak": GATHER_PEAK, "unit": "lane gathers/s",
+                                       "frac": round(rate / GATHER_PEAK, 4), "gathers_per_launch": int(gathers),
+                                       "peak_basis": "one scattered lane per clock per CU, 256 CUs at 2.4 GHz "
+                                                     "(texture-addresser and L1 counters)"}
     sweep_lat = {k: {"p50_ms": round(pct(kt[k], 50), 5), "p99_ms": round(pct(kt[k], 99), 5), "n": len(kt[k])}
                  for k in ("build", "visc_heat", "momentum", "continuity") if len(kt[k])}
 

@@ -158,6 +158,18 @@ int sph_set_timing(sph_solver* s, int32_t enable);
 /* Durations in ms of the recorded launches of kernel `kernel` (SPH_K_*), oldest
  * first; *count receives the number recorded (may exceed max).  Synchronises. */
 int sph_get_timing(sph_solver* s, int32_t kernel, int32_t max, float* ms, int32_t* count);
+/* Contact factor (Section 2.5, eq. 24) of every solid particle at the
+ * current time t: zeta_w = sum over fluid j with |x_w - x_j| < 2h of
+ * V_j W(|x_w - x_j|) (V_j = m / rho_j), divided by the full-immersion
+ * reference, the perfect-lattice kernel sum over the wall's outer half-space
+ * (0.2133 at h = 1.3 dp): about 1 for a wetted surface particle, 0 in air.
+ * zeta: ns doubles in the order of sph_set_solid (may be NULL); body_mean:
+ * one double per body, the mean over the body's solid particles (0 for a body
+ * without particles; may be NULL).  Runs the cell sort and neighbour build of
+ * the current state on the solver's stream (the next step's own build then
+ * reproduces them exactly, so stepping is unaffected) and synchronises.
+ * SPH_ERR_STATE before sph_init or after a latched fault. */
+int sph_contact_factor(sph_solver* s, double* zeta, double* body_mean);
 /* Raw device state for parity tests (SPH_DUMP_*); bytes must be >= the size
  * reported by sph_dump_size.  Synchronises. */
 int sph_dump_size(sph_solver* s, int32_t what, size_t* bytes);
@@ -171,7 +183,7 @@ int sph_destroy(sph_solver* s);
 enum {
   SPH_K_CLEAR = 0, SPH_K_POSE, SPH_K_FOLD, SPH_K_SCAN1, SPH_K_SCAN2, SPH_K_SCAN3, SPH_K_SCATTER,
   SPH_K_CELLSORT, SPH_K_REORDER, SPH_K_BUILD, SPH_K_DT, SPH_K_VISC_HEAT, SPH_K_HALF_A,
-  SPH_K_MOMENTUM, SPH_K_CONTINUITY, SPH_K_END, SPH_K_FINAL, SPH_K_SUMW, SPH_K_COUNT
+  SPH_K_MOMENTUM, SPH_K_CONTINUITY, SPH_K_END, SPH_K_FINAL, SPH_K_SUMW, SPH_K_CONTACT, SPH_K_COUNT
 };
 
 /* dump selectors; arrays are in the device's cell-sorted order unless noted */

@@ -174,6 +174,7 @@ static size_t carve(const Plan& P, void* base, SlotDesc* d) {
   C.takev(D.levb, 4 * ns * rs);
   C.take(D.scell, ns * 4);
   C.take(D.sperm, ns * 4);
+  C.take(D.zeta, ns * 8);
   C.take(D.skey, ns * 8);
   C.take(D.rank, nc * 4);
   C.take(D.cnt_f, nc * 4);
@@ -224,6 +225,23 @@ static double lattice_sum0(double hod) {
   const int R = (int)std::ceil(2.0 * hod) + 1;
   double s = 0.0;
   for (int i = -R; i <= R; ++i)
+    for (int j = -R; j <= R; ++j)
+      for (int k = -R; k <= R; ++k) {
+        const double q = std::sqrt((double)(i * i + j * j + k * k)) / hod;
+        if (q >= 2.0) continue;
+        const double t = 1.0 - 0.5 * q;
+        s += a * t * t * t * t * (1.0 + 2.0 * q);
+      }
+  return s;
+}
+
+// Perfect-lattice kernel sum (units of dp^3) over the sites with x > 0 seen
+// from a site on x = 0: the full-immersion reference of the contact factor.
+static double lattice_halfspace(double hod) {
+  const double a = 21.0 / (16.0 * M_PI * hod * hod * hod);
+  const int R = (int)std::ceil(2.0 * hod) + 1;
+  double s = 0.0;
+  for (int i = 1; i <= R; ++i)
     for (int j = -R; j <= R; ++j)
       for (int k = -R; k <= R; ++k) {
         const double q = std::sqrt((double)(i * i + j * j + k * k)) / hod;
@@ -595,6 +613,7 @@ static int admit(sph_pool* P, const sph_params* p, int32_t nbody, const sph_body
   D.mass = p->rho0 * (p->dp * p->dp * p->dp);
   D.vol_w = p->dp * p->dp * p->dp;
   D.S0 = lattice_sum0(p->h_over_dp);
+  D.zref = lattice_halfspace(p->h_over_dp);
   {
     const double two_h = 2.0 * D.h;
     D.cut2 = two_h * two_h;
@@ -968,6 +987,54 @@ extern "C" int sph_reduce(sph_solver* s, sph_report* r, sph_body_report* br) {
   LCHK(read_ctl(s->pool, S, &c, true));
   fill_reports(S, c, r, br);
   if (c.flags) return fail(flag_code(c.flags), "solve faulted");
+  return SPH_OK;
+}
+
+extern "C" int sph_contact_factor(sph_solver* s, double* zeta, double* body_mean) {
+  if (!s || !s->inited) return fail(SPH_ERR_STATE, "not initialised");
+  sph_pool* P = s->pool;
+  SlotHost& S = P->slots[0];
+  SlotCtl c;
+  LCHK(read_ctl(P, S, &c, true));
+  if (c.flags) return fail(flag_code(c.flags), "solve faulted");
+  LaunchTab T;
+  tab_for(P, std::vector<int>{0}, T);
+  LCHK(enqueue_sort_build(P, T));
+  LCHK(launch(P, T, SPH_K_CONTACT, 1, 0));
+  LCHK(read_ctl(P, S, &c, true));
+  if (c.flags) return fail(flag_code(c.flags), "contact factor build faulted");
+  const size_t ns = (size_t)S.plan.ns;
+  std::vector<double> z(ns);
+  std::vector<uint32_t> sid(ns);
+  std::vector<int32_t> body(ns);
+  if (ns) {
+    LCHK(d2h(z.data(), S.d.zeta, ns * 8));
+    LCHK(d2h(sid.data(), S.d.sid, ns * 4));
+    LCHK(d2h(body.data(), S.d.body, ns * 4));
+  }
+  if (zeta)
+    for (size_t k = 0; k < ns; ++k) zeta[sid[k]] = z[k];
+  if (body_mean) {
+    // mean per body over its particles in their original order, compensated
+    std::vector<double> zo(ns);
+    std::vector<int32_t> bo(ns);
+    for (size_t k = 0; k < ns; ++k) {
+      zo[sid[k]] = z[k];
+      bo[sid[k]] = body[k];
+    }
+    for (int b = 0; b < S.nbody; ++b) {
+      double sum = 0.0, comp = 0.0;
+      int64_t cnt = 0;
+      for (size_t k = 0; k < ns; ++k) {
+        if (bo[k] != b) continue;
+        const double t = sum + zo[k];
+        comp += std::fabs(sum) >= std::fabs(zo[k]) ? (sum - t) + zo[k] : (zo[k] - t) + sum;
+        sum = t;
+        ++cnt;
+      }
+      body_mean[b] = cnt ? (sum + comp) / (double)cnt : 0.0;
+    }
+  }
   return SPH_OK;
 }
 

@@ -56,6 +56,7 @@ struct SlotDesc {
   int64_t rowlen_f, rowlen_s;          // nslices * k * 64
   double dp, h, rho0, c0, eta, k_f, cp_f, mass, vol_w, S0, cut2, cs;
   double cs_r;                         // cs rounded to the interaction type (frame of the offsets)
+  double zref;                         // full-immersion reference of the contact factor
   double cfl_ad, cfl_ac, fixed_dt_ad, nu;
   double g[3], lo[3];
   double kW, kF;                       // W = kW (1-q/2)^4 (1+2q);  F = kF (1-q/2)^3
@@ -85,6 +86,7 @@ struct SlotDesc {
   uint32_t *sidb;
   void *xwb, *nwb, *vwb, *levb;
   uint32_t *scell, *sperm;
+  double *zeta;         // contact factor per sorted solid particle
   uint64_t *skey;
   // cells
   uint32_t *rank, *cnt_f, *cnt_s, *start_f, *start_s, *bsum_f, *bsum_s;

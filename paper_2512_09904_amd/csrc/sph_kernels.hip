@@ -1016,6 +1016,53 @@ __global__ __launch_bounds__(BLOCK) void k_sumw(const SlotDesc* table, LaunchTab
 }
 
 // ---------------------------------------------------------------------------
+// K: contact factor of every solid particle (Section 2.5, eq. 24) after a
+// build at the current time, FP64: the sum of V_j W_wj (V_j = m / rho_j) over
+// the fluid particles within 2h of the solid particle, over the full-immersion
+// reference (the lattice kernel sum over the wall's outer half-space).  The
+// solid particle scans its own 27 fluid cells; an observable, not a step
+// kernel.
+// ---------------------------------------------------------------------------
+template <class P>
+__global__ __launch_bounds__(BLOCK) void k_contact(const SlotDesc* table, LaunchTab tab) {
+#pragma clang fp contract(off)
+  typedef typename P::Pos Pos;
+  typedef typename P::Pos4 Pos4;
+  typedef typename P::Real4 Real4;
+  SLOT_PROLOGUE(DOM_SOLID);
+  const int w = lb * BLOCK + threadIdx.x;
+  if (w >= S.ns) return;
+  const GLB Pos4* xa = gpc<Pos4>(S.xa);
+  const GLB Real4* vr = gpc<Real4>(S.vr);
+  const GLB uint32_t* rank = gpc<uint32_t>(S.rank);
+  const GLB uint32_t* stf = gpc<uint32_t>(S.start_f);
+  const Pos4 xq = gpc<Pos4>(S.xw)[w];
+  int c[3];
+  cell_coords<Pos>(S, xq.x, xq.y, xq.z, c);
+  const double inv_h = 1.0 / S.h, kW = S.kW, m = S.mass, cut2 = S.cut2;
+  double z = 0.0;
+  for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int nx = c[0] + dx, ny = c[1] + dy, nz = c[2] + dz;
+        if (nx < 0 || ny < 0 || nz < 0 || nx >= S.dims[0] || ny >= S.dims[1] || nz >= S.dims[2]) continue;
+        const uint32_t r = rank[cell_linear(S, nx, ny, nz)];
+        for (uint32_t j = stf[r]; j < stf[r + 1]; ++j) {
+          const Pos4 xj = xa[j];
+          const Pos ddx = xq.x - xj.x, ddy = xq.y - xj.y, ddz = xq.z - xj.z;
+          const Pos s2 = ddx * ddx + ddy * ddy;
+          const Pos d2 = s2 + ddz * ddz;
+          if ((double)d2 < cut2) {
+            const double rw = (double)vr[j].w;
+            const double rho = P::kRel ? S.rho0 + rw : rw;
+            z += (m / rho) * kernel_W_d2((double)d2, inv_h, kW);
+          }
+        }
+      }
+  S.zeta[w] = z / S.zref;
+}
+
+// ---------------------------------------------------------------------------
 // K: dual-criteria time step (Section 2.8, eq. 25).  |v|max covers the fluid
 // and the bodies' tip speeds; n_ac is capped by shortening dt_ad.
 // ---------------------------------------------------------------------------
@@ -1645,6 +1692,7 @@ int grid_domain(int kid, int which) {
     case SPH_K_CELLSORT:
       return DOM_CELL;
     case SPH_K_POSE:
+    case SPH_K_CONTACT:
       return DOM_SOLID;
     case SPH_K_SCAN2:
     case SPH_K_DT:
@@ -1677,6 +1725,7 @@ static hipError_t launch_p(int kid, int which, int sub, const SlotDesc* T, const
     case SPH_K_REORDER: hipLaunchKernelGGL(k_reorder<P>, g, b, 0, st, T, L, which); break;
     case SPH_K_BUILD: hipLaunchKernelGGL(k_build<P>, g, b, 0, st, T, L); break;
     case SPH_K_SUMW: hipLaunchKernelGGL(k_sumw<P>, g, b, 0, st, T, L); break;
+    case SPH_K_CONTACT: hipLaunchKernelGGL(k_contact<P>, g, b, 0, st, T, L); break;
     case SPH_K_DT: hipLaunchKernelGGL(k_dt, g, b, 0, st, T, L); break;
     case SPH_K_VISC_HEAT: hipLaunchKernelGGL(k_visc_heat<P>, g, b, 0, st, T, L); break;
     case SPH_K_HALF_A: hipLaunchKernelGGL(k_half_a<P>, g, b, 0, st, T, L, sub); break;

@@ -21,7 +21,7 @@ PREC = {"mixed": 0, "fp64": 1, "fp32": 2}
 MAX_BODIES = 8
 
 KERNELS = ["clear", "pose", "fold", "scan1", "scan2", "scan3", "scatter", "cellsort", "reorder", "build",
-           "dt", "visc_heat", "half_a", "momentum", "continuity", "end", "final", "sumw"]
+           "dt", "visc_heat", "half_a", "momentum", "continuity", "end", "final", "sumw", "contact"]
 K = {n: i for i, n in enumerate(KERNELS)}
 
 DUMP = dict(fluid_ids=1, solid_ids=2, fluid_cell=3, nbr_count=4, nbr_fluid=5, nbr_solid=6, fluid_offset=7,
@@ -88,7 +88,7 @@ def lib():
 
 
 EXPORTS = ["sph_error_string", "sph_last_error", "sph_create", "sph_set_bodies", "sph_set_fluid", "sph_set_solid",
-           "sph_init", "sph_step", "sph_reduce", "sph_get_fluid", "sph_set_graph", "sph_set_timing",
+           "sph_init", "sph_step", "sph_reduce", "sph_contact_factor", "sph_get_fluid", "sph_set_graph", "sph_set_timing",
            "sph_get_timing", "sph_dump_size", "sph_debug_dump", "sph_debug_poke_velocity", "sph_destroy",
            "sph_bytes_required", "sph_pool_create", "sph_pool_admit", "sph_pool_step", "sph_pool_poll",
            "sph_pool_get_fluid", "sph_pool_release", "sph_pool_usage", "sph_pool_set_graph", "sph_pool_destroy"]
@@ -235,6 +235,14 @@ class Solver:
         T = np.zeros(self.nf)
         check(lib().sph_get_fluid(self.h, _p(x), _p(v), _p(r), _p(T)), "sph_get_fluid")
         return dict(x=x, v=v, rho=r, T=T)
+
+    def contact_factor(self):
+        """Contact factor of every solid particle at the current time (eq. 24),
+        in the case's solid order, and its mean per body."""
+        z = np.zeros(max(self.ns, 1))
+        m = np.zeros(max(self.nbody, 1))
+        check(lib().sph_contact_factor(self.h, _p(z), _p(m)), "sph_contact_factor")
+        return z[: self.ns], m[: self.nbody]
 
     def set_timing(self, on=True):
         check(lib().sph_set_timing(self.h, C.c_int32(int(on))), "sph_set_timing")

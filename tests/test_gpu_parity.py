@@ -380,3 +380,59 @@ def test_fluid_without_solids(sph, ora, precision, bar):
     cnt = s.dump("nbr_count").reshape(2, c.nf)
     s.close()
     assert cnt[1].sum() == 0
+
+
+# ---------------------------------------------------------------------------
+# contact factor (Section 2.5, eq. 24)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision,tol", [("mixed", 1e-6), ("fp64", 1e-12)])
+def test_contact_factor_matches_oracle(sph, ora, precision, tol):
+    """Per solid particle against the oracle on the solver's own state, at
+    t = 0 and after 20 steps; the wetted bottom wall reads about 1."""
+    c = cases.tank_c1(seed=5)
+    say("contact factor", precision, c.ns)
+    s = sph.Solver(c, precision=precision)
+    for k in range(2):
+        if k:
+            s.step(20)
+        t = s.reduce()["t"]
+        z, mean = s.contact_factor()
+        g = s.get_fluid()
+        xs, _, _ = ora.body_pose(c.bodies, c.xs0, c.ns0, c.body, t)
+        zo = ora.contact_factor(c.params, g["x"], g["rho"], xs)
+        err = np.max(np.abs(z - zo))
+        say("contact factor max error", t, err, "body means", mean)
+        assert err <= tol, err
+        for b in range(len(c.bodies)):
+            sel = c.body == b
+            if sel.any():
+                assert mean[b] == pytest.approx(float(np.mean(zo[sel])), abs=tol)
+    assert np.all(z >= 0.0)
+    dp = c.params["dp"]
+    bottom = (c.body == 0) & (np.abs(xs[:, 2] + 0.5 * dp) < 0.25 * dp)
+    inner = bottom & (xs[:, 0] > 4 * dp) & (xs[:, 0] < c.meta["box"][0] - 4 * dp) & \
+        (xs[:, 1] > 4 * dp) & (xs[:, 1] < c.meta["box"][1] - 4 * dp)
+    assert inner.sum() > 50
+    assert abs(np.median(z[inner]) - 1.0) <= 0.03, np.median(z[inner])
+    s.close()
+
+
+def test_contact_factor_leaves_the_solve_unchanged(sph):
+    """The contact factor's extra sort and build reproduce the next step's
+    own exactly: stepping with a contact-factor call in between is bitwise
+    the same as stepping without."""
+    c = cases.tank_c1(seed=6)
+    a = sph.Solver(c)
+    a.step(5)
+    a.contact_factor()
+    a.step(5)
+    ga, ra = a.get_fluid(), a.reduce()
+    a.close()
+    b = sph.Solver(c)
+    b.step(10)
+    gb, rb = b.get_fluid(), b.reduce()
+    b.close()
+    for k in ("x", "v", "rho", "T"):
+        assert np.array_equal(ga[k], gb[k]), k
+    assert ra["bodies"][1]["torque_axis"] == rb["bodies"][1]["torque_axis"]
