@@ -720,21 +720,7 @@ __device__ __forceinline__ double kernel_W_d2(double d2, double inv_h, double kW
   return kW * t * t * t * t * (1.0 + 2.0 * q);
 }
 
-__device__ __forceinline__ int wave_min_i(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, WAVE));
-  return __builtin_amdgcn_readfirstlane(v);
-}
-__device__ __forceinline__ int wave_max_i(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, WAVE));
-  return __builtin_amdgcn_readfirstlane(v);
-}
-
 // value of lane l (wave-uniform l) as a scalar
-__device__ __forceinline__ uint32_t rl_u(uint32_t v, int l) {
-  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
-}
 __device__ __forceinline__ float rl(float v, int l) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
 }
