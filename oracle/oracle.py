@@ -34,7 +34,7 @@ class Params(C.Structure):
                 ("gravity", C.c_double * 3), ("grid_lo", C.c_double * 3), ("grid_hi", C.c_double * 3),
                 ("cfl_ad", C.c_double), ("cfl_ac", C.c_double), ("fixed_dt_ad", C.c_double),
                 ("fixed_nac", C.c_int32), ("nac_max", C.c_int32), ("free_surface", C.c_int32),
-                ("eq13_printed", C.c_int32)]
+                ("eq13_printed", C.c_int32), ("viscous_heating", C.c_int32), ("pad", C.c_int32)]
 
 
 class BodyS(C.Structure):
@@ -46,7 +46,7 @@ class Report(C.Structure):
     _fields_ = [("t", C.c_double), ("dt_ad", C.c_double), ("dt", C.c_double), ("n_ac", C.c_int32),
                 ("pad", C.c_int32), ("vmax", C.c_double), ("mass", C.c_double),
                 ("kinetic", C.c_double), ("thermal", C.c_double), ("heat_step", C.c_double),
-                ("mass_proxy", C.c_double)]
+                ("mass_proxy", C.c_double), ("diss_step", C.c_double)]
 
 
 class BodyReport(C.Structure):
@@ -55,7 +55,8 @@ class BodyReport(C.Structure):
 
 
 class Rates(C.Structure):
-    _fields_ = [(n, C.c_void_p) for n in ("a_visc", "dTdt", "sumW", "S_visc", "S_T", "a_p", "S_p", "S_rho")]
+    _fields_ = [(n, C.c_void_p) for n in ("a_visc", "dTdt", "sumW", "S_visc", "S_T", "a_p", "S_p", "S_rho",
+                                          "G", "phi", "S_G")]
 
 
 _lib = None
@@ -102,6 +103,7 @@ def make_params(params: dict, **over) -> Params:
     P.nac_max = int(d.get("nac_max", 16))
     P.free_surface = int(d.get("free_surface", 1))
     P.eq13_printed = int(d.get("eq13_printed", 0))
+    P.viscous_heating = int(d.get("viscous_heating", 0))
     return P
 
 
@@ -263,6 +265,27 @@ def heat(params, nbr: Nbr, rho, mass, k, cp, T, bodies=(), body=None):
     return out, S, bq[:nb]
 
 
+def velocity_gradient(params, nbr: Nbr, v, rho, mass, vs=None):
+    """Velocity gradient G[i, a, b] = d v_a / d x_b (SPH gradient over fluid and
+    wall neighbours) and the per-particle sum of |pair terms|."""
+    n = len(nbr.xf)
+    vs = _c3(np.zeros((len(nbr.xs), 3)) if vs is None else vs)
+    G = np.zeros((n, 3, 3))
+    S = np.zeros(n)
+    f64 = lambda a_: np.ascontiguousarray(a_, dtype=np.float64)
+    lib().ora_velocity_gradient(C.byref(nbr.P), nbr.h, _p(_c3(v)), _p(f64(rho)), _p(f64(mass)), _p(vs),
+                                _p(G), _p(S))
+    return G, S
+
+
+def dissipation(params, G):
+    """Viscous dissipation Phi = 2 eta S:S per particle (eq. 23)."""
+    G = np.ascontiguousarray(G, dtype=np.float64).reshape(-1, 3, 3)
+    out = np.zeros(len(G))
+    lib().ora_dissipation(C.byref(make_params(params)), C.c_int64(len(G)), _p(G), _p(out))
+    return out
+
+
 def momentum(params, nbr: Nbr, v, rho, mass, nsv=None, vs=None, bodies=(), body=None):
     nb, B = _bodies_arg(bodies)
     n = len(nbr.xf)
@@ -358,7 +381,8 @@ class State:
         if want_rates:
             rates = Rates()
             for name, shape in (("a_visc", (nf, 3)), ("dTdt", (nf,)), ("sumW", (nf,)), ("S_visc", (nf,)),
-                                ("S_T", (nf,)), ("a_p", (nf, 3)), ("S_p", (nf,)), ("S_rho", (nf,))):
+                                ("S_T", (nf,)), ("a_p", (nf, 3)), ("S_p", (nf,)), ("S_rho", (nf,)),
+                                ("G", (nf, 3, 3)), ("phi", (nf,)), ("S_G", (nf,))):
                 arr = np.zeros(shape)
                 rates_np[name] = arr
                 setattr(rates, name, arr.ctypes.data)

@@ -536,6 +536,61 @@ void ora_heat(const ora_params* P, const ora_nbr* nb, int32_t nbody, const ora_b
 }
 
 /* ------------------------------------------------------------------------ */
+/* Viscous dissipation (Section 2.6, eq. 23): Phi = 2 eta S:S with the strain  */
+/* rate S = (G + G^T)/2 of the velocity gradient G = grad v.  The paper gives  */
+/* no discretisation; G is the SPH gradient of v with the same kernel         */
+/* gradient as every other sweep, grad_i W_ij = F_ij r_ij:                     */
+/*   G_i[a][b] = sum_j V_j (v_j - v_i)_a F_ij r_ij[b]                          */
+/*             + sum_w V_w (v_w - v_i)_a F_iw r_iw[b],                         */
+/* walls entering with their rigid-body velocity.  S_G[i] = sum over pairs of  */
+/* V |v_j - v_i| |F| |r| bounds the size of every term of every entry.         */
+/* ------------------------------------------------------------------------ */
+void ora_velocity_gradient(const ora_params* P, const ora_nbr* nb, const double* v,
+                           const double* rho, const double* mass, const double* vs, double* G,
+                           double* S) {
+  double Vw = P->dp * P->dp * P->dp;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < nb->nf; ++i) {
+    double g[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, s_abs = 0.0;
+    pgeo q;
+    for (int64_t p = nb->off_f[i]; p < nb->off_f[i + 1]; ++p) {
+      int64_t j = nb->idx_f[p];
+      pair_geom(nb->xb + 3 * i, nb->xb + 3 * j, nb->h, &q);
+      double Vj = mass[j] / rho[j];
+      double dv[3] = {v[3 * j] - v[3 * i], v[3 * j + 1] - v[3 * i + 1], v[3 * j + 2] - v[3 * i + 2]};
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) g[3 * a + b] += Vj * dv[a] * q.F * q.r[b];
+      s_abs += Vj * sqrt(dot3(dv, dv)) * fabs(q.F) * q.rr;
+    }
+    for (int64_t p = nb->off_s[i]; p < nb->off_s[i + 1]; ++p) {
+      int64_t w = nb->idx_s[p];
+      pair_geom(nb->xb + 3 * i, nb->xsb + 3 * w, nb->h, &q);
+      double dv[3] = {vs[3 * w] - v[3 * i], vs[3 * w + 1] - v[3 * i + 1], vs[3 * w + 2] - v[3 * i + 2]};
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) g[3 * a + b] += Vw * dv[a] * q.F * q.r[b];
+      s_abs += Vw * sqrt(dot3(dv, dv)) * fabs(q.F) * q.rr;
+    }
+    for (int k = 0; k < 9; ++k) G[9 * i + k] = g[k];
+    if (S) S[i] = s_abs;
+  }
+}
+
+/* Phi_i = 2 eta S:S, S = (G + G^T)/2, eta = rho0 nu (eq. 23). */
+void ora_dissipation(const ora_params* P, int64_t nf, const double* G, double* phi) {
+  double eta = P->rho0 * P->nu;
+  for (int64_t i = 0; i < nf; ++i) {
+    const double* g = G + 9 * i;
+    double ss = 0.0;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        double sab = 0.5 * (g[3 * a + b] + g[3 * b + a]);
+        ss += sab * sab;
+      }
+    phi[i] = 2.0 * eta * ss;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Riemann momentum (Section 2.3, eq. 10-12; walls Section 2.5, eq. 16-19)    */
 /* ------------------------------------------------------------------------ */
 static double eos_p(const ora_params* P, double rho) { return P->c0 * P->c0 * (rho - P->rho0); }
@@ -805,6 +860,7 @@ int ora_step(const ora_params* P, int32_t nbody, const ora_body* B, int64_t nf, 
          *cpf = malloc(sizeof(double) * nfz), *sumW = malloc(sizeof(double) * nfz),
          *av = malloc(sizeof(double) * 3 * nfz), *ap = malloc(sizeof(double) * 3 * nfz),
          *dTdt = malloc(sizeof(double) * nfz);
+  double *G = NULL, *phi = NULL, *SG = NULL;
   double* bq = calloc((size_t)(nbody > 0 ? nbody : 1), sizeof(double));
   double* bFv = calloc(3 * (size_t)(nbody > 0 ? nbody : 1), sizeof(double));
   double* bTv = calloc(3 * (size_t)(nbody > 0 ? nbody : 1), sizeof(double));
@@ -814,6 +870,12 @@ int ora_step(const ora_params* P, int32_t nbody, const ora_body* B, int64_t nf, 
   ora_nbr* nb = NULL;
   if (!xs || !nsv || !vs || !mass || !kf || !cpf || !sumW || !av || !ap || !dTdt || !bq || !bFv ||
       !bTv || !bFp || !bTp || !kFp) { rc = ORA_ERR_OOM; goto done; }
+  if (P->viscous_heating) {
+    G = malloc(sizeof(double) * 9 * nfz);
+    phi = malloc(sizeof(double) * nfz);
+    SG = malloc(sizeof(double) * nfz);
+    if (!G || !phi || !SG) { rc = ORA_ERR_OOM; goto done; }
+  }
   for (int64_t i = 0; i < nf; ++i) { mass[i] = m0; kf[i] = P->k_f; cpf[i] = P->cp_f; }
 
   /* 1. bodies at t_n */
@@ -837,6 +899,16 @@ int ora_step(const ora_params* P, int32_t nbody, const ora_body* B, int64_t nf, 
   /* 6. viscous and heat rates, frozen for the step */
   ora_viscous(P, nb, nbody, B, body, v, rho, mass, vs, av, rates ? rates->S_visc : NULL, bFv, bTv);
   ora_heat(P, nb, nbody, B, body, rho, mass, kf, cpf, T, dTdt, rates ? rates->S_T : NULL, bq);
+  /* viscous dissipation heating, eq. 23 (off in the paper's model) */
+  ksum kd = {0, 0};
+  if (P->viscous_heating) {
+    ora_velocity_gradient(P, nb, v, rho, mass, vs, G, SG);
+    ora_dissipation(P, nf, G, phi);
+    for (int64_t i = 0; i < nf; ++i) {
+      dTdt[i] += phi[i] / (rho[i] * cpf[i]);
+      kadd(&kd, (mass[i] / rho[i]) * phi[i]);
+    }
+  }
   /* 7. acoustic sub-steps */
   for (int32_t s = 0; s < n_ac; ++s) {
     for (int64_t i = 0; i < nf; ++i) {
@@ -880,16 +952,23 @@ int ora_step(const ora_params* P, int32_t nbody, const ora_body* B, int64_t nf, 
     rep->vmax = tot[4]; rep->mass = tot[0]; rep->kinetic = tot[1]; rep->thermal = tot[2];
     rep->mass_proxy = tot[3];
     rep->heat_step = dt_ad * kval(&kq);
+    rep->diss_step = dt_ad * kval(&kd);
   }
   if (rates) {
     if (rates->a_visc) memcpy(rates->a_visc, av, sizeof(double) * 3 * (size_t)nf);
     if (rates->dTdt) memcpy(rates->dTdt, dTdt, sizeof(double) * (size_t)nf);
     if (rates->sumW) memcpy(rates->sumW, sumW, sizeof(double) * (size_t)nf);
     if (rates->a_p) memcpy(rates->a_p, ap, sizeof(double) * 3 * (size_t)nf);
+    if (P->viscous_heating) {
+      if (rates->G) memcpy(rates->G, G, sizeof(double) * 9 * (size_t)nf);
+      if (rates->phi) memcpy(rates->phi, phi, sizeof(double) * (size_t)nf);
+      if (rates->S_G) memcpy(rates->S_G, SG, sizeof(double) * (size_t)nf);
+    }
   }
 done:
   ora_nbr_free(nb);
   free(xs); free(nsv); free(vs); free(mass); free(kf); free(cpf); free(sumW); free(av); free(ap);
   free(dTdt); free(bq); free(bFv); free(bTv); free(bFp); free(bTp); free(kFp);
+  free(G); free(phi); free(SG);
   return rc;
 }

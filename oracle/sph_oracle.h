@@ -30,6 +30,8 @@ typedef struct {
   int32_t nac_max;         /* cap on acoustic sub-steps per advection step */
   int32_t free_surface;    /* 1: eq. 14 re-initialisation, 0: eq. 15 */
   int32_t eq13_printed;    /* 1: take eq. 13's printed sign (reading study only) */
+  int32_t viscous_heating; /* 1: add the dissipation Phi/(rho cp) of eq. 23 to dT/dt */
+  int32_t pad;
 } ora_params;
 
 typedef struct { double center[3], axis[3], omega, T, k; } ora_body;
@@ -38,6 +40,7 @@ typedef struct {
   double t, dt_ad, dt;
   int32_t n_ac, pad;
   double vmax, mass, kinetic, thermal, heat_step, mass_proxy;
+  double diss_step;        /* dt_ad * sum V_i Phi_i (0 without viscous heating) */
 } ora_report;
 
 typedef struct { double force[3], torque[3], torque_axis, power, heat_rate; } ora_body_report;
@@ -52,6 +55,9 @@ typedef struct {
   double *a_p;      /* nf*3 pressure acceleration of the last sub-step */
   double *S_p;      /* nf   sum of |pressure pair terms| of the last sub-step */
   double *S_rho;    /* nf   sum of |continuity pair terms| of the last sub-step */
+  double *G;        /* nf*9 velocity gradient G[a][b] = d v_a / d x_b (viscous heating only) */
+  double *phi;      /* nf   dissipation 2 eta S:S (viscous heating only) */
+  double *S_G;      /* nf   sum of |velocity-gradient pair terms| (viscous heating only) */
 } ora_rates;
 
 /* Neighbour sets and the frozen pair geometry of one advection step. */
@@ -102,6 +108,13 @@ void ora_momentum(const ora_params* P, const ora_nbr* nb, int32_t nbody, const o
 void ora_continuity(const ora_params* P, const ora_nbr* nb, const double* v,
                     const double* rho, const double* mass, const double* nsv, const double* vs,
                     double* drho, double* S);
+/* Velocity gradient G (nf*9, G[a][b] = d v_a / d x_b) from the SPH gradient over
+   fluid and wall neighbours, and the viscous dissipation Phi = 2 eta S:S of
+   eq. 23 with S = (G + G^T)/2; S (nullable) = sum of |pair terms| per particle. */
+void ora_velocity_gradient(const ora_params* P, const ora_nbr* nb, const double* v,
+                           const double* rho, const double* mass, const double* vs, double* G,
+                           double* S);
+void ora_dissipation(const ora_params* P, int64_t nf, const double* G, double* phi);
 /* pair forces on i from j: pressure part f[0..2], viscous part f[3..5] */
 void ora_pair_force(const ora_params* P, const double* xi, const double* xj, const double* vi,
                     const double* vj, double rhoi, double rhoj, double mi, double mj,

@@ -523,3 +523,91 @@ def test_contact_factor_limits(ora):
     xf1, xs1 = _wall_under_fluid(depth=1)
     z1 = ora.contact_factor(p, xf1, rho[: len(xf1)], xs1)[0]
     assert 0.0 < z1 < 1.0
+
+
+# --------------------------------------------------------------------------
+# Viscous dissipation (Section 2.6, eq. 23): velocity gradient and Phi
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("hod", ["1.3", "1.0"])
+def test_velocity_gradient_linear_field(ora, hod):
+    """SPH gradient of v = A x on a perfect lattice: G = M A entry by entry
+    (M the lattice first moment); A is not symmetric, so a transposed index
+    or a flipped sign fails."""
+    g = gold("kernel_wendland_c2.json")["lattice"][hod]
+    p, x, nb, c = _lattice_setup(ora, float(hod))
+    A = np.array([[0.3, 0.1, -0.2], [0.05, -0.4, 0.2], [0.1, 0.3, 0.7]])
+    v = x @ A.T + np.array([0.2, -0.1, 0.05])
+    rho = np.full(len(x), 1000.0)
+    G, S = ora.velocity_gradient(p, nb, v, rho, rho.copy())
+    assert np.max(np.abs(G[c] - g["first_moment"] * A)) < 1e-6
+    # a uniform velocity has no gradient
+    G0, _ = ora.velocity_gradient(p, nb, np.tile([0.3, -0.2, 0.1], (len(x), 1)), rho, rho.copy())
+    assert np.all(G0[c] == 0.0)
+
+
+@pytest.mark.parametrize("hod", ["1.3", "1.0"])
+def test_dissipation_closed_forms(ora, hod):
+    """Phi = 2 eta S:S: simple shear v = (gamma z, 0, 0) gives eta (M gamma)^2,
+    uniform expansion v = a x gives 6 eta (M a)^2, a rigid rotation gives 0."""
+    g = gold("kernel_wendland_c2.json")["lattice"][hod]
+    M = g["first_moment"]
+    p, x, nb, c = _lattice_setup(ora, float(hod))
+    eta = p["rho0"] * p["nu"]
+    rho = np.full(len(x), 1000.0)
+    xc = x - x[c]
+    gam = 3.0
+    v = np.zeros_like(x)
+    v[:, 0] = gam * xc[:, 2]
+    G, _ = ora.velocity_gradient(p, nb, v, rho, rho.copy())
+    # the golden moment carries six digits: 1e-6 relative on M^2
+    assert ora.dissipation(p, G)[c] == pytest.approx(eta * (M * gam) ** 2, rel=2e-6)
+    a = 0.7
+    G, _ = ora.velocity_gradient(p, nb, a * xc, rho, rho.copy())
+    assert ora.dissipation(p, G)[c] == pytest.approx(6.0 * eta * (M * a) ** 2, rel=2e-6)
+    w = np.array([0.3, -1.1, 0.4])
+    G, S = ora.velocity_gradient(p, nb, np.cross(w, xc), rho, rho.copy())
+    assert np.allclose(G[c], -G[c].T, atol=1e-12 * S[c])
+    assert ora.dissipation(p, G)[c] <= 1e-20 * eta * S[c] ** 2
+
+
+def test_velocity_gradient_wall_terms(ora):
+    """Fluid above a wall lattice, v = A x in both: a fluid site whose support
+    reaches into the wall sees the full lattice, so G = M A there too; with the
+    wall at rest instead, the wall terms pull G away from M A."""
+    g = gold("kernel_wendland_c2.json")["lattice"]["1.3"]
+    n = 12
+    p = lattice_params(1.3, n)
+    x = cases.lattice_block(n)
+    wall = x[:, 2] < 4.0
+    xf, xs = x[~wall], x[wall]
+    nb = ora.Nbr(p, xf, xs)
+    A = np.array([[0.1, 0.4, -0.3], [0.2, 0.1, 0.6], [-0.5, 0.2, 0.3]])
+    rho = np.full(len(xf), 1000.0)
+    i = int(np.argmin(np.sum((xf - np.array([6.5, 6.5, 4.5])) ** 2, axis=1)))
+    G, _ = ora.velocity_gradient(p, nb, xf @ A.T, rho, rho.copy(), vs=xs @ A.T)
+    assert np.max(np.abs(G[i] - g["first_moment"] * A)) < 1e-6
+    G2, _ = ora.velocity_gradient(p, nb, xf @ A.T, rho, rho.copy(), vs=np.zeros_like(xs))
+    assert np.max(np.abs(G2[i] - g["first_moment"] * A)) > 0.1
+
+
+def test_step_heat_balance_with_viscous_heating(ora):
+    """With eq. 23 switched on, the thermal energy gained in a step equals the
+    wall heat plus the dissipated work dt_ad sum V_i Phi_i >= 0; switched off,
+    the dissipated work is zero and the step is unchanged."""
+    c = cases.tank_c1()
+    rng = np.random.default_rng(5)
+    c.vf = 0.5 * np.sin(c.xf[:, [1, 2, 0]] * 90.0) + 0.05 * rng.standard_normal(c.vf.shape)
+    mcp = 2000.0 * 870.0 * (2e-3) ** 3
+    on = ora.State(c, viscous_heating=1)
+    off = ora.State(c)
+    for _ in range(2):
+        T0 = on.T.copy()
+        r = on.step(want_rates=True)
+        r0 = off.step()
+        dE = mcp * (on.T - T0)
+        assert r["diss_step"] > 0.0 and r0["diss_step"] == 0.0
+        assert abs(math.fsum(dE) - (r["heat_step"] + r["diss_step"])) <= 1e-10 * math.fsum(np.abs(dE))
+        assert np.all(r["rates"]["phi"] >= 0.0)
+    np.testing.assert_array_equal(on.v, off.v)
+    assert np.all(on.T >= off.T - 1e-12 * np.abs(off.T))
