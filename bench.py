@@ -122,7 +122,7 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a), q)) if len(a) else None
 
 
-def cpu_baseline(case, steps=2):
+def cpu_baseline(case, steps=6):
     """The FP64 oracle on the host cores, on a bounded sample of the same workload."""
     from oracle import oracle as O
     O.build(force=False)
@@ -317,8 +317,10 @@ def main():
     ap.add_argument("--dp", type=float, default=1.5e-3, help="particle spacing of the gearbox proxy")
     ap.add_argument("--workload", default="gearbox", choices=["gearbox", "full"],
                     help="gearbox: the 1.5 mm proxy at 300 rad/s (default); full: the 1 mm proxy at 600 rad/s")
+    ap.add_argument("--viscous-heating", action="store_true",
+                    help="add the viscous dissipation heating of eq. 23 (off in the paper's model)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--calib-copy", action="store_true", help="run one 1 GiB device copy (counter calibration)")
     ap.add_argument("--serve", action="store_true", help="serving sweep instead of the single-solve bench")
     ap.add_argument("--serve-n", type=int, default=64)
@@ -368,6 +370,8 @@ def main():
     else:
         om, imm, nu, dp = 300.0, 0.030, 1e-4, args.dp
     case = cases.gearbox(seed=0, dp=dp, omega_big=om, immersion=imm, nu=nu)
+    if args.viscous_heating:
+        case.params["viscous_heating"] = 1
     log(f"case: nf={case.nf} ns={case.ns} generated in {time.perf_counter() - t0:.1f} s")
     s = sph.Solver(case, precision=args.precision)
     log("initialised")
@@ -484,7 +488,8 @@ def main():
         "dtype": {"mixed": "f32+f64", "fp64": "f64", "fp32": "f32"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"gearbox proxy dp={dp * 1e3:.2f} mm, two toothed disks 20/40 teeth at "
-                               f"-{2 * om:.0f}/{om:.0f} rad/s, {imm * 1e3:.0f} mm immersion, nu={nu:g}",
+                               f"-{2 * om:.0f}/{om:.0f} rad/s, {imm * 1e3:.0f} mm immersion, nu={nu:g}"
+                               + (", viscous dissipation heating" if args.viscous_heating else ""),
                    "n_fluid": case.nf, "n_solid": case.ns, "n_ac_last": n_ac, "pairs_per_sweep": int(pairs),
                    "pair_sweeps_per_step": round(sweeps, 3), "precision": args.precision, "parallelism": "single GPU"},
         "sweep_latency": sweep_lat,

@@ -82,6 +82,10 @@ typedef struct {
   int32_t precision;    /* SPH_PREC_* */
   int32_t max_fluid_nbrs; /* neighbour row capacity, 0 = 128 */
   int32_t max_solid_nbrs; /* solid neighbour row capacity, 0 = 96 */
+  int32_t viscous_heating; /* 1: add the viscous dissipation Phi = 2 eta S:S of eq. 23 (S the strain
+                              rate from the SPH velocity gradient over fluid and wall neighbours) to
+                              dT/dt as Phi/(rho cp); 0: the paper's model, conduction only */
+  int32_t reserved;     /* must be 0 */
 } sph_params;
 
 /* A rigid body turning at a prescribed speed about a fixed axis; its solid
@@ -105,6 +109,8 @@ typedef struct {
   double heat_total;    /* sum of heat_step since init */
   double mass_proxy;    /* sum rho dp^3 (drift of the continuity equation) */
   int64_t substeps;     /* acoustic sub-steps completed since init */
+  double diss_step;     /* dt_ad * sum V Phi: heat dissipated in the last step (0 without viscous heating) */
+  double diss_total;    /* sum of diss_step since init */
 } sph_report;
 
 /* Per-body report: the last step's values (viscous part frozen for the step,

@@ -75,6 +75,8 @@ static int make_plan(const sph_params* p, int prec, int64_t nf, int64_t ns, Plan
   if (nf < 1 || nf >= (int64_t)1 << 31 || ns < 0 || ns >= (int64_t)1 << 31)
     return fail(SPH_ERR_ARG, "particle counts out of range");
   if (p->fixed_dt_ad > 0 && p->fixed_nac < 1) return fail(SPH_ERR_ARG, "fixed_nac must be >= 1");
+  if (p->viscous_heating != 0 && p->viscous_heating != 1) return fail(SPH_ERR_ARG, "viscous_heating must be 0 or 1");
+  if (p->reserved != 0) return fail(SPH_ERR_ARG, "reserved must be 0");
   const double h = p->h_over_dp * p->dp;
   const double cs = 2.0 * h;
   int64_t ncell = 1;
@@ -186,7 +188,7 @@ static size_t carve(const Plan& P, void* base, SlotDesc* d) {
   C.take(D.vmax_part, nbf * 4);
   C.take(D.visc_part, nbf * NB * 7 * 8);
   C.take(D.press_part, nbf * NB * 6 * 8);
-  C.take(D.glob_part, nbf * NGLOB * 8);
+  C.take(D.glob_part, nbf * (NGLOB + 1) * 8);
   return (C.off + 255) & ~(size_t)255;
 }
 
@@ -420,6 +422,7 @@ static void tab_for(sph_pool* P, const std::vector<int>& slots, LaunchTab& T) {
   for (int d = 0; d < NDOM; ++d) T.blk0[d][0] = 0;
   for (size_t k = 0; k < slots.size(); ++k) {
     T.slot[k] = slots[k];
+    if (P->slots[slots[k]].d.diss) T.flags |= TAB_DISS;
     const Plan& pl = P->slots[slots[k]].plan;
     for (int d = 0; d < NDOM; ++d) T.blk0[d][k + 1] = T.blk0[d][k] + pl.nblk[d];
   }
@@ -598,6 +601,7 @@ static int admit(sph_pool* P, const sph_params* p, int32_t nbody, const sph_body
   D.nbody = nbody;
   for (int a = 0; a < 3; ++a) D.dims[a] = pl.dims[a];
   D.free_surface = p->free_surface ? 1 : 0;
+  D.diss = p->viscous_heating;
   D.fixed_nac = p->fixed_nac;
   for (int d = 0; d < NDOM; ++d) D.nblk[d] = pl.nblk[d];
   D.rowlen_f = pl.rowlen_f;

@@ -20,8 +20,10 @@ enum Flag { F_DOMAIN = 1, F_NONFINITE = 2, F_CAPACITY = 4 };
 
 // Blocks of one launch: the slots it covers and, per domain, the prefix of
 // their block counts.  Passed by value (kernel argument segment).
+constexpr int32_t TAB_DISS = 1;   // some slot of the launch has viscous heating on
+
 struct LaunchTab {
-  int32_t n;
+  int32_t n, flags;
   int32_t slot[MAX_SLOTS];
   int32_t blk0[NDOM][MAX_SLOTS + 1];
 };
@@ -32,7 +34,7 @@ struct SlotCtl {
   int64_t step, target, substeps;
   int32_t n_ac;
   uint32_t flags;
-  double heat_total;
+  double heat_total, diss_total;
   double cum[NB][3];     // time integrals: axial torque, energy, heat
   sph_report rep;
   sph_body_report brep[NB];
@@ -51,7 +53,7 @@ struct SlotDesc {
   int32_t nf, ns, ncells, nslices;
   int32_t kf, ks, nbody, nac_bound;
   int32_t dims[3];
-  int32_t free_surface, fixed_nac, pad0;
+  int32_t free_surface, fixed_nac, diss;   // diss: viscous dissipation heating on
   int32_t nblk[NDOM];
   int64_t rowlen_f, rowlen_s;          // nslices * k * 64
   double dp, h, rho0, c0, eta, k_f, cp_f, mass, vol_w, S0, cut2, cs;
@@ -94,7 +96,7 @@ struct SlotDesc {
   float *vmax_part;
   double *visc_part;    // [NB * 7]: force(3) torque(3) heat
   double *press_part;   // [NB * 6]: sum over sub-steps of force(3) torque(3)
-  double *glob_part;    // [NGLOB]
+  double *glob_part;    // [NGLOB + 1]: the globals, then the dissipated power
 };
 
 // Launch one kernel of the step.  prec: SPH_PREC_*; kid: SPH_K_*; sub: the

@@ -1093,18 +1093,35 @@ __global__ __launch_bounds__(BLOCK) void k_dt(const SlotDesc* table, LaunchTab t
 }
 
 
+// G[a][b] += c dv_a r_b: one pair's term of the SPH velocity gradient
+template <class Real>
+__device__ __forceinline__ void grad_add(Real* G, Real c, Real dx, Real dy, Real dz, Real rx, Real ry, Real rz) {
+  const Real d[3] = {c * dx, c * dy, c * dz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    G[3 * a] += d[a] * rx;
+    G[3 * a + 1] += d[a] * ry;
+    G[3 * a + 2] += d[a] * rz;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // K: viscous acceleration (eq. 10 fluid-fluid, eq. 18 fluid-wall) and heat
 // conduction rate (eq. 22), both frozen for the advection step.  Per-block
 // partials: viscous force and torque on each body and its heat flow into the
 // fluid.  Also clears this block's pressure-force accumulators.
+// DISS: the launch holds a slot with viscous dissipation heating (eq. 23):
+// the velocity gradient G[a][b] = sum V_j (v_j - v_i)_a F_ij r_ij[b] over fluid
+// and wall neighbours gives Phi = 2 eta S:S, S = (G + G^T)/2, added to the
+// heat rate as Phi/(rho cp); per-block partial of sum V_i Phi_i.
 // ---------------------------------------------------------------------------
-template <class P>
+template <class P, bool DISS>
 __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, LaunchTab tab) {
   typedef typename P::Real Real;
   typedef typename P::Temp Temp;
   typedef typename P::Real4 Real4;
   __shared__ double lds[4 * NB * 7];
+  __shared__ double lds_d[BLOCK / WAVE];
   SLOT_PROLOGUE(DOM_FLUID);
   const int nf = S.nf;
   const int i = lb * BLOCK + threadIdx.x;
@@ -1113,6 +1130,7 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
   BodyAcc<7> acc;
   acc.init();
   bool wall = false;
+  double vphi = 0.0;   // V_i Phi_i
   if (i < nf) {
     const GLB Real4* vr = gpc<Real4>(S.vr);
     const GLB Temp* T = gpc<Temp>(S.T);
@@ -1127,6 +1145,9 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
     const Real c2 = (Real)(2.0 * S.eta) * rcp(rhoi);   // 2 eta V_i / m_i
     const Real Kff = (Real)(4.0 * S.k_f * S.k_f / (S.k_f + S.k_f));
     Real ax = 0, ay = 0, az = 0, hs = 0;
+    Real G[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) G[q] = 0;
     const int lane = i & (WAVE - 1);
     const int64_t slice = i >> 6;
     {
@@ -1162,6 +1183,7 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
           ay += cv * (vi.y - vj[u].y);
           az += cv * (vi.z - vj[u].z);
           hs += Vj * Kff * (Real)(Ti - Tj[u]) * Fk;
+          if (DISS) grad_add(G, Vj * Fk, vj[u].x - vi.x, vj[u].y - vi.y, vj[u].z - vi.z, rx, ry, rz);
         }
       }
     }
@@ -1206,6 +1228,7 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
         const Real Kiw = (Real)(4.0 * S.k_f * S.bk[b] / (S.k_f + S.bk[b]));
         const Real term = Vw * Kiw * (Real)(Ti - (Temp)S.bT[b]) * Fk;
         hs += term;
+        if (DISS) grad_add(G, Vw * Fk, vq.x - vi.x, vq.y - vi.y, vq.z - vi.z, rx, ry, rz);
         // force of the fluid on the body is -m_i times this pair's acceleration
         const double gx = -(double)m * fx, gy = -(double)m * fy, gz = -(double)m * fz;
         const double lx = lq.x, ly = lq.y, lz = lq.z;
@@ -1213,6 +1236,15 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
                                    (double)m * (double)S.cp_f * (double)(rc * term)};
         if (!acc.add(b, contrib)) raise_flag(S, F_CAPACITY);
         }
+      }
+      if (DISS && S.diss) {
+        // Phi = 2 eta S:S with S = (G + G^T)/2
+        const Real sxy = (Real)0.5 * (G[1] + G[3]), sxz = (Real)0.5 * (G[2] + G[6]),
+                   syz = (Real)0.5 * (G[5] + G[7]);
+        const Real ss = (G[0] * G[0] + G[4] * G[4] + G[8] * G[8]) + (Real)2 * ((sxy * sxy + sxz * sxz) + syz * syz);
+        const Real phi = (Real)(2.0 * S.eta) * ss;
+        hs += phi;
+        vphi = (double)(m * rcp(rhoi)) * (double)phi;
       }
       Real4 a;
       a.x = ax;
@@ -1226,6 +1258,13 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
     block_body_reduce<7>(acc, S.nbody, S.visc_part, nbf, lb, false, lds);
   else if (threadIdx.x < NB * 7)
     S.visc_part[(size_t)threadIdx.x * nbf + lb] = 0.0;
+  if (DISS && S.diss) {
+    const double sw = wave_sum(vphi);
+    if ((threadIdx.x & (WAVE - 1)) == 0) lds_d[threadIdx.x / WAVE] = sw;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      S.glob_part[(size_t)NGLOB * nbf + lb] = ((lds_d[0] + lds_d[1]) + lds_d[2]) + lds_d[3];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1573,11 +1612,13 @@ __global__ __launch_bounds__(BLOCK) void k_end(const SlotDesc* table, LaunchTab 
 // ---------------------------------------------------------------------------
 constexpr int FINAL_BLOCK = 1024;
 __global__ __launch_bounds__(FINAL_BLOCK) void k_final(const SlotDesc* table, LaunchTab tab) {
-  __shared__ double res[NGLOB + NB * 13];
+  __shared__ double res[NGLOB + NB * 13 + 1];
   SLOT_PROLOGUE(DOM_SLOT);
   (void)lb;
   const int nblk = S.nblk[DOM_FLUID];
-  const int nq = NGLOB + S.nbody * 13;
+  // quantities: the globals, 13 per body, then the dissipated power if on
+  const int nq = NGLOB + S.nbody * 13 + (S.diss ? 1 : 0);
+  const int q_diss = NGLOB + S.nbody * 13;
   const int wv = threadIdx.x / WAVE, ln = threadIdx.x % WAVE;
   for (int qi = wv; qi < nq; qi += FINAL_BLOCK / WAVE) {
     // quantity qi: global k, or body b component c (7 viscous then 6 pressure)
@@ -1587,6 +1628,8 @@ __global__ __launch_bounds__(FINAL_BLOCK) void k_final(const SlotDesc* table, La
     if (qi < NGLOB) {
       src = S.glob_part + (size_t)qi * nblk;
       is_max = qi == 4;
+    } else if (qi == q_diss) {
+      src = S.glob_part + (size_t)NGLOB * nblk;
     } else {
       const int b = (qi - NGLOB) / 13, c = (qi - NGLOB) % 13;
       src = c < 7 ? S.visc_part + (size_t)(b * 7 + c) * nblk : S.press_part + (size_t)(b * 6 + c - 7) * nblk;
@@ -1648,6 +1691,8 @@ __global__ __launch_bounds__(FINAL_BLOCK) void k_final(const SlotDesc* table, La
   C->substeps += C->n_ac;
   const double hs = tad * qsum;
   C->heat_total += hs;
+  const double ds = S.diss ? tad * res[q_diss] : 0.0;
+  C->diss_total += ds;
   sph_report& R = C->rep;
   R.t = C->t;
   R.step = C->step;
@@ -1662,7 +1707,9 @@ __global__ __launch_bounds__(FINAL_BLOCK) void k_final(const SlotDesc* table, La
   R.heat_step = hs;
   R.heat_total = C->heat_total;
   R.substeps = C->substeps;
-  finite = finite && isfinite(res[1]) && isfinite(res[2]) && isfinite(res[3]);
+  R.diss_step = ds;
+  R.diss_total = C->diss_total;
+  finite = finite && isfinite(res[1]) && isfinite(res[2]) && isfinite(res[3]) && isfinite(ds);
   if (!finite) C->flags |= F_NONFINITE;
   R.flags = (int32_t)C->flags;
 }
@@ -1713,7 +1760,10 @@ static hipError_t launch_p(int kid, int which, int sub, const SlotDesc* T, const
     case SPH_K_SUMW: hipLaunchKernelGGL(k_sumw<P>, g, b, 0, st, T, L); break;
     case SPH_K_CONTACT: hipLaunchKernelGGL(k_contact<P>, g, b, 0, st, T, L); break;
     case SPH_K_DT: hipLaunchKernelGGL(k_dt, g, b, 0, st, T, L); break;
-    case SPH_K_VISC_HEAT: hipLaunchKernelGGL(k_visc_heat<P>, g, b, 0, st, T, L); break;
+    case SPH_K_VISC_HEAT:
+      if (L.flags & TAB_DISS) hipLaunchKernelGGL((k_visc_heat<P, true>), g, b, 0, st, T, L);
+      else hipLaunchKernelGGL((k_visc_heat<P, false>), g, b, 0, st, T, L);
+      break;
     case SPH_K_HALF_A: hipLaunchKernelGGL(k_half_a<P>, g, b, 0, st, T, L, sub); break;
     case SPH_K_MOMENTUM: hipLaunchKernelGGL(k_momentum<P>, g, b, 0, st, T, L, sub); break;
     case SPH_K_CONTINUITY: hipLaunchKernelGGL(k_continuity<P>, g, b, 0, st, T, L, sub); break;

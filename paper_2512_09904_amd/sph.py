@@ -40,7 +40,8 @@ class Params(C.Structure):
                 ("grid_lo", C.c_double * 3), ("grid_hi", C.c_double * 3), ("cfl_ad", C.c_double),
                 ("cfl_ac", C.c_double), ("fixed_dt_ad", C.c_double), ("fixed_nac", C.c_int32),
                 ("nac_max", C.c_int32), ("free_surface", C.c_int32), ("precision", C.c_int32),
-                ("max_fluid_nbrs", C.c_int32), ("max_solid_nbrs", C.c_int32)]
+                ("max_fluid_nbrs", C.c_int32), ("max_solid_nbrs", C.c_int32), ("viscous_heating", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class Body(C.Structure):
@@ -52,7 +53,8 @@ class Report(C.Structure):
     _fields_ = [("t", C.c_double), ("step", C.c_int64), ("n_ac", C.c_int32), ("flags", C.c_int32),
                 ("dt_ad", C.c_double), ("dt", C.c_double), ("vmax", C.c_double), ("mass", C.c_double),
                 ("kinetic", C.c_double), ("thermal", C.c_double), ("heat_step", C.c_double),
-                ("heat_total", C.c_double), ("mass_proxy", C.c_double), ("substeps", C.c_int64)]
+                ("heat_total", C.c_double), ("mass_proxy", C.c_double), ("substeps", C.c_int64),
+                ("diss_step", C.c_double), ("diss_total", C.c_double)]
 
 
 class BodyReport(C.Structure):
@@ -154,6 +156,7 @@ def params_struct(params: dict, precision="mixed", fixed_dt_ad=None, fixed_nac=N
     P.precision = PREC[precision] if isinstance(precision, str) else int(precision)
     P.max_fluid_nbrs = int(d.get("max_fluid_nbrs", 0))
     P.max_solid_nbrs = int(d.get("max_solid_nbrs", 0))
+    P.viscous_heating = int(d.get("viscous_heating", 0))
     return P
 
 

@@ -436,3 +436,93 @@ def test_contact_factor_leaves_the_solve_unchanged(sph):
     for k in ("x", "v", "rho", "T"):
         assert np.array_equal(ga[k], gb[k]), k
     assert ra["bodies"][1]["torque_axis"] == rb["bodies"][1]["torque_axis"]
+
+
+# ---------------------------------------------------------------------------
+# viscous dissipation heating (eq. 23), an option off in the paper's model
+# ---------------------------------------------------------------------------
+
+def _sheared(case, seed):
+    """The tank with a smooth velocity field: |v| up to 0.2 Umax, gradients of
+    order 30 Umax per metre, so the dissipation is far above rounding."""
+    rng = np.random.default_rng(seed)
+    u = case.meta["umax"]
+    case.vf = 0.2 * u * np.sin(case.xf[:, [1, 2, 0]] * 150.0 + rng.uniform(0.0, 6.28, 3))
+    return case
+
+
+@pytest.mark.parametrize("precision,bar,tau", [("mixed", 1e-5, 1e-5), ("fp64", 1e-10, 1e-11)])
+def test_viscous_heating_parity(sph, ora, precision, bar, tau):
+    """One step with eq. 23 on from identical sheared state, fixed dt: the
+    state within the one-step bars; per particle, the heat rate within
+    tau (S_T + dPhi) with dPhi the propagated bound of G's rounding
+    (|dG_ab| <= tau S_G, S = (G + G^T)/2, rho >= 0.9 rho0); the dissipated
+    heat and the step's heat balance against the oracle."""
+    c = _sheared(ragged_tank(seed=2), 7)
+    say("viscous heating parity", precision, c.nf)
+    dt, nac = fixed_dt(c)
+    o = ora.State(c, fixed_dt_ad=dt, fixed_nac=nac, viscous_heating=1)
+    ro = o.step(want_rates=True)
+    s = sph.Solver(c, precision=precision, fixed_dt_ad=dt, fixed_nac=nac, viscous_heating=1)
+    s.step(1)
+    rg = s.reduce()
+    g = s.get_fluid()
+    fid = s.dump("fluid_ids").astype(np.int64)
+    st = s.dump("fluid_state").reshape(c.nf, 16)[np.argsort(fid)]
+    s.close()
+    e = _normalised_errors(c, o, g)
+    say("normalised errors", precision, e)
+    assert max(e.values()) <= bar, e
+    R = ro["rates"]
+    p = c.params
+    eta, cp = p["rho0"] * p["nu"], p["cp_f"]
+    Gs = 0.5 * (R["G"] + np.transpose(R["G"], (0, 2, 1)))
+    fro = np.sqrt(np.sum(Gs * Gs, axis=(1, 2)))
+    dphi = 2.0 * eta * (6.0 * tau * R["S_G"] * fro + 9.0 * (tau * R["S_G"]) ** 2) / (0.9 * p["rho0"] * cp)
+    dT = np.abs(st[:, 15] - R["dTdt"])
+    assert np.all(dT <= tau * R["S_T"] + dphi + 1e-300), np.max(dT / (tau * R["S_T"] + dphi + 1e-300))
+    # the dissipation is a visible part of the heat rate here
+    assert np.median(R["phi"] / (p["rho0"] * cp)) > 1e3 * tau * np.median(R["S_T"])
+    assert ro["diss_step"] > 0.0
+    assert rg["diss_step"] == pytest.approx(ro["diss_step"], rel=1e-5 if precision == "mixed" else 1e-10)
+    assert rg["diss_total"] == rg["diss_step"]
+    assert rg["heat_step"] == pytest.approx(ro["heat_step"], rel=1e-5 if precision == "mixed" else 1e-10)
+    # heat balance of the GPU step: thermal energy gained = wall heat + dissipated work
+    mcp = p["rho0"] * p["dp"] ** 3 * cp
+    E0 = math.fsum(mcp * c.Tf)
+    scale = dt * math.fsum(mcp * (R["S_T"] + R["phi"] / (0.9 * p["rho0"] * cp))) + \
+        c.nf * 4.0 * np.finfo(float).eps * np.max(c.Tf) * mcp
+    gap = abs(rg["thermal"] - E0 - rg["heat_step"] - rg["diss_step"])
+    assert gap <= (1e-5 if precision == "mixed" else 1e-10) * scale + 8.0 * np.finfo(float).eps * abs(E0), gap
+
+
+def test_viscous_heating_off_is_unchanged(sph):
+    """With eq. 23 off, the report's dissipation is zero and the solve is
+    bitwise the same as a solver built without the field set."""
+    c = _sheared(cases.tank_c1(seed=8), 3)
+    a = sph.Solver(c, viscous_heating=0)
+    a.step(3)
+    ra, ga = a.reduce(), a.get_fluid()
+    a.close()
+    b = sph.Solver(c)
+    b.step(3)
+    rb, gb = b.reduce(), b.get_fluid()
+    b.close()
+    assert ra["diss_step"] == 0.0 and ra["diss_total"] == 0.0
+    for k in ("x", "v", "rho", "T"):
+        assert np.array_equal(ga[k], gb[k]), k
+    c2 = _sheared(cases.tank_c1(seed=8), 3)
+    h = sph.Solver(c2, viscous_heating=1)
+    h.step(3)
+    rh, gh = h.reduce(), h.get_fluid()
+    h.close()
+    # heating only adds heat: same motion, warmer oil
+    for k in ("x", "v", "rho"):
+        assert np.array_equal(gh[k], ga[k]), k
+    assert rh["diss_total"] > 0.0 and rh["thermal"] > ra["thermal"]
+
+
+def test_viscous_heating_rejects_bad_flag(sph):
+    c = cases.tank_c1()
+    with pytest.raises(sph.SphError):
+        sph.Solver(c, viscous_heating=2)

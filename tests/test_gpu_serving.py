@@ -89,6 +89,27 @@ def test_alone_equals_in_mix(sph):
         assert ra["heat_total"] == rm["heat_total"]
 
 
+
+def test_alone_equals_in_mix_with_viscous_heating(sph):
+    """The middle request has viscous dissipation heating (eq. 23) on, so the
+    batched viscous launch takes its dissipation variant for every slot; each
+    request still matches its solo run bitwise, and only the heated one
+    reports dissipated heat."""
+    reqs = _requests()
+    reqs[1].params = dict(reqs[1].params, viscous_heating=1)
+    steps = [6, 5, 4]
+    say("serving: alone vs mix, one slot with viscous heating")
+    alone = {q: _run_pool(sph, [reqs[q]], [steps[q]], [0])[0] for q in range(3)}
+    mix = _run_pool(sph, reqs, steps, [0, 1, 1])
+    for q in range(3):
+        ga, ra = alone[q]
+        gm, rm = mix[q]
+        assert ra["rc"] == 0 and rm["rc"] == 0
+        for key in ("x", "v", "rho", "T"):
+            assert np.array_equal(ga[key], gm[key]), (q, key)
+        assert ra["diss_total"] == rm["diss_total"]
+        assert (rm["diss_total"] > 0.0) == (q == 1)
+
 def test_solver_equals_pool_slot(sph):
     c = _requests()[0]
     say("serving: solver vs pool")
