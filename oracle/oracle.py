@@ -413,3 +413,62 @@ class State:
         out = np.zeros(5)
         lib().ora_totals(C.byref(self.P), C.c_int64(len(self.x)), _p(self.v), _p(self.rho), _p(self.T), _p(out))
         return dict(mass=out[0], kinetic=out[1], thermal=out[2], mass_proxy=out[3], vmax=out[4])
+
+
+# ---------------------------------------------------------------------------
+# physics-driven particle relaxation (Section 2.2, eq. 5-9)
+# ---------------------------------------------------------------------------
+
+SHAPES = {"sphere": 1, "box": 2, "cylinder": 3, "gear": 4}
+
+
+class Shape(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("teeth", C.c_int32), ("inside", C.c_int32), ("pad", C.c_int32),
+                ("center", C.c_double * 3), ("size", C.c_double * 3), ("phase", C.c_double)]
+
+
+def make_shape(d: dict) -> Shape:
+    """d: kind (sphere/box/cylinder/gear), center, size (3), teeth, phase, inside."""
+    s = Shape()
+    s.kind = SHAPES[d["kind"]]
+    s.teeth = int(d.get("teeth", 0))
+    s.inside = int(d.get("inside", 1))
+    s.center[:] = [float(v) for v in d["center"]]
+    sz = list(d["size"]) + [0.0] * (3 - len(d["size"]))
+    s.size[:] = [float(v) for v in sz]
+    s.phase = float(d.get("phase", 0.0))
+    return s
+
+
+def shape_phi(shape: dict, x):
+    x = _c3(x)
+    out = np.zeros(len(x))
+    lib().ora_shape_eval(C.byref(make_shape(shape)), C.c_double(0.0), C.c_int64(len(x)), _p(x), _p(out), None)
+    return out
+
+
+def shape_normal(shape: dict, x, eps):
+    x = _c3(x)
+    out = np.zeros((len(x), 3))
+    lib().ora_shape_eval(C.byref(make_shape(shape)), C.c_double(eps), C.c_int64(len(x)), _p(x), None, _p(out))
+    return out
+
+
+def exterior_integral(params, shape: dict, x):
+    x = _c3(x)
+    out = np.zeros((len(x), 3))
+    lib().ora_exterior_integral_n(C.byref(make_params(params)), C.byref(make_shape(shape)), C.c_int64(len(x)),
+                                  _p(x), _p(out))
+    return out
+
+
+def relax_step(params, shape: dict, x):
+    """One relaxation iteration; returns (new positions, F_p, stats dict)."""
+    x = _c3(x).copy()
+    acc = np.zeros_like(x)
+    st = np.zeros(3)
+    rc = lib().ora_relax_step(C.byref(make_params(params)), C.byref(make_shape(shape)), C.c_int64(len(x)),
+                              _p(x), _p(acc), _p(st))
+    if rc != 0:
+        raise RuntimeError(f"ora_relax_step failed: {rc}")
+    return x, acc, dict(amax=st[0], dt=st[1], bounded=int(st[2]))

@@ -972,3 +972,220 @@ done:
   free(G); free(phi); free(SG);
   return rc;
 }
+
+/* ======================================================================== */
+/* Physics-driven particle relaxation (Section 2.2, eq. 5-9)                  */
+/* ======================================================================== */
+
+/* Level sets of the analytic shapes (eq. 5: the surface is the zero contour, */
+/* negative inside).  Every function returns the exact signed distance.       */
+static double len2(double a, double b) { return sqrt(a * a + b * b); }
+
+/* extrusion along y of a cross-section with signed distance d2 over the slab */
+/* |y| <= half: exact distance of the intersection of the prism and the slab  */
+static double extrude(double d2, double y, double half) {
+  double dy = fabs(y) - half;
+  double ox = d2 > 0.0 ? d2 : 0.0, oy = dy > 0.0 ? dy : 0.0;
+  double in = d2 > dy ? d2 : dy;
+  return len2(ox, oy) + (in < 0.0 ? in : 0.0);
+}
+
+/* distance from (px, pz) to the arc of radius R between tooth coordinates   */
+/* u0 < u1 (angle theta = 2 pi (u - 1/4 - phase) / z)                         */
+static double arc_dist(double px, double pz, double r, double u, double R, double u0, double u1, int z,
+                       double phase) {
+  if (u >= u0 && u <= u1) return fabs(r - R);
+  double best = INFINITY;
+  for (int e = 0; e < 2; ++e) {
+    double th = 2.0 * ORA_PI * ((e ? u1 : u0) - 0.25 - phase) / (double)z;
+    double d = len2(px - R * cos(th), pz - R * sin(th));
+    if (d < best) best = d;
+  }
+  return best;
+}
+
+/* distance from (px, pz) to the radial flank at tooth coordinate u, r in [r0, r1] */
+static double flank_dist(double px, double pz, double u, double r0, double r1, int z, double phase) {
+  double th = 2.0 * ORA_PI * (u - 0.25 - phase) / (double)z;
+  double ex = cos(th), ez = sin(th);
+  double t = px * ex + pz * ez;
+  if (t < r0) t = r0;
+  if (t > r1) t = r1;
+  return len2(px - t * ex, pz - t * ez);
+}
+
+/* Gear cross-section (axis y): root disk r <= r_root plus teeth up to r_tip   */
+/* where the tooth coordinate u = z theta / 2 pi + 1/4 + phase has frac(u) <  */
+/* 1/2.  Its boundary: tip arcs over teeth, root arcs over gaps, radial flanks */
+/* at the half-integers of u.  The nearest boundary point lies on the pieces  */
+/* of the half-pitch holding the point or of its two neighbours.              */
+static double gear_section(double px, double pz, int z, double r_tip, double r_root, double phase) {
+  double r = len2(px, pz);
+  double u = (double)z * atan2(pz, px) / (2.0 * ORA_PI) + 0.25 + phase;
+  double k = floor(2.0 * u);            /* half-pitch index: even = tooth, odd = gap */
+  double best = INFINITY;
+  for (int m = -1; m <= 1; ++m) {
+    double kk = k + (double)m;
+    double u0 = 0.5 * kk, u1 = u0 + 0.5;
+    /* shift the point's u into this half-pitch's period for the arc test */
+    double up = u;
+    int tooth = fmod(fabs(kk), 2.0) == 0.0;
+    double d = arc_dist(px, pz, r, up, tooth ? r_tip : r_root, u0, u1, z, phase);
+    if (d < best) best = d;
+    d = flank_dist(px, pz, u0, r_root, r_tip, z, phase);
+    if (d < best) best = d;
+  }
+  {
+    double d = flank_dist(px, pz, 0.5 * (k + 2.0), r_root, r_tip, z, phase);
+    if (d < best) best = d;
+  }
+  double fu = u - floor(u);
+  int inside = r <= r_root || (r <= r_tip && fu < 0.5);
+  return inside ? -best : best;
+}
+
+double ora_shape_phi(const ora_shape* s, const double* x) {
+  double d[3] = {x[0] - s->center[0], x[1] - s->center[1], x[2] - s->center[2]};
+  double phi;
+  switch (s->kind) {
+    case ORA_SHAPE_SPHERE:
+      phi = sqrt(dot3(d, d)) - s->size[0];
+      break;
+    case ORA_SHAPE_BOX: {
+      double q[3], o = 0.0, in = -INFINITY;
+      for (int a = 0; a < 3; ++a) {
+        q[a] = fabs(d[a]) - s->size[a];
+        if (q[a] > 0.0) o += q[a] * q[a];
+        if (q[a] > in) in = q[a];
+      }
+      phi = sqrt(o) + (in < 0.0 ? in : 0.0);
+      break;
+    }
+    case ORA_SHAPE_CYLINDER:
+      phi = extrude(len2(d[0], d[2]) - s->size[0], d[1], s->size[1]);
+      break;
+    case ORA_SHAPE_GEAR:
+      phi = extrude(gear_section(d[0], d[2], s->teeth, s->size[0], s->size[1], s->phase), d[1], s->size[2]);
+      break;
+    default:
+      return NAN;
+  }
+  return s->inside ? phi : -phi;
+}
+
+/* unit normal: central differences of phi, step eps = 1e-6 h */
+void ora_shape_normal(const ora_shape* s, double eps, const double* x, double* n) {
+  double g[3];
+  for (int a = 0; a < 3; ++a) {
+    double xp[3] = {x[0], x[1], x[2]}, xm[3] = {x[0], x[1], x[2]};
+    xp[a] += eps;
+    xm[a] -= eps;
+    g[a] = ora_shape_phi(s, xp) - ora_shape_phi(s, xm);
+  }
+  double l = sqrt(dot3(g, g));
+  for (int a = 0; a < 3; ++a) n[a] = l > 0.0 ? g[a] / l : 0.0;
+}
+
+/* Kernel-gradient integral over the region outside the shape, phi > 0,       */
+/* seen from x: I = int_{phi(y) > 0} grad_x W(x - y) dy, by the midpoint rule */
+/* on the cube [-2h, 2h]^3 around x cut into (2K)^3 cells of edge h/4, each   */
+/* cell weighted by its outside volume fraction, taken linear in phi across   */
+/* one cell edge: clamp(1/2 + phi/edge, 0, 1) (exact for a face-parallel     */
+/* plane).                                                                    */
+void ora_exterior_integral(const ora_params* P, const ora_shape* s, const double* x, double* I) {
+  double h = P->h_over_dp * P->dp;
+  double del = 0.25 * h;
+  const int K = ORA_RELAX_QK;
+  double acc[3] = {0.0, 0.0, 0.0};
+  I[0] = I[1] = I[2] = 0.0;
+  if (ora_shape_phi(s, x) <= -2.0 * h - del) return;   /* every cell entirely inside */
+  double dv = del * del * del;
+  for (int a = -K; a < K; ++a)
+    for (int b = -K; b < K; ++b)
+      for (int c = -K; c < K; ++c) {
+        double y[3] = {x[0] + del * ((double)a + 0.5), x[1] + del * ((double)b + 0.5),
+                       x[2] + del * ((double)c + 0.5)};
+        double r = sqrt(dist2(x, y));
+        if (r >= 2.0 * h) continue;
+        /* outside volume fraction of the cell: linear in phi across one edge */
+        double f = 0.5 + ora_shape_phi(s, y) / del;
+        if (!(f > 0.0)) continue;
+        if (f > 1.0) f = 1.0;
+        double F = ora_kernel_F(r, h);        /* grad_x W(x - y) = F (x - y) */
+        for (int k = 0; k < 3; ++k) acc[k] += F * (x[k] - y[k]) * (f * dv);
+      }
+  I[0] = acc[0];
+  I[1] = acc[1];
+  I[2] = acc[2];
+}
+
+/* One relaxation iteration over n particles of volume dp^3 inside the shape:
+ *   F_p,i = -(2/m) sum_j V_i V_j p0 grad_i W_ij  (eq. 7), with the particles
+ *           missing beyond the surface replaced by the continuum: the sum
+ *           gains V_i p0 times the exterior integral (reading of the level-set
+ *           compensation of the kernel deficiency);
+ *   dt    = 0.25 sqrt(h / max_i |F_p,i|)         (eq. 8);
+ *   x_i  += F_p,i dt^2 / 2                       (eq. 9);
+ *   confinement: a particle with phi > -dp/2 after the move is put back on
+ *   the level phi = -dp/2 along the normal (reading of the static level-set
+ *   confinement).
+ * acc (n x 3, nullable) receives F_p; stats = {max |F_p|, dt, bounded count}.
+ * p0 and the density cancel in the displacement; p0 = 1 and rho0 are used.  */
+int ora_relax_step(const ora_params* P, const ora_shape* s, int64_t n, double* x, double* acc,
+                   double* stats) {
+  double h = P->h_over_dp * P->dp;
+  double V = P->dp * P->dp * P->dp, m = P->rho0 * V, p0 = 1.0;
+  ora_nbr* nb = NULL;
+  int rc = ora_nbr_build(P, n, x, 0, NULL, 0, &nb);
+  if (rc) return rc;
+  double* a = malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+  if (!a) { ora_nbr_free(nb); return ORA_ERR_OOM; }
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t i = 0; i < n; ++i) {
+    double sum[3] = {0.0, 0.0, 0.0}, I[3];
+    pgeo g;
+    for (int64_t p = nb->off_f[i]; p < nb->off_f[i + 1]; ++p) {
+      pair_geom(nb->xb + 3 * i, nb->xb + 3 * (int64_t)nb->idx_f[p], nb->h, &g);
+      for (int k = 0; k < 3; ++k) sum[k] += V * V * p0 * g.F * g.r[k];
+    }
+    ora_exterior_integral(P, s, x + 3 * i, I);
+    for (int k = 0; k < 3; ++k) a[3 * i + k] = -(2.0 / m) * (sum[k] + V * p0 * I[k]);
+  }
+  double amax = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    double l = sqrt(dot3(a + 3 * i, a + 3 * i));
+    if (l > amax) amax = l;
+  }
+  double dt = amax > 0.0 ? 0.25 * sqrt(h / amax) : 0.0;
+  int64_t bounded = 0;
+#pragma omp parallel for schedule(static) reduction(+ : bounded)
+  for (int64_t i = 0; i < n; ++i) {
+    double* xi = x + 3 * i;
+    for (int k = 0; k < 3; ++k) xi[k] += 0.5 * a[3 * i + k] * dt * dt;
+    double phi = ora_shape_phi(s, xi);
+    if (phi > -0.5 * P->dp) {
+      double nn[3];
+      ora_shape_normal(s, 1e-6 * h, xi, nn);
+      for (int k = 0; k < 3; ++k) xi[k] -= (phi + 0.5 * P->dp) * nn[k];
+      bounded += 1;
+    }
+  }
+  if (acc) memcpy(acc, a, sizeof(double) * 3 * (size_t)n);
+  if (stats) { stats[0] = amax; stats[1] = dt; stats[2] = (double)bounded; }
+  free(a);
+  ora_nbr_free(nb);
+  return ORA_OK;
+}
+
+void ora_shape_eval(const ora_shape* s, double eps, int64_t n, const double* x, double* phi, double* nrm) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    if (phi) phi[i] = ora_shape_phi(s, x + 3 * i);
+    if (nrm) ora_shape_normal(s, eps, x + 3 * i, nrm + 3 * i);
+  }
+}
+
+void ora_exterior_integral_n(const ora_params* P, const ora_shape* s, int64_t n, const double* x, double* I) {
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < n; ++i) ora_exterior_integral(P, s, x + 3 * i, I + 3 * i);
+}

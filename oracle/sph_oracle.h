@@ -135,6 +135,34 @@ int ora_step(const ora_params* P, int32_t nbody, const ora_body* B, int64_t nf, 
 void ora_totals(const ora_params* P, int64_t nf, const double* v, const double* rho,
                 const double* T, double* out5);
 
+/* --- physics-driven particle relaxation (Section 2.2, eq. 5-9) ----------- */
+enum { ORA_SHAPE_SPHERE = 1, ORA_SHAPE_BOX = 2, ORA_SHAPE_CYLINDER = 3, ORA_SHAPE_GEAR = 4 };
+enum { ORA_RELAX_QK = 8 };   /* exterior integral: (2 K)^3 midpoint cells of edge h/4 */
+
+/* An analytic shape; cylinder and gear have their axis along y.
+ * size: sphere (R); box (half extents); cylinder (R, half length);
+ * gear (r_tip, r_root, half face width), teeth z, tooth where
+ * frac(z theta / 2 pi + 1/4 + phase) < 1/2 with theta = atan2(z - cz, x - cx).
+ * inside = 1: the region is the shape; 0: its complement. */
+typedef struct {
+  int32_t kind, teeth, inside, pad;
+  double center[3], size[3], phase;
+} ora_shape;
+
+/* signed distance of the region (negative inside it) */
+double ora_shape_phi(const ora_shape* s, const double* x);
+/* unit gradient of phi by central differences of step eps */
+void ora_shape_normal(const ora_shape* s, double eps, const double* x, double* n);
+/* int over phi(y) > 0 of grad_x W(x - y) dy (midpoint rule, cells of edge h/4) */
+void ora_exterior_integral(const ora_params* P, const ora_shape* s, const double* x, double* I);
+/* phi and normals (either nullable) of n points; the exterior integral of n points */
+void ora_shape_eval(const ora_shape* s, double eps, int64_t n, const double* x, double* phi, double* nrm);
+void ora_exterior_integral_n(const ora_params* P, const ora_shape* s, int64_t n, const double* x, double* I);
+/* one relaxation iteration in place; acc (n x 3, nullable) = F_p;
+   stats = {max |F_p|, dt, number of particles put back by the confinement} */
+int ora_relax_step(const ora_params* P, const ora_shape* s, int64_t n, double* x, double* acc,
+                   double* stats);
+
 #ifdef __cplusplus
 }
 #endif
