@@ -176,6 +176,46 @@ int sph_get_timing(sph_solver* s, int32_t kernel, int32_t max, float* ms, int32_
  * reproduces them exactly, so stepping is unaffected) and synchronises.
  * SPH_ERR_STATE before sph_init or after a latched fault. */
 int sph_contact_factor(sph_solver* s, double* zeta, double* body_mean);
+
+/* An analytic shape bounding the particle relaxation (Section 2.2, eq. 5):
+ * its surface is the zero contour of the signed distance phi, negative inside.
+ * Cylinder and gear have their axis along y through the centre.
+ *   sphere:   size = (radius, -, -)
+ *   box:      size = half extents
+ *   cylinder: size = (radius, half length, -)
+ *   gear:     size = (tip radius, root radius, half face width), `teeth` teeth,
+ *             tooth where frac(teeth theta / 2 pi + 1/4 + phase) < 1/2 with
+ *             theta = atan2(z - cz, x - cx): a root disk with rectangular teeth
+ * inside = 1 relaxes within the shape, 0 within its complement. */
+enum { SPH_SHAPE_SPHERE = 1, SPH_SHAPE_BOX = 2, SPH_SHAPE_CYLINDER = 3, SPH_SHAPE_GEAR = 4 };
+typedef struct {
+  int32_t kind, teeth, inside, reserved;
+  double center[3], size[3], phase;
+} sph_shape;
+
+typedef struct {
+  int32_t iterations;     /* iterations done */
+  int32_t bounded_last;   /* particles put back by the confinement in the last iteration */
+  double amax_first;      /* max |F_p| of the first iteration [m/s^2 per unit p0/rho0] */
+  double amax_last;       /* max |F_p| of the last iteration */
+  double dt_last;         /* relaxation step of the last iteration (eq. 8) */
+} sph_relax_report;
+
+/* Physics-driven particle relaxation (Section 2.2, eq. 6-9) of the solver's
+ * fluid particles, which must lie in the region of `shape` (phi < 0), each of
+ * volume dp^3 and mass rho0 dp^3, background pressure p0 = 1 (p0 and rho0
+ * cancel in the displacement).  Each iteration: cell sort and neighbour build;
+ * F_p,i = -(2/m) V p0 (sum_j V grad_i W_ij + I_i) where I_i, the integral of
+ * grad W over the outside of the region (phi > 0) on cells of edge h/4
+ * weighted by their outside fraction clamp(1/2 + phi/edge, 0, 1), stands in
+ * for the neighbours missing beyond the surface; dt = 0.25 sqrt(h / max|F_p|)
+ * (eq. 8); x += F_p dt^2 / 2 (eq. 9); a particle ending at phi > -dp/2 is put
+ * back on the level -dp/2 along the unit normal (static confinement).  Only
+ * positions change (read them with sph_get_fluid; the density re-initialisation
+ * of each build also runs).  Call between steps; synchronises.  SPH_ERR_ARG
+ * for a bad shape or iterations < 1, SPH_ERR_DOMAIN if a particle leaves the
+ * grid, SPH_ERR_STATE before sph_init or after a latched fault. */
+int sph_relax(sph_solver* s, const sph_shape* shape, int32_t iterations, sph_relax_report* report);
 /* Raw device state for parity tests (SPH_DUMP_*); bytes must be >= the size
  * reported by sph_dump_size.  Synchronises. */
 int sph_dump_size(sph_solver* s, int32_t what, size_t* bytes);
@@ -189,7 +229,8 @@ int sph_destroy(sph_solver* s);
 enum {
   SPH_K_CLEAR = 0, SPH_K_POSE, SPH_K_FOLD, SPH_K_SCAN1, SPH_K_SCAN2, SPH_K_SCAN3, SPH_K_SCATTER,
   SPH_K_CELLSORT, SPH_K_REORDER, SPH_K_BUILD, SPH_K_DT, SPH_K_VISC_HEAT, SPH_K_HALF_A,
-  SPH_K_MOMENTUM, SPH_K_CONTINUITY, SPH_K_END, SPH_K_FINAL, SPH_K_SUMW, SPH_K_CONTACT, SPH_K_COUNT
+  SPH_K_MOMENTUM, SPH_K_CONTINUITY, SPH_K_END, SPH_K_FINAL, SPH_K_SUMW, SPH_K_CONTACT,
+  SPH_K_RELAX_FORCE, SPH_K_RELAX_MAX, SPH_K_RELAX_MOVE, SPH_K_COUNT
 };
 
 /* dump selectors; arrays are in the device's cell-sorted order unless noted */

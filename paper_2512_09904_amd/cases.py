@@ -414,3 +414,54 @@ def sub_box(case: Case, center, half, halo: float) -> dict:
     core = np.all(d <= h, axis=1)
     halo_m = np.all(d <= h + halo, axis=1) & ~core
     return dict(core=np.nonzero(core)[0], halo=np.nonzero(halo_m)[0])
+
+
+# ----------------------------------------------------------------------------
+# particle relaxation (Section 2.2): lattice sites inside an analytic shape
+# ----------------------------------------------------------------------------
+
+def shape_inside(shape: dict):
+    """Inside test of an analytic shape (the dict of the relaxation calls):
+    sphere, box, cylinder or gear, axis along y for the last two."""
+    c = np.asarray(shape["center"], dtype=np.float64)
+    s = list(shape["size"]) + [0.0] * (3 - len(shape["size"]))
+    k = shape["kind"]
+    if k == "sphere":
+        f = lambda x: np.sum((x - c) ** 2, axis=1) < s[0] ** 2
+    elif k == "box":
+        f = lambda x: np.all(np.abs(x - c) < np.asarray(s[:3]), axis=1)
+    elif k == "cylinder":
+        f = lambda x: (((x[:, 0] - c[0]) ** 2 + (x[:, 2] - c[2]) ** 2) < s[0] ** 2) & (np.abs(x[:, 1] - c[1]) < s[1])
+    elif k == "gear":
+        f = gear_inside(c, int(shape["teeth"]), s[0], s[1], 2.0 * s[2], float(shape.get("phase", 0.0)))
+    else:
+        raise ValueError(k)
+    if int(shape.get("inside", 1)):
+        return f
+    return lambda x: ~f(x)
+
+
+def relax_case(shape: dict, dp: float, bound: float, jitter_amp: float = 0.25, seed: int = 0,
+               h_over_dp: float = 1.3) -> Case:
+    """Initial particles of a relaxation: the sites (i + 1/2) dp of the lattice
+    inside `shape`, within the cube [-bound, bound]^3 around the shape's
+    centre, moved by a seeded jitter of +-jitter_amp dp per axis (the start of
+    eq. 6's relaxation: a lattice embedded in the geometry).  Carried as the
+    fluid of a case with one static body and no solid particles."""
+    c = np.asarray(shape["center"], dtype=np.float64)
+    lo_i = np.floor((c - bound) / dp).astype(int)
+    hi_i = np.ceil((c + bound) / dp).astype(int)
+    rng = [np.arange(lo_i[a], hi_i[a]) for a in range(3)]
+    I, J, K = np.meshgrid(*rng, indexing="ij")
+    x = (np.stack([I.ravel(), J.ravel(), K.ravel()], axis=1) + 0.5) * dp
+    x = x[shape_inside(shape)(x)]
+    if jitter_amp > 0:
+        x = x + jitter(seed, len(x), dp, jitter_amp)
+    n = len(x)
+    params = default_params(dp, 1000.0, 10.0, 1e-4, 0.13, 2000.0, tuple(c - bound - dp), tuple(c + bound + dp),
+                            h_over_dp=h_over_dp, gravity=(0.0, 0.0, 0.0))
+    return Case(name=f"relax-{shape['kind']}", params=params,
+                bodies=[Body(tuple(c), (0.0, 1.0, 0.0), 0.0, 300.0, 20.0)],
+                xf=np.ascontiguousarray(x), vf=np.zeros((n, 3)), rhof=np.full(n, 1000.0), Tf=np.full(n, 300.0),
+                xs0=np.zeros((0, 3)), ns0=np.zeros((0, 3)), body=np.zeros(0, np.int32),
+                meta=dict(shape=dict(shape), umax=1.0))

@@ -377,6 +377,28 @@ static int launch(sph_pool* P, const LaunchTab& tab, int kid, int which, int sub
   return SPH_OK;
 }
 
+static int launch_rx(sph_pool* P, const LaunchTab& tab, int kid, int iter, const RelaxShape& g) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (P->timing) {
+    for (hipEvent_t* e : {&a, &b}) {
+      if (!P->free_events.empty()) {
+        *e = P->free_events.back();
+        P->free_events.pop_back();
+      } else {
+        HIPCHK(hipEventCreate(e));
+      }
+    }
+    HIPCHK(hipEventRecord(a, P->stream));
+  }
+  hipError_t e = launch_relax(P->prec, kid, iter, P->d_table, tab, g, P->stream);
+  if (e != hipSuccess) return fail(SPH_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  if (P->timing) {
+    HIPCHK(hipEventRecord(b, P->stream));
+    P->pending.push_back({kid, a, b});
+  }
+  return SPH_OK;
+}
+
 #define LCHK(x)            \
   do {                     \
     int r_ = (x);          \
@@ -1038,6 +1060,61 @@ extern "C" int sph_contact_factor(sph_solver* s, double* zeta, double* body_mean
       }
       body_mean[b] = cnt ? (sum + comp) / (double)cnt : 0.0;
     }
+  }
+  return SPH_OK;
+}
+
+static bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+extern "C" int sph_relax(sph_solver* s, const sph_shape* sh, int32_t iterations, sph_relax_report* rep) {
+  if (!s || !s->inited) return fail(SPH_ERR_STATE, "not initialised");
+  if (!sh) return fail(SPH_ERR_ARG, "shape is NULL");
+  if (iterations < 1) return fail(SPH_ERR_ARG, "iterations must be >= 1");
+  if (sh->inside != 0 && sh->inside != 1) return fail(SPH_ERR_ARG, "inside must be 0 or 1");
+  if (sh->reserved != 0) return fail(SPH_ERR_ARG, "reserved must be 0");
+  if (!finite3(sh->center) || !finite3(sh->size) || !std::isfinite(sh->phase))
+    return fail(SPH_ERR_ARG, "non-finite shape");
+  const double* z = sh->size;
+  bool ok;
+  switch (sh->kind) {
+    case SPH_SHAPE_SPHERE: ok = z[0] > 0; break;
+    case SPH_SHAPE_BOX: ok = z[0] > 0 && z[1] > 0 && z[2] > 0; break;
+    case SPH_SHAPE_CYLINDER: ok = z[0] > 0 && z[1] > 0; break;
+    case SPH_SHAPE_GEAR: ok = z[1] > 0 && z[0] > z[1] && z[2] > 0 && sh->teeth >= 2 && sh->teeth <= 10000; break;
+    default: return fail(SPH_ERR_ARG, "unknown shape kind");
+  }
+  if (!ok) return fail(SPH_ERR_ARG, "shape sizes out of range");
+  sph_pool* P = s->pool;
+  SlotHost& S = P->slots[0];
+  SlotCtl c;
+  LCHK(read_ctl(P, S, &c, true));
+  if (c.flags) return fail(flag_code(c.flags), "solve faulted");
+  RelaxShape g;
+  g.kind = sh->kind;
+  g.teeth = sh->teeth;
+  g.inside = sh->inside;
+  g.pad = 0;
+  for (int a = 0; a < 3; ++a) {
+    g.center[a] = sh->center[a];
+    g.size[a] = sh->size[a];
+  }
+  g.phase = sh->phase;
+  LaunchTab T;
+  tab_for(P, std::vector<int>{0}, T);
+  for (int it = 0; it < iterations; ++it) {
+    LCHK(enqueue_sort_build(P, T));
+    LCHK(launch_rx(P, T, SPH_K_RELAX_FORCE, it, g));
+    LCHK(launch_rx(P, T, SPH_K_RELAX_MAX, it, g));
+    LCHK(launch_rx(P, T, SPH_K_RELAX_MOVE, it, g));
+  }
+  LCHK(read_ctl(P, S, &c, true));
+  if (c.flags) return fail(flag_code(c.flags), "relaxation faulted");
+  if (rep) {
+    rep->iterations = iterations;
+    rep->bounded_last = c.relax_bounded;
+    rep->amax_first = c.relax_first;
+    rep->amax_last = c.relax_amax;
+    rep->dt_last = c.relax_dt;
   }
   return SPH_OK;
 }

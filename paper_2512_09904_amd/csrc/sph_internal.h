@@ -35,6 +35,8 @@ struct SlotCtl {
   int32_t n_ac;
   uint32_t flags;
   double heat_total, diss_total;
+  double relax_amax, relax_dt, relax_first;   // particle relaxation: max |F_p|, step
+  int32_t relax_bounded, relax_pad;           // particles put back by the confinement
   double cum[NB][3];     // time integrals: axial torque, energy, heat
   sph_report rep;
   sph_body_report brep[NB];
@@ -98,6 +100,17 @@ struct SlotDesc {
   double *press_part;   // [NB * 6]: sum over sub-steps of force(3) torque(3)
   double *glob_part;    // [NGLOB + 1]: the globals, then the dissipated power
 };
+
+// An analytic shape of the particle relaxation (sph_shape, checked).
+struct RelaxShape {
+  int32_t kind, teeth, inside, pad;
+  double center[3], size[3], phase;
+};
+
+// Launch one kernel of the particle relaxation (SPH_K_RELAX_*); iter: the
+// iteration index (0 records the first maximum).
+hipError_t launch_relax(int prec, int kid, int iter, const SlotDesc* table, const LaunchTab& tab,
+                        const RelaxShape& shape, hipStream_t stream);
 
 // Launch one kernel of the step.  prec: SPH_PREC_*; kid: SPH_K_*; sub: the
 // acoustic sub-step index (only for the sub-step kernels); which: 0 fluid, 1

@@ -21,7 +21,8 @@ PREC = {"mixed": 0, "fp64": 1, "fp32": 2}
 MAX_BODIES = 8
 
 KERNELS = ["clear", "pose", "fold", "scan1", "scan2", "scan3", "scatter", "cellsort", "reorder", "build",
-           "dt", "visc_heat", "half_a", "momentum", "continuity", "end", "final", "sumw", "contact"]
+           "dt", "visc_heat", "half_a", "momentum", "continuity", "end", "final", "sumw", "contact",
+           "relax_force", "relax_max", "relax_move"]
 K = {n: i for i, n in enumerate(KERNELS)}
 
 DUMP = dict(fluid_ids=1, solid_ids=2, fluid_cell=3, nbr_count=4, nbr_fluid=5, nbr_solid=6, fluid_offset=7,
@@ -63,6 +64,31 @@ class BodyReport(C.Structure):
                 ("energy_int", C.c_double), ("heat_int", C.c_double)]
 
 
+SHAPES = {"sphere": 1, "box": 2, "cylinder": 3, "gear": 4}
+
+
+class Shape(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("teeth", C.c_int32), ("inside", C.c_int32), ("reserved", C.c_int32),
+                ("center", C.c_double * 3), ("size", C.c_double * 3), ("phase", C.c_double)]
+
+
+class RelaxReport(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("bounded_last", C.c_int32), ("amax_first", C.c_double),
+                ("amax_last", C.c_double), ("dt_last", C.c_double)]
+
+
+def shape_struct(d: dict) -> Shape:
+    """d: kind (sphere/box/cylinder/gear), center, size, teeth, phase, inside."""
+    s = Shape()
+    s.kind = SHAPES[d["kind"]]
+    s.teeth = int(d.get("teeth", 0))
+    s.inside = int(d.get("inside", 1))
+    s.center[:] = [float(v) for v in d["center"]]
+    s.size[:] = [float(v) for v in list(d["size"]) + [0.0] * (3 - len(d["size"]))]
+    s.phase = float(d.get("phase", 0.0))
+    return s
+
+
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
 
@@ -90,7 +116,7 @@ def lib():
 
 
 EXPORTS = ["sph_error_string", "sph_last_error", "sph_create", "sph_set_bodies", "sph_set_fluid", "sph_set_solid",
-           "sph_init", "sph_step", "sph_reduce", "sph_contact_factor", "sph_get_fluid", "sph_set_graph", "sph_set_timing",
+           "sph_init", "sph_step", "sph_reduce", "sph_contact_factor", "sph_relax", "sph_get_fluid", "sph_set_graph", "sph_set_timing",
            "sph_get_timing", "sph_dump_size", "sph_debug_dump", "sph_debug_poke_velocity", "sph_destroy",
            "sph_bytes_required", "sph_pool_create", "sph_pool_admit", "sph_pool_step", "sph_pool_poll",
            "sph_pool_get_fluid", "sph_pool_release", "sph_pool_usage", "sph_pool_set_graph", "sph_pool_destroy"]
@@ -246,6 +272,14 @@ class Solver:
         m = np.zeros(max(self.nbody, 1))
         check(lib().sph_contact_factor(self.h, _p(z), _p(m)), "sph_contact_factor")
         return z[: self.ns], m[: self.nbody]
+
+    def relax(self, shape: dict, iterations: int):
+        """Physics-driven relaxation (Section 2.2) of the fluid particles inside
+        `shape`; positions change in place (read them with get_fluid)."""
+        r = RelaxReport()
+        check(lib().sph_relax(self.h, C.byref(shape_struct(shape)), C.c_int32(int(iterations)), C.byref(r)),
+              "sph_relax")
+        return {k: getattr(r, k) for k, _ in RelaxReport._fields_}
 
     def set_timing(self, on=True):
         check(lib().sph_set_timing(self.h, C.c_int32(int(on))), "sph_set_timing")
