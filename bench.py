@@ -30,7 +30,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 GATHER_PEAK = 256 * 2.4e9
-KERNEL_SRC = os.path.join(ROOT, "paper_2512_09904_amd", "csrc", "sph_kernels.hip")
+# the solver kernels' sources: the HBM-traffic record is valid only for these exact texts
+KERNEL_SRC = [os.path.join(ROOT, "paper_2512_09904_amd", "csrc", f)
+              for f in ("sph_kernels.hip", "sph_device.h", "sph_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gearbox_c2.json")
 
 
@@ -39,8 +41,11 @@ def log(*a):
 
 
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for p in KERNEL_SRC:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def pair_counts(s, nf):

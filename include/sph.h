@@ -183,7 +183,8 @@ int sph_contact_factor(sph_solver* s, double* zeta, double* body_mean);
  *   sphere:   size = (radius, -, -)
  *   box:      size = half extents
  *   cylinder: size = (radius, half length, -)
- *   gear:     size = (tip radius, root radius, half face width), `teeth` teeth,
+ *   gear:     size = (tip radius, root radius, half face width), `teeth` teeth
+ *             (2 to 512),
  *             tooth where frac(teeth theta / 2 pi + 1/4 + phase) < 1/2 with
  *             theta = atan2(z - cz, x - cx): a root disk with rectangular teeth
  * inside = 1 relaxes within the shape, 0 within its complement. */

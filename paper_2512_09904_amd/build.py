@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsph.so")
-SOURCES = ["sph_kernels.hip", "sph_capi.hip"]
+SOURCES = ["sph_kernels.hip", "sph_relax.hip", "sph_capi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

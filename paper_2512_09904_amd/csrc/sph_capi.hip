@@ -1080,7 +1080,7 @@ extern "C" int sph_relax(sph_solver* s, const sph_shape* sh, int32_t iterations,
     case SPH_SHAPE_SPHERE: ok = z[0] > 0; break;
     case SPH_SHAPE_BOX: ok = z[0] > 0 && z[1] > 0 && z[2] > 0; break;
     case SPH_SHAPE_CYLINDER: ok = z[0] > 0 && z[1] > 0; break;
-    case SPH_SHAPE_GEAR: ok = z[1] > 0 && z[0] > z[1] && z[2] > 0 && sh->teeth >= 2 && sh->teeth <= 10000; break;
+    case SPH_SHAPE_GEAR: ok = z[1] > 0 && z[0] > z[1] && z[2] > 0 && sh->teeth >= 2 && sh->teeth <= 512; break;
     default: return fail(SPH_ERR_ARG, "unknown shape kind");
   }
   if (!ok) return fail(SPH_ERR_ARG, "shape sizes out of range");

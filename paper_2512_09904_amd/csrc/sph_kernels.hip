@@ -15,225 +15,9 @@
 
 #include <type_traits>
 
-#include "sph_internal.h"
+#include "sph_device.h"
 
 namespace sphk {
-
-// ---------------------------------------------------------------------------
-// precision policies: position anchors, interaction arithmetic, temperature
-// ---------------------------------------------------------------------------
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef uint32_t u4 __attribute__((ext_vector_type(4)));
-typedef double d4 __attribute__((ext_vector_type(4)));
-
-struct PMixed {
-  typedef double Pos;
-  typedef float Real;
-  typedef double Temp;
-  typedef d4 Pos4;
-  typedef f4 Real4;
-  static constexpr bool kRel = true;   // density stored as rho - rho0
-};
-struct PF64 {
-  typedef double Pos;
-  typedef double Real;
-  typedef double Temp;
-  typedef d4 Pos4;
-  typedef d4 Real4;
-  static constexpr bool kRel = true;
-};
-struct PF32 {
-  typedef float Pos;
-  typedef float Real;
-  typedef float Temp;
-  typedef f4 Pos4;
-  typedef f4 Real4;
-  static constexpr bool kRel = false;  // absolute density in FP32
-};
-
-// Arrays live in device global memory; loads through these pointers compile
-// to global (not flat) memory instructions.
-#define GLB __attribute__((address_space(1)))
-template <class T>
-__device__ __forceinline__ GLB T* gp(void* p) {
-  return (GLB T*)p;
-}
-template <class T>
-__device__ __forceinline__ const GLB T* gpc(const void* p) {
-  return (const GLB T*)p;
-}
-
-// ---------------------------------------------------------------------------
-// helpers
-// ---------------------------------------------------------------------------
-// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
-// L2).  Logical block numbers are laid out so that every XCD runs one
-// contiguous range of blocks, i.e. one contiguous range of Morton-sorted
-// particles, and the neighbour gathers of adjacent blocks hit the same L2.
-constexpr int NXCD = 8;
-__device__ __forceinline__ int xcd_block(int b, int g) {
-  const int q = g / NXCD, r = g % NXCD;
-  const int x = b % NXCD, k = b / NXCD;
-  return x * q + min(x, r) + k;
-}
-
-__device__ __forceinline__ int find_slot(const LaunchTab& L, int dom, int& lb) {
-  const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
-  int k = 0;
-  for (int s = 1; s < L.n; ++s)
-    if (blk >= L.blk0[dom][s]) k = s;
-  lb = blk - L.blk0[dom][k];
-  return L.slot[k];
-}
-
-__device__ __forceinline__ bool live(const SlotDesc& S) {
-  return S.ctl->flags == 0u && S.ctl->step < S.ctl->target;
-}
-
-#define SLOT_PROLOGUE(DOM)                          \
-  int lb_;                                          \
-  const SlotDesc& S = table[find_slot(tab, DOM, lb_)]; \
-  if (!live(S)) return;                             \
-  const int lb = lb_;
-
-__device__ __forceinline__ void raise_flag(const SlotDesc& S, uint32_t f) {
-  atomicOr(&S.ctl->flags, f);
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-  return v;
-}
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, WAVE));
-  return v;
-}
-__device__ __forceinline__ uint32_t wave_sum_u(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-  return v;
-}
-
-// Neumaier-compensated accumulator (additions only, so no contraction applies)
-struct KS {
-  double s, c;
-};
-__device__ __forceinline__ void ks_add(KS& k, double x) {
-  double t = k.s + x;
-  if (fabs(k.s) >= fabs(x)) k.c += (k.s - t) + x;
-  else k.c += (x - t) + k.s;
-  k.s = t;
-}
-__device__ __forceinline__ KS wave_ks(KS k) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    double s = __shfl_xor(k.s, o, WAVE);
-    double c = __shfl_xor(k.c, o, WAVE);
-    ks_add(k, s);
-    k.c += c;
-  }
-  return k;
-}
-
-// cell of a point: floor((x - lo)/cs) per axis, FP64, correctly rounded
-// division, no contraction.  Out-of-grid points are clamped and reported.
-template <class PosT>
-__device__ __forceinline__ bool cell_coords(const SlotDesc& S, PosT x, PosT y, PosT z, int c[3]) {
-#pragma clang fp contract(off)
-  const double p[3] = {(double)x, (double)y, (double)z};
-  bool ok = true;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    double f = floor((p[a] - S.lo[a]) / S.cs);
-    if (!(f >= 0.0) || f >= (double)S.dims[a]) {
-      ok = false;
-      f = 0.0;
-    }
-    c[a] = (int)f;
-  }
-  return ok;
-}
-
-__device__ __forceinline__ int cell_linear(const SlotDesc& S, int cx, int cy, int cz) {
-  return (cz * S.dims[1] + cy) * S.dims[0] + cx;
-}
-
-template <class P>
-__device__ __forceinline__ typename P::Real rho_abs(const SlotDesc& S, typename P::Real s) {
-  typedef typename P::Real Real;
-  return P::kRel ? (Real)S.rho0 + s : s;
-}
-template <class P>
-__device__ __forceinline__ typename P::Real press(const SlotDesc& S, typename P::Real s) {
-  typedef typename P::Real Real;
-  const Real c2 = (Real)(S.c0 * S.c0);
-  return P::kRel ? c2 * s : c2 * (s - (Real)S.rho0);
-}
-
-// Reciprocal and reciprocal square root of the interaction type: the FP32
-// hardware instructions (about 1 ulp) in the FP32 sweeps, IEEE operations in
-// FP64 mode.
-__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
-__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
-
-// A 32-bit integer in the fourth lane of a 4-wide record: its bit pattern in
-// FP32 (never a NaN: values stay below 2^30), its exact value in FP64.
-__device__ __forceinline__ float pack_index(uint32_t j, float) { return __builtin_bit_cast(float, j); }
-__device__ __forceinline__ double pack_index(uint32_t j, double) { return (double)j; }
-__device__ __forceinline__ uint32_t unpack_index(float w) { return __builtin_bit_cast(uint32_t, w); }
-__device__ __forceinline__ uint32_t unpack_index(double w) { return (uint32_t)w; }
-
-// Cell-relative positions.  At the build every particle stores
-// o = x - (lo + c cs_r) rounded to the interaction type, with its cell c
-// packed as 10 bits per axis.  A pair's vector is then
-//   r_ij = (o_i - o_j) + (c_i - c_j) cs_r,
-// where c_i - c_j is -1, 0 or 1 per axis, so the second term is exact and
-// r_ij carries only the offsets' roundings (a few ulp of cs_r), however far
-// the particles are from the grid origin.
-__device__ __forceinline__ uint32_t pack_cell(const int c[3]) {
-  return (uint32_t)c[0] | (uint32_t)c[1] << 10 | (uint32_t)c[2] << 20;
-}
-template <class Real, class Real4>
-__device__ __forceinline__ void pair_vec(const Real4 a, uint32_t ca, const Real4 b, Real csr, Real& rx, Real& ry,
-                                         Real& rz) {
-  const uint32_t cb = unpack_index(b.w);
-  const int dx = (int)(ca & 1023u) - (int)(cb & 1023u);
-  const int dy = (int)((ca >> 10) & 1023u) - (int)((cb >> 10) & 1023u);
-  const int dz = (int)(ca >> 20) - (int)(cb >> 20);
-  rx = (a.x - b.x) + (Real)dx * csr;
-  ry = (a.y - b.y) + (Real)dy * csr;
-  rz = (a.z - b.z) + (Real)dz * csr;
-}
-template <class P, class Pos>
-__device__ __forceinline__ typename P::Real4 cell_offset(const SlotDesc& S, Pos x, Pos y, Pos z, const int c[3]) {
-#pragma clang fp contract(off)
-  typedef typename P::Real Real;
-  typename P::Real4 o;
-  o.x = (Real)((double)x - (S.lo[0] + (double)c[0] * S.cs_r));
-  o.y = (Real)((double)y - (S.lo[1] + (double)c[1] * S.cs_r));
-  o.z = (Real)((double)z - (S.lo[2] + (double)c[2] * S.cs_r));
-  o.w = pack_index(pack_cell(c), (Real)0);
-  return o;
-}
-
-// F = (dW/dr)/r = kF (1 - q/2)^3 of the Wendland C2 kernel from |r|^2
-template <class Real>
-__device__ __forceinline__ Real kernel_F(Real r2, Real inv_h, Real kF) {
-  const Real q = r2 * rsq(r2) * inv_h;
-  const Real t = (Real)1 - (Real)0.5 * q;
-  return r2 > (Real)0 ? kF * t * t * t : kF;
-}
-
-// rows are streamed once per sweep: non-temporal loads keep them from
-// evicting the gathered particle state in L2
-template <class T>
-__device__ __forceinline__ T ldnt(const GLB T* p) {
-  return __builtin_nontemporal_load(p);
-}
 
 // Rows are walked ROW_UNROLL entries at a time (SOLID_UNROLL for the wall
 // rows), and the next group's indices are loaded before the current group's
@@ -1610,7 +1394,6 @@ __global__ __launch_bounds__(BLOCK) void k_end(const SlotDesc* table, LaunchTab 
 // per-body force, torque, axial torque, power and heat flow; time integrals;
 // advance t and the step counter.
 // ---------------------------------------------------------------------------
-constexpr int FINAL_BLOCK = 1024;
 __global__ __launch_bounds__(FINAL_BLOCK) void k_final(const SlotDesc* table, LaunchTab tab) {
   __shared__ double res[NGLOB + NB * 13 + 1];
   SLOT_PROLOGUE(DOM_SLOT);
@@ -1714,278 +1497,6 @@ __global__ __launch_bounds__(FINAL_BLOCK) void k_final(const SlotDesc* table, La
   R.flags = (int32_t)C->flags;
 }
 
-
-// ===========================================================================
-// Physics-driven particle relaxation (Section 2.2, eq. 5-9) of a slot's fluid
-// particles inside an analytic shape.  Every level-set evaluation is FP64.
-// ===========================================================================
-
-// signed distance of the extrusion along y (|y| <= half) of a cross-section
-// with signed distance d2
-__device__ double ls_extrude(double d2, double y, double half) {
-  const double dy = fabs(y) - half;
-  const double ox = fmax(d2, 0.0), oy = fmax(dy, 0.0);
-  return sqrt(ox * ox + oy * oy) + fmin(fmax(d2, dy), 0.0);
-}
-
-// point (px, pz) in the gear frame; the angle of tooth coordinate u
-__device__ __forceinline__ double ls_angle(const RelaxShape& g, double u) {
-  return 2.0 * M_PI * (u - 0.25 - g.phase) / (double)g.teeth;
-}
-
-// distance to the radial flank at tooth coordinate u (radius r_root..r_tip)
-__device__ double ls_flank(const RelaxShape& g, double px, double pz, double u) {
-  double sn, cs;
-  sincos(ls_angle(g, u), &sn, &cs);
-  const double t = fmin(fmax(px * cs + pz * sn, g.size[1]), g.size[0]);
-  const double ex = px - t * cs, ez = pz - t * sn;
-  return sqrt(ex * ex + ez * ez);
-}
-
-// Gear cross-section: root disk plus teeth where frac(u) < 1/2, u = z theta /
-// 2 pi + 1/4 + phase.  Boundary: tip arcs over teeth, root arcs over gaps and
-// radial flanks at half-integer u; the nearest piece belongs to the point's
-// half-pitch or one of its two neighbours.
-__device__ double ls_gear2d(const RelaxShape& g, double px, double pz) {
-  const double r = sqrt(px * px + pz * pz);
-  const double u = (double)g.teeth * atan2(pz, px) / (2.0 * M_PI) + 0.25 + g.phase;
-  const double k = floor(2.0 * u);
-  double best = INFINITY;
-  for (int m = -1; m <= 2; ++m) {
-    const double kk = k + (double)m;
-    const double u0 = 0.5 * kk;
-    best = fmin(best, ls_flank(g, px, pz, u0));
-    if (m == 2) break;
-    // arc of this half-pitch: tip over a tooth (even index), root over a gap
-    const double R = fmod(fabs(kk), 2.0) == 0.0 ? g.size[0] : g.size[1];
-    if (m == 0) {
-      best = fmin(best, fabs(r - R));
-    } else {
-      for (int e = 0; e < 2; ++e) {
-        double sn, cs;
-        sincos(ls_angle(g, e ? u0 + 0.5 : u0), &sn, &cs);
-        const double ex = px - R * cs, ez = pz - R * sn;
-        best = fmin(best, sqrt(ex * ex + ez * ez));
-      }
-    }
-  }
-  const bool in = r <= g.size[1] || (r <= g.size[0] && u - floor(u) < 0.5);
-  return in ? -best : best;
-}
-
-// signed distance of the relaxation region (negative inside it)
-__device__ double ls_phi(const RelaxShape& g, double x, double y, double z) {
-  const double dx = x - g.center[0], dy = y - g.center[1], dz = z - g.center[2];
-  double phi;
-  switch (g.kind) {
-    case SPH_SHAPE_SPHERE: phi = sqrt(dx * dx + dy * dy + dz * dz) - g.size[0]; break;
-    case SPH_SHAPE_BOX: {
-      const double qx = fabs(dx) - g.size[0], qy = fabs(dy) - g.size[1], qz = fabs(dz) - g.size[2];
-      const double ox = fmax(qx, 0.0), oy = fmax(qy, 0.0), oz = fmax(qz, 0.0);
-      phi = sqrt(ox * ox + oy * oy + oz * oz) + fmin(fmax(qx, fmax(qy, qz)), 0.0);
-      break;
-    }
-    case SPH_SHAPE_CYLINDER: phi = ls_extrude(sqrt(dx * dx + dz * dz) - g.size[0], dy, g.size[1]); break;
-    default: phi = ls_extrude(ls_gear2d(g, dx, dz), dy, g.size[2]); break;
-  }
-  return g.inside ? phi : -phi;
-}
-
-// K: relaxation force of eq. 7 on every particle, F_p = -(2/m) V p0 (sum_j V_j
-// grad_i W_ij + I_i): the neighbour sum from the rows (as the other sweeps),
-// I_i the kernel-gradient integral over the outside of the region (cells of
-// edge h/4 over the cube [-2h, 2h]^3, weighted by the outside fraction
-// clamp(1/2 + phi/edge, 0, 1)), spread over the 64 lanes of the wavefront for
-// each particle that needs it.  Per-block maximum of |F_p|.
-template <class P>
-__global__ __launch_bounds__(BLOCK) void k_relax_force(const SlotDesc* table, LaunchTab tab, RelaxShape g) {
-  typedef typename P::Real Real;
-  typedef typename P::Pos4 Pos4;
-  typedef typename P::Real4 Real4;
-  __shared__ double red[BLOCK / WAVE];
-  SLOT_PROLOGUE(DOM_FLUID);
-  const int i = lb * BLOCK + threadIdx.x;
-  const int lane = threadIdx.x & (WAVE - 1);
-  const bool live_i = i < S.nf;
-  const double h = S.h, del = 0.25 * h, vol = S.vol_w, p0 = 1.0;
-  double sx = 0.0, sy = 0.0, sz = 0.0;
-  double px = 0.0, py = 0.0, pz = 0.0;
-  bool need = false;
-  if (live_i) {
-    const GLB Real4* xo = gpc<Real4>(S.xo);
-    const Real4 oi = xo[i];
-    const uint32_t ci = unpack_index(oi.w);
-    const Real inv_h = (Real)(1.0 / h), kF = (Real)S.kF, csr = (Real)S.cs_r;
-    Real ax = 0, ay = 0, az = 0;
-    const int n = (int)S.nfc[i];
-    const GLB uint32_t* R = gpc<uint32_t>(S.nrec) + (int64_t)(i >> 6) * S.kf * WAVE + lane;
-    for (int k = 0; k < n; ++k) {
-      const uint32_t j = ldnt(R + (int64_t)k * WAVE);
-      Real rx, ry, rz;
-      pair_vec(oi, ci, xo[j], csr, rx, ry, rz);
-      const Real Fk = kernel_F(rx * rx + ry * ry + rz * rz, inv_h, kF);
-      ax += Fk * rx;
-      ay += Fk * ry;
-      az += Fk * rz;
-    }
-    sx = (double)ax * vol;
-    sy = (double)ay * vol;
-    sz = (double)az * vol;
-    const Pos4 x = gpc<Pos4>(S.xa)[i];
-    px = (double)x.x;
-    py = (double)x.y;
-    pz = (double)x.z;
-    need = ls_phi(g, px, py, pz) > -2.0 * h - del;
-  }
-  // exterior integral, one particle at a time across the wavefront
-  constexpr int QK = 8, QN = 2 * QK;
-  double Ix = 0.0, Iy = 0.0, Iz = 0.0;
-  uint64_t todo = __ballot(need);
-  const double dv = del * del * del, cut = 2.0 * h, inv_h = 1.0 / h;
-  while (todo) {
-    const int src = __builtin_ctzll(todo);
-    todo &= todo - 1;
-    const double qx = __shfl(px, src, WAVE), qy = __shfl(py, src, WAVE), qz = __shfl(pz, src, WAVE);
-    double ax = 0.0, ay = 0.0, az = 0.0;
-    for (int q = lane; q < QN * QN * QN; q += WAVE) {
-      const int a = q / (QN * QN) - QK, b = (q / QN) % QN - QK, c = q % QN - QK;
-      const double yx = qx + del * ((double)a + 0.5), yy = qy + del * ((double)b + 0.5),
-                   yz = qz + del * ((double)c + 0.5);
-      const double ex = qx - yx, ey = qy - yy, ez = qz - yz;
-      const double r2 = (ex * ex + ey * ey) + ez * ez;
-      if (!(r2 < cut * cut)) continue;
-      const double f = fmin(0.5 + ls_phi(g, yx, yy, yz) / del, 1.0);
-      if (!(f > 0.0)) continue;
-      const double t = 1.0 - 0.5 * sqrt(r2) * inv_h;
-      const double F = S.kF * t * t * t;
-      const double w = F * (f * dv);
-      ax += w * ex;
-      ay += w * ey;
-      az += w * ez;
-    }
-    ax = wave_sum(ax);
-    ay = wave_sum(ay);
-    az = wave_sum(az);
-    if (lane == src) {
-      Ix = ax;
-      Iy = ay;
-      Iz = az;
-    }
-  }
-  double amag = 0.0;
-  if (live_i) {
-    const double c = -(2.0 / S.mass) * vol * p0;
-    Real4 a;
-    a.x = (Real)(c * (sx + Ix));
-    a.y = (Real)(c * (sy + Iy));
-    a.z = (Real)(c * (sz + Iz));
-    a.w = (Real)0;
-    gp<Real4>(S.ah)[i] = a;
-    const double ax = a.x, ay = a.y, az = a.z;
-    amag = sqrt(ax * ax + ay * ay + az * az);
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) amag = fmax(amag, __shfl_xor(amag, o, WAVE));
-  if (lane == 0) red[threadIdx.x / WAVE] = amag;
-  __syncthreads();
-  if (threadIdx.x == 0)
-    S.glob_part[(size_t)4 * S.nblk[DOM_FLUID] + lb] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-}
-
-// K: max |F_p| over the blocks, the step of eq. 8, dt = 0.25 sqrt(h / max|F_p|)
-__global__ __launch_bounds__(FINAL_BLOCK) void k_relax_max(const SlotDesc* table, LaunchTab tab, int iter) {
-  __shared__ double red[FINAL_BLOCK / WAVE];
-  SLOT_PROLOGUE(DOM_SLOT);
-  (void)lb;
-  const int nblk = S.nblk[DOM_FLUID];
-  const GLB double* q = gpc<double>(S.glob_part + (size_t)4 * nblk);
-  double m = 0.0;
-  for (int k = threadIdx.x; k < nblk; k += FINAL_BLOCK) m = fmax(m, q[k]);
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, WAVE));
-  if (threadIdx.x % WAVE == 0) red[threadIdx.x / WAVE] = m;
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  for (int w = 1; w < FINAL_BLOCK / WAVE; ++w) m = fmax(m, red[w]);
-  m = fmax(m, red[0]);
-  SlotCtl* C = S.ctl;
-  C->relax_amax = m;
-  C->relax_dt = m > 0.0 ? 0.25 * sqrt(S.h / m) : 0.0;
-  if (iter == 0) C->relax_first = m;
-  C->relax_bounded = 0;
-}
-
-// K: move by eq. 9, x += F_p dt^2 / 2, in FP64 on the anchors; a particle
-// that ends with phi > -dp/2 is put back on the level -dp/2 along the unit
-// normal (central differences of phi, step 1e-6 h)
-template <class P>
-__global__ __launch_bounds__(BLOCK) void k_relax_move(const SlotDesc* table, LaunchTab tab, RelaxShape g) {
-  typedef typename P::Pos Pos;
-  typedef typename P::Pos4 Pos4;
-  typedef typename P::Real4 Real4;
-  SLOT_PROLOGUE(DOM_FLUID);
-  const int i = lb * BLOCK + threadIdx.x;
-  bool bounded = false;
-  if (i < S.nf) {
-    const double dt = S.ctl->relax_dt;
-    const Real4 a = gpc<Real4>(S.ah)[i];
-    GLB Pos4* xa = gp<Pos4>(S.xa);
-    Pos4 x4 = xa[i];
-    double x[3] = {(double)x4.x, (double)x4.y, (double)x4.z};
-    const double ac[3] = {(double)a.x, (double)a.y, (double)a.z};
-    for (int k = 0; k < 3; ++k) x[k] += 0.5 * ac[k] * dt * dt;
-    const double phi = ls_phi(g, x[0], x[1], x[2]);
-    if (phi > -0.5 * S.dp) {
-      const double eps = 1e-6 * S.h;
-      double gr[3];
-      for (int k = 0; k < 3; ++k) {
-        double xp[3] = {x[0], x[1], x[2]}, xm[3] = {x[0], x[1], x[2]};
-        xp[k] += eps;
-        xm[k] -= eps;
-        gr[k] = ls_phi(g, xp[0], xp[1], xp[2]) - ls_phi(g, xm[0], xm[1], xm[2]);
-      }
-      const double l = sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
-      for (int k = 0; k < 3; ++k) x[k] -= (phi + 0.5 * S.dp) * (l > 0.0 ? gr[k] / l : 0.0);
-      bounded = true;
-    }
-    x4.x = (Pos)x[0];
-    x4.y = (Pos)x[1];
-    x4.z = (Pos)x[2];
-    xa[i] = x4;
-  }
-  const int nb = __syncthreads_count(bounded);
-  if (threadIdx.x == 0 && nb > 0) atomicAdd(&S.ctl->relax_bounded, nb);
-}
-
-hipError_t launch_relax(int prec, int kid, int iter, const SlotDesc* T, const LaunchTab& L,
-                        const RelaxShape& g, hipStream_t st) {
-  const int dom = kid == SPH_K_RELAX_MAX ? DOM_SLOT : DOM_FLUID;
-  const int nblk = L.blk0[dom][L.n];
-  if (nblk <= 0) return hipSuccess;
-  const dim3 gr(nblk), b(BLOCK);
-  if (kid == SPH_K_RELAX_MAX) {
-    hipLaunchKernelGGL(k_relax_max, gr, dim3(FINAL_BLOCK), 0, st, T, L, iter);
-    return hipGetLastError();
-  }
-  if (kid != SPH_K_RELAX_FORCE && kid != SPH_K_RELAX_MOVE) return hipErrorInvalidValue;
-  const bool force = kid == SPH_K_RELAX_FORCE;
-  switch (prec) {
-    case SPH_PREC_MIXED:
-      if (force) hipLaunchKernelGGL(k_relax_force<PMixed>, gr, b, 0, st, T, L, g);
-      else hipLaunchKernelGGL(k_relax_move<PMixed>, gr, b, 0, st, T, L, g);
-      break;
-    case SPH_PREC_FP64:
-      if (force) hipLaunchKernelGGL(k_relax_force<PF64>, gr, b, 0, st, T, L, g);
-      else hipLaunchKernelGGL(k_relax_move<PF64>, gr, b, 0, st, T, L, g);
-      break;
-    case SPH_PREC_FP32:
-      if (force) hipLaunchKernelGGL(k_relax_force<PF32>, gr, b, 0, st, T, L, g);
-      else hipLaunchKernelGGL(k_relax_move<PF32>, gr, b, 0, st, T, L, g);
-      break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
 
 // ---------------------------------------------------------------------------
 // dispatch

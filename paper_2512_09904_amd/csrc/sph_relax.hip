@@ -1,0 +1,298 @@
+// sph_relax.hip -- physics-driven particle relaxation (arXiv 2512.09904,
+// Section 2.2, eq. 5-9) on gfx950: FP64 level sets of analytic shapes, the
+// relaxation force over the neighbour rows of the solver's own cell sort and
+// build, and the move with level-set confinement.  Launched by sph_relax; one
+// iteration is sort/build -> relax_force -> relax_max -> relax_move.
+#include "sph_device.h"
+
+namespace sphk {
+
+// Every level-set evaluation is FP64.
+
+// signed distance of the extrusion along y (|y| <= half) of a cross-section
+// with signed distance d2
+__device__ double ls_extrude(double d2, double y, double half) {
+  const double dy = fabs(y) - half;
+  const double ox = fmax(d2, 0.0), oy = fmax(dy, 0.0);
+  return sqrt(ox * ox + oy * oy) + fmin(fmax(d2, dy), 0.0);
+}
+
+// Directions of the gear's flanks: entry j (0 <= j < 2 teeth) is the unit
+// vector at the angle of tooth coordinate j/2, theta_j = 2 pi (j/2 - 1/4 -
+// phase) / teeth.  Every block computes the table into LDS once.
+constexpr int MAX_TEETH = 512;
+typedef double d2v __attribute__((ext_vector_type(2)));
+__device__ void ls_flank_table(const RelaxShape& g, d2v* E) {
+  if (g.kind != SPH_SHAPE_GEAR) return;
+  for (int j = threadIdx.x; j < 2 * g.teeth; j += blockDim.x) {
+    double sn, cs;
+    sincos(2.0 * M_PI * (0.5 * (double)j - 0.25 - g.phase) / (double)g.teeth, &sn, &cs);
+    E[j] = d2v{cs, sn};
+  }
+}
+
+// distance from (px, pz) to the radial segment along e from r_root to r_tip
+__device__ __forceinline__ double ls_flank(const RelaxShape& g, double px, double pz, d2v e) {
+  const double t = fmin(fmax(px * e.x + pz * e.y, g.size[1]), g.size[0]);
+  const double ex = px - t * e.x, ez = pz - t * e.y;
+  return sqrt(ex * ex + ez * ez);
+}
+
+// Gear cross-section: root disk plus teeth where frac(u) < 1/2, u = z theta /
+// 2 pi + 1/4 + phase.  Boundary: tip arcs over teeth, root arcs over gaps and
+// radial flanks at half-integer u; the nearest piece belongs to the point's
+// half-pitch k = floor(2u) or one of its two neighbours: flanks k-1 .. k+2,
+// the own arc (radial distance) and the neighbours' arcs (their end points).
+__device__ double ls_gear2d(const RelaxShape& g, const d2v* E, double px, double pz) {
+  const double r = sqrt(px * px + pz * pz);
+  const double u = (double)g.teeth * atan2(pz, px) / (2.0 * M_PI) + 0.25 + g.phase;
+  const int k = (int)floor(2.0 * u);
+  const int n2 = 2 * g.teeth;
+  d2v e[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) e[m] = E[(((k - 1 + m) % n2) + n2) % n2];
+  double best = INFINITY;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) best = fmin(best, ls_flank(g, px, pz, e[m]));
+  // tip arc over a tooth (even half-pitch), root arc over a gap
+  const bool even = (k & 1) == 0;
+  best = fmin(best, fabs(r - (even ? g.size[0] : g.size[1])));
+  const double Rn = even ? g.size[1] : g.size[0];   // the neighbours' arcs
+#pragma unroll
+  for (int m = 0; m < 4; m += 3) {                     // end points k-1, k (left) and k+1, k+2 (right)
+    const d2v a = m == 0 ? e[0] : e[2], b = m == 0 ? e[1] : e[3];
+    const double ax = px - Rn * a.x, az = pz - Rn * a.y, bx = px - Rn * b.x, bz = pz - Rn * b.y;
+    best = fmin(best, fmin(sqrt(ax * ax + az * az), sqrt(bx * bx + bz * bz)));
+  }
+  const bool in = r <= g.size[1] || (r <= g.size[0] && u - floor(u) < 0.5);
+  return in ? -best : best;
+}
+
+// signed distance of the relaxation region (negative inside it); E: the
+// flank table (gear only)
+__device__ double ls_phi(const RelaxShape& g, const d2v* E, double x, double y, double z) {
+  const double dx = x - g.center[0], dy = y - g.center[1], dz = z - g.center[2];
+  double phi;
+  switch (g.kind) {
+    case SPH_SHAPE_SPHERE: phi = sqrt(dx * dx + dy * dy + dz * dz) - g.size[0]; break;
+    case SPH_SHAPE_BOX: {
+      const double qx = fabs(dx) - g.size[0], qy = fabs(dy) - g.size[1], qz = fabs(dz) - g.size[2];
+      const double ox = fmax(qx, 0.0), oy = fmax(qy, 0.0), oz = fmax(qz, 0.0);
+      phi = sqrt(ox * ox + oy * oy + oz * oz) + fmin(fmax(qx, fmax(qy, qz)), 0.0);
+      break;
+    }
+    case SPH_SHAPE_CYLINDER: phi = ls_extrude(sqrt(dx * dx + dz * dz) - g.size[0], dy, g.size[1]); break;
+    default: phi = ls_extrude(ls_gear2d(g, E, dx, dz), dy, g.size[2]); break;
+  }
+  return g.inside ? phi : -phi;
+}
+
+// K: relaxation force of eq. 7 on every particle, F_p = -(2/m) V p0 (sum_j V_j
+// grad_i W_ij + I_i): the neighbour sum from the rows (as the other sweeps),
+// I_i the kernel-gradient integral over the outside of the region (cells of
+// edge h/4 over the cube [-2h, 2h]^3, weighted by the outside fraction
+// clamp(1/2 + phi/edge, 0, 1)), spread over the 64 lanes of the wavefront for
+// each particle that needs it.  Per-block maximum of |F_p|.
+template <class P>
+__global__ __launch_bounds__(BLOCK) void k_relax_force(const SlotDesc* table, LaunchTab tab, RelaxShape g) {
+  typedef typename P::Real Real;
+  typedef typename P::Pos4 Pos4;
+  typedef typename P::Real4 Real4;
+  __shared__ double red[BLOCK / WAVE];
+  __shared__ d2v E[2 * MAX_TEETH];
+  SLOT_PROLOGUE(DOM_FLUID);
+  ls_flank_table(g, E);
+  __syncthreads();
+  const int i = lb * BLOCK + threadIdx.x;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const bool live_i = i < S.nf;
+  const double h = S.h, del = 0.25 * h, vol = S.vol_w, p0 = 1.0;
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+  double px = 0.0, py = 0.0, pz = 0.0, phx = 0.0;
+  bool need = false;
+  if (live_i) {
+    const GLB Real4* xo = gpc<Real4>(S.xo);
+    const Real4 oi = xo[i];
+    const uint32_t ci = unpack_index(oi.w);
+    const Real inv_h = (Real)(1.0 / h), kF = (Real)S.kF, csr = (Real)S.cs_r;
+    Real ax = 0, ay = 0, az = 0;
+    const int n = (int)S.nfc[i];
+    const GLB uint32_t* R = gpc<uint32_t>(S.nrec) + (int64_t)(i >> 6) * S.kf * WAVE + lane;
+    for (int k = 0; k < n; ++k) {
+      const uint32_t j = ldnt(R + (int64_t)k * WAVE);
+      Real rx, ry, rz;
+      pair_vec(oi, ci, xo[j], csr, rx, ry, rz);
+      const Real Fk = kernel_F(rx * rx + ry * ry + rz * rz, inv_h, kF);
+      ax += Fk * rx;
+      ay += Fk * ry;
+      az += Fk * rz;
+    }
+    sx = (double)ax * vol;
+    sy = (double)ay * vol;
+    sz = (double)az * vol;
+    const Pos4 x = gpc<Pos4>(S.xa)[i];
+    px = (double)x.x;
+    py = (double)x.y;
+    pz = (double)x.z;
+    phx = ls_phi(g, E, px, py, pz);
+    need = phx > -2.0 * h - del;
+  }
+  // exterior integral, one particle at a time across the wavefront
+  constexpr int QK = 8, QN = 2 * QK;
+  double Ix = 0.0, Iy = 0.0, Iz = 0.0;
+  uint64_t todo = __ballot(need);
+  const double dv = del * del * del, cut = 2.0 * h, inv_h = 1.0 / h;
+  while (todo) {
+    const int src = __builtin_ctzll(todo);
+    todo &= todo - 1;
+    const double qx = __shfl(px, src, WAVE), qy = __shfl(py, src, WAVE), qz = __shfl(pz, src, WAVE);
+    const double qphi = __shfl(phx, src, WAVE);
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    for (int q = lane; q < QN * QN * QN; q += WAVE) {
+      const int a = q / (QN * QN) - QK, b = (q / QN) % QN - QK, c = q % QN - QK;
+      const double yx = qx + del * ((double)a + 0.5), yy = qy + del * ((double)b + 0.5),
+                   yz = qz + del * ((double)c + 0.5);
+      const double ex = qx - yx, ey = qy - yy, ez = qz - yz;
+      const double r2 = (ex * ex + ey * ey) + ez * ez;
+      if (!(r2 < cut * cut)) continue;
+      // phi is a distance (1-Lipschitz): phi(y) <= phi(x) + |x - y|, so a
+      // cell with phi(x) + |x - y| <= -edge/2 lies wholly inside
+      const double rr = sqrt(r2);
+      if (qphi + rr <= -0.5 * del) continue;
+      const double f = fmin(0.5 + ls_phi(g, E, yx, yy, yz) / del, 1.0);
+      if (!(f > 0.0)) continue;
+      const double t = 1.0 - 0.5 * rr * inv_h;
+      const double F = S.kF * t * t * t;
+      const double w = F * (f * dv);
+      ax += w * ex;
+      ay += w * ey;
+      az += w * ez;
+    }
+    ax = wave_sum(ax);
+    ay = wave_sum(ay);
+    az = wave_sum(az);
+    if (lane == src) {
+      Ix = ax;
+      Iy = ay;
+      Iz = az;
+    }
+  }
+  double amag = 0.0;
+  if (live_i) {
+    const double c = -(2.0 / S.mass) * vol * p0;
+    Real4 a;
+    a.x = (Real)(c * (sx + Ix));
+    a.y = (Real)(c * (sy + Iy));
+    a.z = (Real)(c * (sz + Iz));
+    a.w = (Real)0;
+    gp<Real4>(S.ah)[i] = a;
+    const double ax = a.x, ay = a.y, az = a.z;
+    amag = sqrt(ax * ax + ay * ay + az * az);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) amag = fmax(amag, __shfl_xor(amag, o, WAVE));
+  if (lane == 0) red[threadIdx.x / WAVE] = amag;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    S.glob_part[(size_t)4 * S.nblk[DOM_FLUID] + lb] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+// K: max |F_p| over the blocks, the step of eq. 8, dt = 0.25 sqrt(h / max|F_p|)
+__global__ __launch_bounds__(FINAL_BLOCK) void k_relax_max(const SlotDesc* table, LaunchTab tab, int iter) {
+  __shared__ double red[FINAL_BLOCK / WAVE];
+  SLOT_PROLOGUE(DOM_SLOT);
+  (void)lb;
+  const int nblk = S.nblk[DOM_FLUID];
+  const GLB double* q = gpc<double>(S.glob_part + (size_t)4 * nblk);
+  double m = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += FINAL_BLOCK) m = fmax(m, q[k]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, WAVE));
+  if (threadIdx.x % WAVE == 0) red[threadIdx.x / WAVE] = m;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int w = 1; w < FINAL_BLOCK / WAVE; ++w) m = fmax(m, red[w]);
+  m = fmax(m, red[0]);
+  SlotCtl* C = S.ctl;
+  C->relax_amax = m;
+  C->relax_dt = m > 0.0 ? 0.25 * sqrt(S.h / m) : 0.0;
+  if (iter == 0) C->relax_first = m;
+  C->relax_bounded = 0;
+}
+
+// K: move by eq. 9, x += F_p dt^2 / 2, in FP64 on the anchors; a particle
+// that ends with phi > -dp/2 is put back on the level -dp/2 along the unit
+// normal (central differences of phi, step 1e-6 h)
+template <class P>
+__global__ __launch_bounds__(BLOCK) void k_relax_move(const SlotDesc* table, LaunchTab tab, RelaxShape g) {
+  typedef typename P::Pos Pos;
+  typedef typename P::Pos4 Pos4;
+  typedef typename P::Real4 Real4;
+  __shared__ d2v E[2 * MAX_TEETH];
+  SLOT_PROLOGUE(DOM_FLUID);
+  ls_flank_table(g, E);
+  __syncthreads();
+  const int i = lb * BLOCK + threadIdx.x;
+  bool bounded = false;
+  if (i < S.nf) {
+    const double dt = S.ctl->relax_dt;
+    const Real4 a = gpc<Real4>(S.ah)[i];
+    GLB Pos4* xa = gp<Pos4>(S.xa);
+    Pos4 x4 = xa[i];
+    double x[3] = {(double)x4.x, (double)x4.y, (double)x4.z};
+    const double ac[3] = {(double)a.x, (double)a.y, (double)a.z};
+    for (int k = 0; k < 3; ++k) x[k] += 0.5 * ac[k] * dt * dt;
+    const double phi = ls_phi(g, E, x[0], x[1], x[2]);
+    if (phi > -0.5 * S.dp) {
+      const double eps = 1e-6 * S.h;
+      double gr[3];
+      for (int k = 0; k < 3; ++k) {
+        double xp[3] = {x[0], x[1], x[2]}, xm[3] = {x[0], x[1], x[2]};
+        xp[k] += eps;
+        xm[k] -= eps;
+        gr[k] = ls_phi(g, E, xp[0], xp[1], xp[2]) - ls_phi(g, E, xm[0], xm[1], xm[2]);
+      }
+      const double l = sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
+      for (int k = 0; k < 3; ++k) x[k] -= (phi + 0.5 * S.dp) * (l > 0.0 ? gr[k] / l : 0.0);
+      bounded = true;
+    }
+    x4.x = (Pos)x[0];
+    x4.y = (Pos)x[1];
+    x4.z = (Pos)x[2];
+    xa[i] = x4;
+  }
+  const int nb = __syncthreads_count(bounded);
+  if (threadIdx.x == 0 && nb > 0) atomicAdd(&S.ctl->relax_bounded, nb);
+}
+
+hipError_t launch_relax(int prec, int kid, int iter, const SlotDesc* T, const LaunchTab& L,
+                        const RelaxShape& g, hipStream_t st) {
+  const int dom = kid == SPH_K_RELAX_MAX ? DOM_SLOT : DOM_FLUID;
+  const int nblk = L.blk0[dom][L.n];
+  if (nblk <= 0) return hipSuccess;
+  const dim3 gr(nblk), b(BLOCK);
+  if (kid == SPH_K_RELAX_MAX) {
+    hipLaunchKernelGGL(k_relax_max, gr, dim3(FINAL_BLOCK), 0, st, T, L, iter);
+    return hipGetLastError();
+  }
+  if (kid != SPH_K_RELAX_FORCE && kid != SPH_K_RELAX_MOVE) return hipErrorInvalidValue;
+  const bool force = kid == SPH_K_RELAX_FORCE;
+  switch (prec) {
+    case SPH_PREC_MIXED:
+      if (force) hipLaunchKernelGGL(k_relax_force<PMixed>, gr, b, 0, st, T, L, g);
+      else hipLaunchKernelGGL(k_relax_move<PMixed>, gr, b, 0, st, T, L, g);
+      break;
+    case SPH_PREC_FP64:
+      if (force) hipLaunchKernelGGL(k_relax_force<PF64>, gr, b, 0, st, T, L, g);
+      else hipLaunchKernelGGL(k_relax_move<PF64>, gr, b, 0, st, T, L, g);
+      break;
+    case SPH_PREC_FP32:
+      if (force) hipLaunchKernelGGL(k_relax_force<PF32>, gr, b, 0, st, T, L, g);
+      else hipLaunchKernelGGL(k_relax_move<PF32>, gr, b, 0, st, T, L, g);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace sphk
