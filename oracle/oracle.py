@@ -354,9 +354,13 @@ def timestep(params, bodies, x0, body, v):
 class State:
     """Oracle state of one case: FP64 fluid arrays in the case's particle order."""
 
-    def __init__(self, case, **param_over):
+    def __init__(self, case, k=None, cp=None, **param_over):
+        """k, cp: optional per-particle thermal conductivity and specific heat
+        (several fluid materials); default the case's k_f, cp_f."""
         self.params = dict(case.params)
         self.params.update(param_over)
+        self.k = None if k is None else np.ascontiguousarray(k, dtype=np.float64)
+        self.cp = None if cp is None else np.ascontiguousarray(cp, dtype=np.float64)
         self.P = make_params(self.params)
         self.bodies = list(case.bodies)
         self.nb, self.B = _bodies_arg(self.bodies)
@@ -387,10 +391,12 @@ class State:
                 rates_np[name] = arr
                 setattr(rates, name, arr.ctypes.data)
         t = C.c_double(self.t)
-        rc = lib().ora_step(C.byref(self.P), C.c_int32(self.nb), self.B, C.c_int64(nf), _p(self.x), _p(self.v),
-                            _p(self.rho), _p(self.T), _p(self.drho), C.c_int64(len(self.x0)), _p(self.x0),
-                            _p(self.n0), _p(self.body), C.byref(t), C.byref(rep), brep,
-                            C.byref(rates) if rates is not None else None)
+        rc = lib().ora_step_kc(C.byref(self.P), C.c_int32(self.nb), self.B, C.c_int64(nf), _p(self.x),
+                               _p(self.v), _p(self.rho), _p(self.T), _p(self.drho), C.c_int64(len(self.x0)),
+                               _p(self.x0), _p(self.n0), _p(self.body),
+                               _p(self.k) if self.k is not None else None,
+                               _p(self.cp) if self.cp is not None else None, C.byref(t), C.byref(rep), brep,
+                               C.byref(rates) if rates is not None else None)
         if rc != 0:
             raise RuntimeError(f"ora_step failed: {rc}")
         self.t = t.value
@@ -411,7 +417,8 @@ class State:
 
     def totals(self):
         out = np.zeros(5)
-        lib().ora_totals(C.byref(self.P), C.c_int64(len(self.x)), _p(self.v), _p(self.rho), _p(self.T), _p(out))
+        lib().ora_totals_cp(C.byref(self.P), C.c_int64(len(self.x)), _p(self.v), _p(self.rho), _p(self.T),
+                            _p(self.cp) if self.cp is not None else None, _p(out))
         return dict(mass=out[0], kinetic=out[1], thermal=out[2], mass_proxy=out[3], vmax=out[4])
 
 

@@ -829,6 +829,11 @@ void ora_timestep(const ora_params* P, int32_t nbody, const ora_body* B, int64_t
 
 void ora_totals(const ora_params* P, int64_t nf, const double* v, const double* rho,
                 const double* T, double* out5) {
+  ora_totals_cp(P, nf, v, rho, T, NULL, out5);
+}
+
+void ora_totals_cp(const ora_params* P, int64_t nf, const double* v, const double* rho,
+                   const double* T, const double* cp, double* out5) {
   double m = P->rho0 * P->dp * P->dp * P->dp;
   ksum km = {0, 0}, ke = {0, 0}, kt = {0, 0}, kp = {0, 0};
   double vm = 0.0;
@@ -836,7 +841,7 @@ void ora_totals(const ora_params* P, int64_t nf, const double* v, const double* 
     double v2 = dot3(v + 3 * i, v + 3 * i);
     kadd(&km, m);
     kadd(&ke, 0.5 * m * v2);
-    kadd(&kt, m * P->cp_f * T[i]);
+    kadd(&kt, m * (cp ? cp[i] : P->cp_f) * T[i]);
     kadd(&kp, rho[i] * P->dp * P->dp * P->dp);
     if (sqrt(v2) > vm) vm = sqrt(v2);
   }
@@ -850,6 +855,13 @@ int ora_step(const ora_params* P, int32_t nbody, const ora_body* B, int64_t nf, 
              double* v, double* rho, double* T, double* drho, int64_t ns, const double* x0,
              const double* n0, const int32_t* body, double* t, ora_report* rep,
              ora_body_report* brep, ora_rates* rates) {
+  return ora_step_kc(P, nbody, B, nf, x, v, rho, T, drho, ns, x0, n0, body, NULL, NULL, t, rep, brep, rates);
+}
+
+int ora_step_kc(const ora_params* P, int32_t nbody, const ora_body* B, int64_t nf, double* x,
+                double* v, double* rho, double* T, double* drho, int64_t ns, const double* x0,
+                const double* n0, const int32_t* body, const double* k_in, const double* cp_in,
+                double* t, ora_report* rep, ora_body_report* brep, ora_rates* rates) {
   int rc = ORA_OK;
   double dp3 = P->dp * P->dp * P->dp;
   double m0 = P->rho0 * dp3;
@@ -876,7 +888,11 @@ int ora_step(const ora_params* P, int32_t nbody, const ora_body* B, int64_t nf, 
     SG = malloc(sizeof(double) * nfz);
     if (!G || !phi || !SG) { rc = ORA_ERR_OOM; goto done; }
   }
-  for (int64_t i = 0; i < nf; ++i) { mass[i] = m0; kf[i] = P->k_f; cpf[i] = P->cp_f; }
+  for (int64_t i = 0; i < nf; ++i) {
+    mass[i] = m0;
+    kf[i] = k_in ? k_in[i] : P->k_f;
+    cpf[i] = cp_in ? cp_in[i] : P->cp_f;
+  }
 
   /* 1. bodies at t_n */
   ora_body_pose(nbody, B, ns, x0, n0, body, *t, xs, nsv, vs);
@@ -945,7 +961,7 @@ int ora_step(const ora_params* P, int32_t nbody, const ora_body* B, int64_t nf, 
   }
   if (rep) {
     double tot[5];
-    ora_totals(P, nf, v, rho, T, tot);
+    ora_totals_cp(P, nf, v, rho, T, cpf, tot);
     ksum kq = {0, 0};
     for (int32_t b = 0; b < nbody; ++b) kadd(&kq, bq[b]);
     rep->t = *t; rep->dt_ad = dt_ad; rep->dt = dt; rep->n_ac = n_ac; rep->pad = 0;

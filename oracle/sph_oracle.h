@@ -131,9 +131,18 @@ int ora_step(const ora_params* P, int32_t nbody, const ora_body* B, int64_t nf, 
              double* v, double* rho, double* T, double* drho, int64_t ns, const double* x0,
              const double* n0, const int32_t* body, double* t, ora_report* rep,
              ora_body_report* brep, ora_rates* rates);
-/* totals of the state: mass, kinetic, thermal, mass proxy, vmax (Neumaier sums) */
+/* One advection step with per-particle thermal conductivity k_in and specific
+   heat cp_in (several fluid materials in eq. 22; either NULL: k_f, cp_f). */
+int ora_step_kc(const ora_params* P, int32_t nbody, const ora_body* B, int64_t nf, double* x,
+                double* v, double* rho, double* T, double* drho, int64_t ns, const double* x0,
+                const double* n0, const int32_t* body, const double* k_in, const double* cp_in,
+                double* t, ora_report* rep, ora_body_report* brep, ora_rates* rates);
+/* totals of the state: mass, kinetic, thermal, mass proxy, vmax (Neumaier sums);
+   the _cp form takes per-particle specific heats (NULL: cp_f) */
 void ora_totals(const ora_params* P, int64_t nf, const double* v, const double* rho,
                 const double* T, double* out5);
+void ora_totals_cp(const ora_params* P, int64_t nf, const double* v, const double* rho,
+                   const double* T, const double* cp, double* out5);
 
 /* --- physics-driven particle relaxation (Section 2.2, eq. 5-9) ----------- */
 enum { ORA_SHAPE_SPHERE = 1, ORA_SHAPE_BOX = 2, ORA_SHAPE_CYLINDER = 3, ORA_SHAPE_GEAR = 4 };

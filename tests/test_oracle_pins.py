@@ -611,3 +611,51 @@ def test_step_heat_balance_with_viscous_heating(ora):
         assert np.all(r["rates"]["phi"] >= 0.0)
     np.testing.assert_array_equal(on.v, off.v)
     assert np.all(on.T >= off.T - 1e-12 * np.abs(off.T))
+
+
+# --------------------------------------------------------------------------
+# Several fluid materials in eq. 22 (per-particle k and cp through a step)
+# --------------------------------------------------------------------------
+
+def _two_material_tank():
+    c = cases.tank_c1(seed=3)
+    left = c.xf[:, 0] < 0.02
+    c.Tf = np.where(left, c.Tf + 5.0, c.Tf)
+    k = np.where(left, 0.13, 0.45)
+    cp = np.where(left, 2000.0, 1300.0)
+    return c, k, cp
+
+
+def test_step_with_uniform_materials_is_the_default_step(ora):
+    """Per-particle k = k_f and cp = cp_f everywhere reproduce the step of the
+    case's own constants bit for bit."""
+    c = cases.tank_c1(seed=3)
+    a = ora.State(c)
+    b = ora.State(c, k=np.full(c.nf, c.params["k_f"]), cp=np.full(c.nf, c.params["cp_f"]))
+    ra, rb = a.step(), b.step()
+    for name in ("x", "v", "rho", "T"):
+        np.testing.assert_array_equal(getattr(a, name), getattr(b, name))
+    assert ra["thermal"] == rb["thermal"] and ra["heat_step"] == rb["heat_step"]
+
+
+def test_step_heat_balance_two_materials(ora):
+    """Two materials with a 5 K step between them: the thermal energy sum m cp_i
+    T_i gains exactly the wall heat (the conduction between the materials,
+    K_ij = 4 k_i k_j / (k_i + k_j), cancels pairwise), the hot side cools and
+    the cold side warms, and the report's thermal energy uses cp_i."""
+    c, k, cp = _two_material_tank()
+    s = ora.State(c, k=k, cp=cp)
+    m = 870.0 * (2e-3) ** 3
+    left = c.xf[:, 0] < 0.02
+    for _ in range(2):
+        T0 = s.T.copy()
+        r = s.step()
+        dE = m * cp * (s.T - T0)
+        assert abs(math.fsum(dE) - r["heat_step"]) <= 1e-10 * math.fsum(np.abs(dE))
+        assert r["thermal"] == pytest.approx(math.fsum(m * cp * s.T), rel=1e-14)
+    # away from the walls and the disk, across the material boundary x = 20 mm
+    core = (np.abs(c.xf[:, 1] - 0.025) < 0.015) & (c.xf[:, 2] > 0.006) & (c.xf[:, 2] < 0.014)
+    iface_l = core & left & (c.xf[:, 0] > 0.02 - 3e-3)
+    iface_r = core & ~left & (c.xf[:, 0] < 0.02 + 3e-3)
+    assert iface_l.sum() > 20 and iface_r.sum() > 20
+    assert np.all(s.T[iface_l] < c.Tf[iface_l]) and np.all(s.T[iface_r] > c.Tf[iface_r])
