@@ -61,6 +61,9 @@ typedef struct {
   void* user;
 } sph_allocator;
 
+/* fluid materials of one solve (thermal properties of eq. 22) */
+#define SPH_MAX_MATERIALS 8
+
 /* Problem parameters (Section 2 and Tables 5-6 of the paper). */
 typedef struct {
   double dp;            /* particle spacing [m]; fluid mass = rho0 dp^3, solid volume = dp^3 */
@@ -86,6 +89,12 @@ typedef struct {
                               rate from the SPH velocity gradient over fluid and wall neighbours) to
                               dT/dt as Phi/(rho cp); 0: the paper's model, conduction only */
   int32_t reserved;     /* must be 0 */
+  int32_t n_materials;  /* 0: one fluid material (k_f, cp_f); 1..SPH_MAX_MATERIALS: the table below,
+                           indexed by the per-particle material of sph_set_fluid / sph_pool_admit
+                           (eq. 22 with k_i, k_j, cp_i per particle; density and viscosity shared) */
+  int32_t reserved2;    /* must be 0 */
+  double mat_k[SPH_MAX_MATERIALS];   /* thermal conductivity of each material [W/(m K)] */
+  double mat_cp[SPH_MAX_MATERIALS];  /* specific heat of each material [J/(kg K)] */
 } sph_params;
 
 /* A rigid body turning at a prescribed speed about a fixed axis; its solid
@@ -137,9 +146,10 @@ const char* sph_last_error(void);
 int sph_create(const sph_params* p, const sph_allocator* a, void* hip_stream, sph_solver** out);
 /* Bodies: n in [1, SPH_MAX_BODIES]; axis need not be unit length. */
 int sph_set_bodies(sph_solver* s, int32_t n, const sph_body* b);
-/* Fluid particles: positions, velocities, densities, temperatures (copied at sph_init). */
+/* Fluid particles: positions, velocities, densities, temperatures and material
+ * indices (nullable: all 0; each below max(n_materials, 1)); copied at sph_init. */
 int sph_set_fluid(sph_solver* s, int64_t n, const double* x, const double* v, const double* rho,
-                  const double* T);
+                  const double* T, const int32_t* material);
 /* Solid particles at t = 0 in the world frame: positions, unit normals pointing
  * into the fluid, body index of each. */
 int sph_set_solid(sph_solver* s, int64_t n, const double* x0, const double* n0,
@@ -261,13 +271,14 @@ int sph_pool_create(size_t hbm_budget, int32_t max_slots, int32_t precision,
  * as for sph_set_fluid / sph_set_solid; precision in p is ignored. */
 int sph_pool_admit(sph_pool* pool, const sph_params* p, int32_t nbody, const sph_body* b,
                    int64_t nf, const double* x, const double* v, const double* rho,
-                   const double* T, int64_t ns, const double* x0, const double* n0,
-                   const int32_t* body, int64_t target_steps, int32_t* slot);
+                   const double* T, const int32_t* material, int64_t ns, const double* x0,
+                   const double* n0, const int32_t* body, int64_t target_steps, int32_t* slot);
 /* Enqueue n advection steps for every active slot in batched launches. */
 int sph_pool_step(sph_pool* pool, int32_t n_adv_steps);
 /* Non-blocking: *done = 1 once the slot has finished its target steps (or
  * faulted) and its work has completed on the device; then reports are filled.
- * The return value carries the slot's latched fault, if any. */
+ * The return value carries the slot's latched fault, if any.  Until the
+ * slot's upload has run on the stream, *done stays 0 and nothing is read. */
 int sph_pool_poll(sph_pool* pool, int32_t slot, int32_t* done, sph_report* r,
                   sph_body_report* per_body);
 int sph_pool_get_fluid(sph_pool* pool, int32_t slot, double* x, double* v, double* rho,

@@ -90,6 +90,7 @@ class Case:
     ns0: np.ndarray
     body: np.ndarray
     meta: dict = dataclasses.field(default_factory=dict)
+    material: Optional[np.ndarray] = None   # fluid material index per particle (params["materials"])
 
     @property
     def nf(self) -> int:
@@ -103,7 +104,8 @@ class Case:
         return dataclasses.replace(
             self, params=dict(self.params), bodies=[dataclasses.replace(b) for b in self.bodies],
             xf=self.xf.copy(), vf=self.vf.copy(), rhof=self.rhof.copy(), Tf=self.Tf.copy(),
-            xs0=self.xs0.copy(), ns0=self.ns0.copy(), body=self.body.copy(), meta=dict(self.meta))
+            xs0=self.xs0.copy(), ns0=self.ns0.copy(), body=self.body.copy(), meta=dict(self.meta),
+            material=None if self.material is None else self.material.copy())
 
 
 def default_params(dp: float, rho0: float, c0: float, nu: float, k_f: float, cp_f: float,

@@ -56,6 +56,7 @@ struct Plan {
   int32_t ncells = 0, dims[3] = {0, 0, 0}, nslices = 0, kf = 0, ks = 0;
   int32_t nblk[NDOM] = {0, 0, 0, 0};
   int64_t rowlen_f = 0, rowlen_s = 0;
+  int32_t nmat = 1;
   size_t pos_sz = 8, real_sz = 4, temp_sz = 8;
   size_t total = 0;
 };
@@ -76,7 +77,12 @@ static int make_plan(const sph_params* p, int prec, int64_t nf, int64_t ns, Plan
     return fail(SPH_ERR_ARG, "particle counts out of range");
   if (p->fixed_dt_ad > 0 && p->fixed_nac < 1) return fail(SPH_ERR_ARG, "fixed_nac must be >= 1");
   if (p->viscous_heating != 0 && p->viscous_heating != 1) return fail(SPH_ERR_ARG, "viscous_heating must be 0 or 1");
-  if (p->reserved != 0) return fail(SPH_ERR_ARG, "reserved must be 0");
+  if (p->reserved != 0 || p->reserved2 != 0) return fail(SPH_ERR_ARG, "reserved fields must be 0");
+  if (p->n_materials < 0 || p->n_materials > SPH_MAX_MATERIALS)
+    return fail(SPH_ERR_ARG, "n_materials must be in [0, 8]");
+  for (int m = 0; m < p->n_materials; ++m)
+    if (!(p->mat_k[m] > 0) || !(p->mat_cp[m] > 0)) return fail(SPH_ERR_ARG, "material k and cp must be > 0");
+  P->nmat = p->n_materials > 1 ? p->n_materials : 1;
   const double h = p->h_over_dp * p->dp;
   const double cs = 2.0 * h;
   int64_t ncell = 1;
@@ -151,6 +157,10 @@ static size_t carve(const Plan& P, void* base, SlotDesc* d) {
   C.takev(D.drho2, nf * rs);
   C.takev(D.T2, nf * ts);
   C.take(D.fid2, nf * 4);
+  if (P.nmat > 1) {
+    C.take(D.mat, nf * 4);
+    C.take(D.mat2, nf * 4);
+  }
   C.take(D.nfc, nf * 4);
   C.take(D.nsc, nf * 4);
   C.take(D.nrec, 4 * (size_t)P.rowlen_f);
@@ -286,6 +296,7 @@ struct SlotHost {
   int64_t target = 0, launched = 0;
   hipEvent_t ev_done = nullptr;
   bool ev_recorded = false;
+  hipEvent_t ev_admit = nullptr;   // the slot's upload has completed on the main stream
   std::vector<uint32_t> morton_of_rank;
   std::vector<char> staging;
 };
@@ -324,6 +335,7 @@ struct sph_solver {
   int32_t nbody = 0;
   sph_body bodies[NB];
   std::vector<double> x, v, rho, T, x0, n0;
+  std::vector<int32_t> material;
   std::vector<int32_t> body;
   int64_t nf = 0, ns = 0;
 };
@@ -445,6 +457,7 @@ static void tab_for(sph_pool* P, const std::vector<int>& slots, LaunchTab& T) {
   for (size_t k = 0; k < slots.size(); ++k) {
     T.slot[k] = slots[k];
     if (P->slots[slots[k]].d.diss) T.flags |= TAB_DISS;
+    if (P->slots[slots[k]].d.nmat > 1) T.flags |= TAB_MAT;
     const Plan& pl = P->slots[slots[k]].plan;
     for (int d = 0; d < NDOM; ++d) T.blk0[d][k + 1] = T.blk0[d][k] + pl.nblk[d];
   }
@@ -526,7 +539,8 @@ static void put(std::vector<char>& buf, size_t off, T val) {
 
 // host copies converted to the device layout of a slot
 static int upload_slot(sph_pool* P, SlotHost& S, const double* x, const double* v, const double* rho,
-                       const double* T, const double* x0, const double* n0, const int32_t* body) {
+                       const double* T, const int32_t* material, const double* x0, const double* n0,
+                       const int32_t* body) {
   const Plan& pl = S.plan;
   const size_t nf = (size_t)pl.nf, ns = (size_t)pl.ns;
   const size_t ps = pl.pos_sz, rs = pl.real_sz, ts = pl.temp_sz;
@@ -535,9 +549,10 @@ static int upload_slot(sph_pool* P, SlotHost& S, const double* x, const double* 
   std::vector<uint32_t> rank;
   rank_table(pl.dims, rank, S.morton_of_rank);
   // staging: xa (x,y,z,0) | vr (vx,vy,vz,rho) | T | fid | x0 (x,y,z,0) | n0 | body | sid | rank
+  const size_t nm = pl.nmat > 1 ? nf : 0;
   const size_t o_xa = 0, o_v = o_xa + 4 * nf * ps, o_T = o_v + 4 * nf * rs, o_fid = o_T + nf * ts,
-               o_x0 = o_fid + nf * 4, o_n0 = o_x0 + ns * 32, o_b = o_n0 + ns * 32, o_sid = o_b + ns * 4,
-               o_rank = o_sid + ns * 4, o_end = o_rank + rank.size() * 4;
+               o_mat = o_fid + nf * 4, o_x0 = o_mat + nm * 4, o_n0 = o_x0 + ns * 32, o_b = o_n0 + ns * 32,
+               o_sid = o_b + ns * 4, o_rank = o_sid + ns * 4, o_end = o_rank + rank.size() * 4;
   S.staging.assign(o_end, 0);
   std::vector<char>& B = S.staging;
   auto put_real = [&](size_t off, size_t sz, size_t idx, double val) {
@@ -552,6 +567,7 @@ static int upload_slot(sph_pool* P, SlotHost& S, const double* x, const double* 
     put_real(o_v, rs, 4 * i + 3, rel ? rho[i] - rho0 : rho[i]);
     put_real(o_T, ts, i, T[i]);
     put<uint32_t>(B, o_fid + i * 4, (uint32_t)i);
+    if (nm) put<uint32_t>(B, o_mat + i * 4, material ? (uint32_t)material[i] : 0u);
   }
   for (size_t w = 0; w < ns; ++w) {
     for (size_t k = 0; k < 3; ++k) {
@@ -569,6 +585,7 @@ static int upload_slot(sph_pool* P, SlotHost& S, const double* x, const double* 
   HIPCHK(hipMemcpyAsync(D.vr, B.data() + o_v, 4 * nf * rs, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(D.T, B.data() + o_T, nf * ts, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(D.fid, B.data() + o_fid, nf * 4, hipMemcpyHostToDevice, st));
+  if (nm) HIPCHK(hipMemcpyAsync(D.mat, B.data() + o_mat, nf * 4, hipMemcpyHostToDevice, st));
   if (ns) {
     HIPCHK(hipMemcpyAsync(D.x0, B.data() + o_x0, ns * 32, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(D.n0, B.data() + o_n0, ns * 32, hipMemcpyHostToDevice, st));
@@ -580,8 +597,9 @@ static int upload_slot(sph_pool* P, SlotHost& S, const double* x, const double* 
 }
 
 static int admit(sph_pool* P, const sph_params* p, int32_t nbody, const sph_body* b, int64_t nf,
-                 const double* x, const double* v, const double* rho, const double* T, int64_t ns,
-                 const double* x0, const double* n0, const int32_t* body, int64_t target, int32_t* slot_out) {
+                 const double* x, const double* v, const double* rho, const double* T, const int32_t* material,
+                 int64_t ns, const double* x0, const double* n0, const int32_t* body, int64_t target,
+                 int32_t* slot_out) {
   if (!P || !slot_out) return fail(SPH_ERR_ARG, "NULL pool or slot");
   if (nbody < 1 || nbody > NB || !b) return fail(SPH_ERR_ARG, "need 1..8 bodies");
   if (!x || !rho || !T) return fail(SPH_ERR_ARG, "fluid arrays missing");
@@ -592,6 +610,9 @@ static int admit(sph_pool* P, const sph_params* p, int32_t nbody, const sph_body
   if (rc) return rc;
   for (int64_t w = 0; w < ns; ++w)
     if (body[w] < 0 || body[w] >= nbody) return fail(SPH_ERR_ARG, "solid body index out of range");
+  if (material)
+    for (int64_t i = 0; i < nf; ++i)
+      if (material[i] < 0 || material[i] >= pl.nmat) return fail(SPH_ERR_ARG, "material index out of range");
   for (int k = 0; k < nbody; ++k) {
     const double an = std::sqrt(b[k].axis[0] * b[k].axis[0] + b[k].axis[1] * b[k].axis[1] + b[k].axis[2] * b[k].axis[2]);
     if (!(an > 0) || !(b[k].k > 0)) return fail(SPH_ERR_ARG, "body axis must be non-zero and k > 0");
@@ -634,8 +655,14 @@ static int admit(sph_pool* P, const sph_params* p, int32_t nbody, const sph_body
   D.c0 = p->c0;
   D.nu = p->nu;
   D.eta = p->rho0 * p->nu;
-  D.k_f = p->k_f;
-  D.cp_f = p->cp_f;
+  // one material: k_f, cp_f (or the table's only entry); several: the table
+  D.k_f = p->n_materials >= 1 ? p->mat_k[0] : p->k_f;
+  D.cp_f = p->n_materials >= 1 ? p->mat_cp[0] : p->cp_f;
+  D.nmat = pl.nmat;
+  for (int m = 0; m < NMAT; ++m) {
+    D.mk[m] = m < pl.nmat && p->n_materials > 0 ? p->mat_k[m] : D.k_f;
+    D.mcp[m] = m < pl.nmat && p->n_materials > 0 ? p->mat_cp[m] : D.cp_f;
+  }
   D.mass = p->rho0 * (p->dp * p->dp * p->dp);
   D.vol_w = p->dp * p->dp * p->dp;
   D.S0 = lattice_sum0(p->h_over_dp);
@@ -690,7 +717,7 @@ static int admit(sph_pool* P, const sph_params* p, int32_t nbody, const sph_body
   D.nac_bound = nac_bound(p, vtip);
   S.target = target;
   S.launched = 0;
-  rc = upload_slot(P, S, x, v, rho, T, x0, n0, body);
+  rc = upload_slot(P, S, x, v, rho, T, material, x0, n0, body);
   if (rc) {
     dev_free(P, S.arena);
     S = SlotHost();
@@ -707,6 +734,10 @@ static int admit(sph_pool* P, const sph_params* p, int32_t nbody, const sph_body
   HIPCHK(hipMemcpyAsync(D.ctl, S.staging.data() + tail, sizeof(SlotCtl), hipMemcpyHostToDevice, P->stream));
   HIPCHK(hipMemcpyAsync(P->d_table + s, &S.d, sizeof(SlotDesc), hipMemcpyHostToDevice, P->stream));
   HIPCHK(hipEventCreateWithFlags(&S.ev_done, hipEventDisableTiming));
+  // polls read the control block on the copy stream; they must not see the
+  // arena's earlier contents before the zeroed block has landed
+  HIPCHK(hipEventCreateWithFlags(&S.ev_admit, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(S.ev_admit, P->stream));
   S.used = true;
   P->used += bytes;
   P->comp_dirty = true;
@@ -715,10 +746,10 @@ static int admit(sph_pool* P, const sph_params* p, int32_t nbody, const sph_body
 }
 
 extern "C" int sph_pool_admit(sph_pool* P, const sph_params* p, int32_t nbody, const sph_body* b, int64_t nf,
-                              const double* x, const double* v, const double* rho, const double* T, int64_t ns,
-                              const double* x0, const double* n0, const int32_t* body, int64_t target_steps,
-                              int32_t* slot) {
-  return admit(P, p, nbody, b, nf, x, v, rho, T, ns, x0, n0, body, target_steps, slot);
+                              const double* x, const double* v, const double* rho, const double* T,
+                              const int32_t* material, int64_t ns, const double* x0, const double* n0,
+                              const int32_t* body, int64_t target_steps, int32_t* slot) {
+  return admit(P, p, nbody, b, nf, x, v, rho, T, material, ns, x0, n0, body, target_steps, slot);
 }
 
 static int pool_step(sph_pool* P, int32_t n) {
@@ -804,6 +835,13 @@ extern "C" int sph_pool_poll(sph_pool* P, int32_t slot, int32_t* done, sph_repor
     if (q == hipSuccess) complete = true;
     else if (q != hipErrorNotReady) return fail(SPH_ERR_HIP, std::string("hipEventQuery: ") + hipGetErrorString(q));
   }
+  // until the slot's upload has run, its control block holds whatever the
+  // reused memory held before: nothing to read yet
+  {
+    const hipError_t q = hipEventQuery(S.ev_admit);
+    if (q == hipErrorNotReady) return SPH_OK;
+    if (q != hipSuccess) return fail(SPH_ERR_HIP, std::string("hipEventQuery: ") + hipGetErrorString(q));
+  }
   LCHK(read_ctl(P, S, &c, false));
   if (c.flags) {
     *done = 1;
@@ -838,6 +876,7 @@ extern "C" int sph_pool_release(sph_pool* P, int32_t slot) {
     dev_free(P, S.arena);
   }
   if (S.ev_done) (void)hipEventDestroy(S.ev_done);
+  if (S.ev_admit) (void)hipEventDestroy(S.ev_admit);
   P->used -= S.bytes;
   S = SlotHost();
   return SPH_OK;
@@ -868,6 +907,7 @@ extern "C" int sph_pool_destroy(sph_pool* P) {
     if (S.used) {
       dev_free(P, S.arena);
       if (S.ev_done) (void)hipEventDestroy(S.ev_done);
+      if (S.ev_admit) (void)hipEventDestroy(S.ev_admit);
     }
   }
   dev_free(P, P->d_table);
@@ -954,7 +994,7 @@ extern "C" int sph_set_bodies(sph_solver* s, int32_t n, const sph_body* b) {
 }
 
 extern "C" int sph_set_fluid(sph_solver* s, int64_t n, const double* x, const double* v, const double* rho,
-                             const double* T) {
+                             const double* T, const int32_t* material) {
   if (!s || n < 1 || !x || !rho || !T) return fail(SPH_ERR_ARG, "fluid arrays missing");
   if (s->inited) return fail(SPH_ERR_STATE, "already initialised");
   s->nf = n;
@@ -963,6 +1003,8 @@ extern "C" int sph_set_fluid(sph_solver* s, int64_t n, const double* x, const do
   if (v) s->v.assign(v, v + 3 * n);
   s->rho.assign(rho, rho + n);
   s->T.assign(T, T + n);
+  s->material.clear();
+  if (material) s->material.assign(material, material + n);
   return SPH_OK;
 }
 
@@ -982,7 +1024,8 @@ extern "C" int sph_init(sph_solver* s) {
   if (s->nbody < 1 || s->nf < 1) return fail(SPH_ERR_STATE, "bodies and fluid must be set first");
   int32_t slot = -1;
   int rc = admit(s->pool, &s->p, s->nbody, s->bodies, s->nf, s->x.data(), s->v.data(), s->rho.data(), s->T.data(),
-                 s->ns, s->x0.data(), s->n0.data(), s->body.data(), INT64_MAX, &slot);
+                 s->material.empty() ? nullptr : s->material.data(), s->ns, s->x0.data(), s->n0.data(),
+                 s->body.data(), INT64_MAX, &slot);
   if (rc) return rc;
   sph_pool* P = s->pool;
   LaunchTab T;
@@ -997,6 +1040,7 @@ extern "C" int sph_init(sph_solver* s) {
   s->v.clear();
   s->rho.clear();
   s->T.clear();
+  s->material.clear();
   if (c.flags) return fail(flag_code(c.flags), "initial build faulted");
   return SPH_OK;
 }
@@ -1098,7 +1142,8 @@ extern "C" int sph_relax(sph_solver* s, const sph_shape* sh, int32_t iterations,
     g.center[a] = sh->center[a];
     g.size[a] = sh->size[a];
   }
-  g.phase = sh->phase;
+  g.phase = sh->phase - std::floor(sh->phase);   // the same teeth; keeps the tooth index small
+  g.zu = (double)sh->teeth / (2.0 * M_PI);
   LaunchTab T;
   tab_for(P, std::vector<int>{0}, T);
   for (int it = 0; it < iterations; ++it) {

@@ -21,6 +21,8 @@ enum Flag { F_DOMAIN = 1, F_NONFINITE = 2, F_CAPACITY = 4 };
 // Blocks of one launch: the slots it covers and, per domain, the prefix of
 // their block counts.  Passed by value (kernel argument segment).
 constexpr int32_t TAB_DISS = 1;   // some slot of the launch has viscous heating on
+constexpr int32_t TAB_MAT = 2;    // some slot of the launch has several fluid materials
+constexpr int NMAT = SPH_MAX_MATERIALS;
 
 struct LaunchTab {
   int32_t n, flags;
@@ -65,6 +67,8 @@ struct SlotDesc {
   double g[3], lo[3];
   double kW, kF;                       // W = kW (1-q/2)^4 (1+2q);  F = kF (1-q/2)^3
   double bc[NB][3], ba[NB][3], bom[NB], bT[NB], bk[NB], btip[NB];
+  double mk[NMAT], mcp[NMAT];          // conductivity and specific heat per fluid material
+  int32_t nmat, pad1;                  // materials (1: every particle takes k_f, cp_f)
   SlotCtl* ctl;
   // fluid state (sorted order) and its gather buffers
   void *xa, *drift, *vr, *vrn, *drho, *T, *ah;
@@ -74,6 +78,7 @@ struct SlotDesc {
   uint64_t *fkey;       // scatter output: (original id << 32) | staged index, per sorted slot
   void *xa2, *vr2, *drho2, *T2;
   uint32_t *fid2;
+  uint32_t *mat, *mat2;  // material of each sorted particle and its staging copy (nmat > 1 only)
   // neighbour rows (SELL, slice height 64) of sorted neighbour indices, and
   // the cell-relative positions the sweeps take r_ij from
   uint32_t *nfc, *nsc;
@@ -105,6 +110,7 @@ struct SlotDesc {
 struct RelaxShape {
   int32_t kind, teeth, inside, pad;
   double center[3], size[3], phase;
+  double zu;            // gear: teeth / (2 pi)
 };
 
 // Launch one kernel of the particle relaxation (SPH_K_RELAX_*); iter: the

@@ -243,6 +243,7 @@ __global__ __launch_bounds__(BLOCK) void k_fold(const SlotDesc* table, LaunchTab
     const Temp T = gpc<Temp>(S.T)[i];
     gp<Temp>(S.T2)[i] = T;
     S.fid2[i] = S.fid[i];
+    if (S.mat) S.mat2[i] = S.mat[i];
     const bool finite = isfinite((double)x.x) && isfinite((double)x.y) && isfinite((double)x.z) &&
                         isfinite((double)v.x) && isfinite((double)v.y) && isfinite((double)v.z) &&
                         isfinite((double)v.w) && isfinite((double)T);
@@ -449,6 +450,7 @@ __global__ __launch_bounds__(BLOCK) void k_reorder(const SlotDesc* table, Launch
     gp<Real>(S.drho)[k] = gpc<Real>(S.drho2)[s];
     gp<Temp>(S.T)[k] = gpc<Temp>(S.T2)[s];
     S.fid[k] = S.fid2[s];
+    if (S.mat) S.mat[k] = S.mat2[s];
   } else {
     if (k >= S.ns) return;
     const uint32_t s = S.sperm[k];
@@ -898,15 +900,27 @@ __device__ __forceinline__ void grad_add(Real* G, Real c, Real dx, Real dy, Real
 // the velocity gradient G[a][b] = sum V_j (v_j - v_i)_a F_ij r_ij[b] over fluid
 // and wall neighbours gives Phi = 2 eta S:S, S = (G + G^T)/2, added to the
 // heat rate as Phi/(rho cp); per-block partial of sum V_i Phi_i.
+// MAT: the launch holds a slot with several fluid materials: k and cp per
+// particle (material index gathered per neighbour), K_ij = 4 k_i k_j /
+// (k_i + k_j) from a per-block table.
 // ---------------------------------------------------------------------------
-template <class P, bool DISS>
+template <class P, bool DISS, bool MAT>
 __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, LaunchTab tab) {
   typedef typename P::Real Real;
   typedef typename P::Temp Temp;
   typedef typename P::Real4 Real4;
   __shared__ double lds[4 * NB * 7];
   __shared__ double lds_d[BLOCK / WAVE];
+  __shared__ Real Ktab[MAT ? NMAT * NMAT : 1];
   SLOT_PROLOGUE(DOM_FLUID);
+  const bool mats = MAT && S.mat != nullptr;
+  if (mats) {
+    for (int q = threadIdx.x; q < NMAT * NMAT; q += BLOCK) {
+      const double ka = S.mk[q / NMAT], kb = S.mk[q % NMAT];
+      Ktab[q] = (Real)(4.0 * ka * kb / (ka + kb));
+    }
+    __syncthreads();
+  }
   const int nf = S.nf;
   const int i = lb * BLOCK + threadIdx.x;
   const size_t nbf = (size_t)S.nblk[DOM_FLUID];
@@ -928,6 +942,8 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
     const Temp Ti = T[i];
     const Real c2 = (Real)(2.0 * S.eta) * rcp(rhoi);   // 2 eta V_i / m_i
     const Real Kff = (Real)(4.0 * S.k_f * S.k_f / (S.k_f + S.k_f));
+    const uint32_t mi = mats ? S.mat[i] : 0u;
+    const double kI = mats ? S.mk[mi] : S.k_f, cpI = mats ? S.mcp[mi] : S.cp_f;
     Real ax = 0, ay = 0, az = 0, hs = 0;
     Real G[9];
 #pragma unroll
@@ -966,7 +982,8 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
           ax += cv * (vi.x - vj[u].x);
           ay += cv * (vi.y - vj[u].y);
           az += cv * (vi.z - vj[u].z);
-          hs += Vj * Kff * (Real)(Ti - Tj[u]) * Fk;
+          const Real Kij = mats ? Ktab[mi * NMAT + S.mat[j[u]]] : Kff;
+          hs += Vj * Kij * (Real)(Ti - Tj[u]) * Fk;
           if (DISS) grad_add(G, Vj * Fk, vj[u].x - vi.x, vj[u].y - vi.y, vj[u].z - vi.z, rx, ry, rz);
         }
       }
@@ -979,7 +996,7 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
       const GLB Real4* vw = gpc<Real4>(S.vw);
       const GLB Real4* lv = gpc<Real4>(S.lev);
       const Real Vw = (Real)S.vol_w;
-      const Real rc = rcp(rhoi * (Real)S.cp_f);
+      const Real rc = rcp(rhoi * (Real)cpI);
       uint32_t wn[SOLID_UNROLL];
 #pragma unroll
       for (int u = 0; u < SOLID_UNROLL; ++u) wn[u] = ldnt(R + (int64_t)u * WAVE);
@@ -1009,7 +1026,7 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
         ax += fx;
         ay += fy;
         az += fz;
-        const Real Kiw = (Real)(4.0 * S.k_f * S.bk[b] / (S.k_f + S.bk[b]));
+        const Real Kiw = (Real)(4.0 * kI * S.bk[b] / (kI + S.bk[b]));
         const Real term = Vw * Kiw * (Real)(Ti - (Temp)S.bT[b]) * Fk;
         hs += term;
         if (DISS) grad_add(G, Vw * Fk, vq.x - vi.x, vq.y - vi.y, vq.z - vi.z, rx, ry, rz);
@@ -1017,7 +1034,7 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
         const double gx = -(double)m * fx, gy = -(double)m * fy, gz = -(double)m * fz;
         const double lx = lq.x, ly = lq.y, lz = lq.z;
         const double contrib[7] = {gx, gy, gz, ly * gz - lz * gy, lz * gx - lx * gz, lx * gy - ly * gx,
-                                   (double)m * (double)S.cp_f * (double)(rc * term)};
+                                   (double)m * cpI * (double)(rc * term)};
         if (!acc.add(b, contrib)) raise_flag(S, F_CAPACITY);
         }
       }
@@ -1362,7 +1379,7 @@ __global__ __launch_bounds__(BLOCK) void k_end(const SlotDesc* table, LaunchTab 
     const double r = P::kRel ? S.rho0 + (double)v.w : (double)v.w;
     q[0] = S.mass;
     q[1] = 0.5 * S.mass * v2;
-    q[2] = S.mass * S.cp_f * (double)Tn;
+    q[2] = S.mass * (S.mat ? S.mcp[S.mat[i]] : S.cp_f) * (double)Tn;
     q[3] = r * (S.dp * S.dp * S.dp);
     q[4] = sqrt(v2);
     if (!isfinite(v2) || !isfinite(r) || !isfinite((double)Tn)) raise_flag(S, F_NONFINITE);
@@ -1545,8 +1562,13 @@ static hipError_t launch_p(int kid, int which, int sub, const SlotDesc* T, const
     case SPH_K_CONTACT: hipLaunchKernelGGL(k_contact<P>, g, b, 0, st, T, L); break;
     case SPH_K_DT: hipLaunchKernelGGL(k_dt, g, b, 0, st, T, L); break;
     case SPH_K_VISC_HEAT:
-      if (L.flags & TAB_DISS) hipLaunchKernelGGL((k_visc_heat<P, true>), g, b, 0, st, T, L);
-      else hipLaunchKernelGGL((k_visc_heat<P, false>), g, b, 0, st, T, L);
+      if (L.flags & TAB_MAT) {
+        if (L.flags & TAB_DISS) hipLaunchKernelGGL((k_visc_heat<P, true, true>), g, b, 0, st, T, L);
+        else hipLaunchKernelGGL((k_visc_heat<P, false, true>), g, b, 0, st, T, L);
+      } else {
+        if (L.flags & TAB_DISS) hipLaunchKernelGGL((k_visc_heat<P, true, false>), g, b, 0, st, T, L);
+        else hipLaunchKernelGGL((k_visc_heat<P, false, false>), g, b, 0, st, T, L);
+      }
       break;
     case SPH_K_HALF_A: hipLaunchKernelGGL(k_half_a<P>, g, b, 0, st, T, L, sub); break;
     case SPH_K_MOMENTUM: hipLaunchKernelGGL(k_momentum<P>, g, b, 0, st, T, L, sub); break;

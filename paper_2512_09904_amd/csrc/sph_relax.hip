@@ -3,9 +3,55 @@
 // relaxation force over the neighbour rows of the solver's own cell sort and
 // build, and the move with level-set confinement.  Launched by sph_relax; one
 // iteration is sort/build -> relax_force -> relax_max -> relax_move.
+#include <algorithm>
+#include <vector>
+
 #include "sph_device.h"
 
 namespace sphk {
+
+// Cells of the exterior-integral quadrature: the cube [-2h, 2h]^3 cut into
+// 16^3 cells of edge h/4, cell (a, b, c) centred at (a + 1/2, b + 1/2, c + 1/2)
+// h/4 from the particle, a, b, c in [-8, 8).  Only cells with key
+// (2a+1)^2 + (2b+1)^2 + (2c+1)^2 = (distance / (h/8))^2 below 264 can lie
+// within 2h (256) plus a rounding margin; they are listed by ascending key
+// (ties by linear index), so the cells nearer than a distance form a prefix.
+// Entry: key << 12 | (a+8) << 8 | (b+8) << 4 | (c+8).
+constexpr int QK = 8, QN = 2 * QK, QKEY_MAX = 264, QMAX = 2400;
+__constant__ uint32_t qcells[QMAX];
+
+static int qcells_count = 0;
+static bool qcells_loaded[64] = {};
+
+// the table, built on the host and copied to the current device once
+static hipError_t qcells_init(int* count) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  if (!qcells_loaded[dev]) {
+    std::vector<uint64_t> v;
+    for (int a = -QK; a < QK; ++a)
+      for (int b = -QK; b < QK; ++b)
+        for (int c = -QK; c < QK; ++c) {
+          const uint32_t key = (uint32_t)((2 * a + 1) * (2 * a + 1) + (2 * b + 1) * (2 * b + 1) + (2 * c + 1) * (2 * c + 1));
+          if (key >= (uint32_t)QKEY_MAX) continue;
+          const uint32_t lin = (uint32_t)(((a + QK) * QN + (b + QK)) * QN + (c + QK));
+          const uint32_t ent = key << 12 | (uint32_t)(a + QK) << 8 | (uint32_t)(b + QK) << 4 | (uint32_t)(c + QK);
+          v.push_back((uint64_t)key << 44 | (uint64_t)lin << 32 | ent);
+        }
+    std::sort(v.begin(), v.end());
+    if ((int)v.size() > QMAX) return hipErrorInvalidValue;
+    std::vector<uint32_t> t(v.size());
+    for (size_t k = 0; k < v.size(); ++k) t[k] = (uint32_t)v[k];
+    e = hipMemcpyToSymbol(HIP_SYMBOL(qcells), t.data(), t.size() * sizeof(uint32_t));
+    if (e != hipSuccess) return e;
+    qcells_count = (int)t.size();
+    qcells_loaded[dev] = true;
+  }
+  *count = qcells_count;
+  return hipSuccess;
+}
 
 // Every level-set evaluation is FP64.
 
@@ -31,11 +77,12 @@ __device__ void ls_flank_table(const RelaxShape& g, d2v* E) {
   }
 }
 
-// distance from (px, pz) to the radial segment along e from r_root to r_tip
-__device__ __forceinline__ double ls_flank(const RelaxShape& g, double px, double pz, d2v e) {
+// squared distance from (px, pz) to the radial segment along e from r_root
+// to r_tip
+__device__ __forceinline__ double ls_flank2(const RelaxShape& g, double px, double pz, d2v e) {
   const double t = fmin(fmax(px * e.x + pz * e.y, g.size[1]), g.size[0]);
   const double ex = px - t * e.x, ez = pz - t * e.y;
-  return sqrt(ex * ex + ez * ez);
+  return ex * ex + ez * ez;
 }
 
 // Gear cross-section: root disk plus teeth where frac(u) < 1/2, u = z theta /
@@ -43,27 +90,34 @@ __device__ __forceinline__ double ls_flank(const RelaxShape& g, double px, doubl
 // radial flanks at half-integer u; the nearest piece belongs to the point's
 // half-pitch k = floor(2u) or one of its two neighbours: flanks k-1 .. k+2,
 // the own arc (radial distance) and the neighbours' arcs (their end points).
+// The point distances are compared squared and rooted once: sqrt is
+// correctly rounded and monotonic, so this is the minimum of their roots.
 __device__ double ls_gear2d(const RelaxShape& g, const d2v* E, double px, double pz) {
   const double r = sqrt(px * px + pz * pz);
-  const double u = (double)g.teeth * atan2(pz, px) / (2.0 * M_PI) + 0.25 + g.phase;
+  const double u = g.zu * atan2(pz, px) + 0.25 + g.phase;   // zu = teeth / 2 pi
   const int k = (int)floor(2.0 * u);
   const int n2 = 2 * g.teeth;
+  // phase in [0, 1) keeps k in [-teeth - 1, teeth + 2]: one wrap each way
+  int j0 = k - 1;
+  j0 += j0 < 0 ? n2 : 0;
   d2v e[4];
 #pragma unroll
-  for (int m = 0; m < 4; ++m) e[m] = E[(((k - 1 + m) % n2) + n2) % n2];
-  double best = INFINITY;
+  for (int m = 0; m < 4; ++m) {
+    const int j = j0 + m;
+    e[m] = E[min(max(j >= n2 ? j - n2 : j, 0), n2 - 1)];   // the clamp only guards a non-finite point
+  }
+  double b2 = INFINITY;
 #pragma unroll
-  for (int m = 0; m < 4; ++m) best = fmin(best, ls_flank(g, px, pz, e[m]));
+  for (int m = 0; m < 4; ++m) b2 = fmin(b2, ls_flank2(g, px, pz, e[m]));
   // tip arc over a tooth (even half-pitch), root arc over a gap
   const bool even = (k & 1) == 0;
-  best = fmin(best, fabs(r - (even ? g.size[0] : g.size[1])));
   const double Rn = even ? g.size[1] : g.size[0];   // the neighbours' arcs
 #pragma unroll
-  for (int m = 0; m < 4; m += 3) {                     // end points k-1, k (left) and k+1, k+2 (right)
-    const d2v a = m == 0 ? e[0] : e[2], b = m == 0 ? e[1] : e[3];
-    const double ax = px - Rn * a.x, az = pz - Rn * a.y, bx = px - Rn * b.x, bz = pz - Rn * b.y;
-    best = fmin(best, fmin(sqrt(ax * ax + az * az), sqrt(bx * bx + bz * bz)));
+  for (int m = 0; m < 4; ++m) {                     // their end points: flanks k-1 .. k+2
+    const double ax = px - Rn * e[m].x, az = pz - Rn * e[m].y;
+    b2 = fmin(b2, ax * ax + az * az);
   }
+  const double best = fmin(sqrt(b2), fabs(r - (even ? g.size[0] : g.size[1])));
   const bool in = r <= g.size[1] || (r <= g.size[0] && u - floor(u) < 0.5);
   return in ? -best : best;
 }
@@ -94,7 +148,7 @@ __device__ double ls_phi(const RelaxShape& g, const d2v* E, double x, double y, 
 // clamp(1/2 + phi/edge, 0, 1)), spread over the 64 lanes of the wavefront for
 // each particle that needs it.  Per-block maximum of |F_p|.
 template <class P>
-__global__ __launch_bounds__(BLOCK) void k_relax_force(const SlotDesc* table, LaunchTab tab, RelaxShape g) {
+__global__ __launch_bounds__(BLOCK) void k_relax_force(const SlotDesc* table, LaunchTab tab, RelaxShape g, int nq) {
   typedef typename P::Real Real;
   typedef typename P::Pos4 Pos4;
   typedef typename P::Real4 Real4;
@@ -138,28 +192,42 @@ __global__ __launch_bounds__(BLOCK) void k_relax_force(const SlotDesc* table, La
     need = phx > -2.0 * h - del;
   }
   // exterior integral, one particle at a time across the wavefront
-  constexpr int QK = 8, QN = 2 * QK;
   double Ix = 0.0, Iy = 0.0, Iz = 0.0;
   uint64_t todo = __ballot(need);
-  const double dv = del * del * del, cut = 2.0 * h, inv_h = 1.0 / h;
+  const double dv = del * del * del, cut = 2.0 * h, inv_h = 1.0 / h, inv_del = 1.0 / del;
   while (todo) {
     const int src = __builtin_ctzll(todo);
     todo &= todo - 1;
     const double qx = __shfl(px, src, WAVE), qy = __shfl(py, src, WAVE), qz = __shfl(pz, src, WAVE);
     const double qphi = __shfl(phx, src, WAVE);
+    // phi is a distance (1-Lipschitz): phi(y) <= phi(x) + |x - y|, so a cell
+    // with phi(x) + |x - y| <= -edge/2 lies wholly inside.  Skip the prefix of
+    // cells surely that near (key below (2 lim / edge)^2, less a margin); the
+    // test below catches the rest.
+    int s0 = 0;
+    const double lim = -0.5 * del - qphi;
+    if (lim > 0.0) {
+      const double kl = 4.0 * (lim / del) * (lim / del) * (1.0 - 1e-9);
+      int lo = 0, hi = nq;                       // first entry with key >= kl
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((double)(qcells[mid] >> 12) < kl) lo = mid + 1;
+        else hi = mid;
+      }
+      s0 = lo;
+    }
     double ax = 0.0, ay = 0.0, az = 0.0;
-    for (int q = lane; q < QN * QN * QN; q += WAVE) {
-      const int a = q / (QN * QN) - QK, b = (q / QN) % QN - QK, c = q % QN - QK;
+    for (int q = s0 + lane; q < nq; q += WAVE) {
+      const uint32_t ent = qcells[q];
+      const int a = (int)((ent >> 8) & 15u) - QK, b = (int)((ent >> 4) & 15u) - QK, c = (int)(ent & 15u) - QK;
       const double yx = qx + del * ((double)a + 0.5), yy = qy + del * ((double)b + 0.5),
                    yz = qz + del * ((double)c + 0.5);
       const double ex = qx - yx, ey = qy - yy, ez = qz - yz;
       const double r2 = (ex * ex + ey * ey) + ez * ez;
       if (!(r2 < cut * cut)) continue;
-      // phi is a distance (1-Lipschitz): phi(y) <= phi(x) + |x - y|, so a
-      // cell with phi(x) + |x - y| <= -edge/2 lies wholly inside
       const double rr = sqrt(r2);
       if (qphi + rr <= -0.5 * del) continue;
-      const double f = fmin(0.5 + ls_phi(g, E, yx, yy, yz) / del, 1.0);
+      const double f = fmin(0.5 + ls_phi(g, E, yx, yy, yz) * inv_del, 1.0);
       if (!(f > 0.0)) continue;
       const double t = 1.0 - 0.5 * rr * inv_h;
       const double F = S.kF * t * t * t;
@@ -277,17 +345,22 @@ hipError_t launch_relax(int prec, int kid, int iter, const SlotDesc* T, const La
   }
   if (kid != SPH_K_RELAX_FORCE && kid != SPH_K_RELAX_MOVE) return hipErrorInvalidValue;
   const bool force = kid == SPH_K_RELAX_FORCE;
+  int nq = 0;
+  if (force) {
+    const hipError_t e = qcells_init(&nq);
+    if (e != hipSuccess) return e;
+  }
   switch (prec) {
     case SPH_PREC_MIXED:
-      if (force) hipLaunchKernelGGL(k_relax_force<PMixed>, gr, b, 0, st, T, L, g);
+      if (force) hipLaunchKernelGGL(k_relax_force<PMixed>, gr, b, 0, st, T, L, g, nq);
       else hipLaunchKernelGGL(k_relax_move<PMixed>, gr, b, 0, st, T, L, g);
       break;
     case SPH_PREC_FP64:
-      if (force) hipLaunchKernelGGL(k_relax_force<PF64>, gr, b, 0, st, T, L, g);
+      if (force) hipLaunchKernelGGL(k_relax_force<PF64>, gr, b, 0, st, T, L, g, nq);
       else hipLaunchKernelGGL(k_relax_move<PF64>, gr, b, 0, st, T, L, g);
       break;
     case SPH_PREC_FP32:
-      if (force) hipLaunchKernelGGL(k_relax_force<PF32>, gr, b, 0, st, T, L, g);
+      if (force) hipLaunchKernelGGL(k_relax_force<PF32>, gr, b, 0, st, T, L, g, nq);
       else hipLaunchKernelGGL(k_relax_move<PF32>, gr, b, 0, st, T, L, g);
       break;
     default: return hipErrorInvalidValue;

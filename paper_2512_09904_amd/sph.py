@@ -42,7 +42,8 @@ class Params(C.Structure):
                 ("cfl_ac", C.c_double), ("fixed_dt_ad", C.c_double), ("fixed_nac", C.c_int32),
                 ("nac_max", C.c_int32), ("free_surface", C.c_int32), ("precision", C.c_int32),
                 ("max_fluid_nbrs", C.c_int32), ("max_solid_nbrs", C.c_int32), ("viscous_heating", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("reserved", C.c_int32), ("n_materials", C.c_int32), ("reserved2", C.c_int32),
+                ("mat_k", C.c_double * 8), ("mat_cp", C.c_double * 8)]
 
 
 class Body(C.Structure):
@@ -183,7 +184,17 @@ def params_struct(params: dict, precision="mixed", fixed_dt_ad=None, fixed_nac=N
     P.max_fluid_nbrs = int(d.get("max_fluid_nbrs", 0))
     P.max_solid_nbrs = int(d.get("max_solid_nbrs", 0))
     P.viscous_heating = int(d.get("viscous_heating", 0))
+    mats = d.get("materials") or []
+    P.n_materials = len(mats)
+    for m, (k, cp) in enumerate(mats):
+        P.mat_k[m] = float(k)
+        P.mat_cp[m] = float(cp)
     return P
+
+
+def _material(case):
+    m = getattr(case, "material", None)
+    return None if m is None else np.ascontiguousarray(m, dtype=np.int32)
 
 
 def bodies_array(bodies):
@@ -235,7 +246,9 @@ class Solver:
         B = bodies_array(case.bodies)
         check(L.sph_set_bodies(h, C.c_int32(self.nbody), B), "sph_set_bodies")
         x, v, r, T = _f64(case.xf, (-1, 3)), _f64(case.vf, (-1, 3)), _f64(case.rhof), _f64(case.Tf)
-        check(L.sph_set_fluid(h, C.c_int64(self.nf), _p(x), _p(v), _p(r), _p(T)), "sph_set_fluid")
+        mat = _material(case)
+        check(L.sph_set_fluid(h, C.c_int64(self.nf), _p(x), _p(v), _p(r), _p(T), _p(mat) if mat is not None else None),
+              "sph_set_fluid")
         x0, n0 = _f64(case.xs0, (-1, 3)), _f64(case.ns0, (-1, 3))
         body = np.ascontiguousarray(case.body, dtype=np.int32)
         check(L.sph_set_solid(h, C.c_int64(self.ns), _p(x0), _p(n0), _p(body)), "sph_set_solid")
@@ -370,9 +383,10 @@ class Pool:
         x0, n0 = _f64(case.xs0, (-1, 3)), _f64(case.ns0, (-1, 3))
         body = np.ascontiguousarray(case.body, dtype=np.int32)
         slot = C.c_int32(-1)
+        mat = _material(case)
         rc = lib().sph_pool_admit(self.h, C.byref(P), C.c_int32(len(case.bodies)), B, C.c_int64(case.nf), _p(x),
-                                  _p(v), _p(r), _p(T), C.c_int64(case.ns), _p(x0), _p(n0), _p(body),
-                                  C.c_int64(int(target_steps)), C.byref(slot))
+                                  _p(v), _p(r), _p(T), _p(mat) if mat is not None else None, C.c_int64(case.ns),
+                                  _p(x0), _p(n0), _p(body), C.c_int64(int(target_steps)), C.byref(slot))
         if rc == SPH_ERR_BUDGET:
             return None
         check(rc, "sph_pool_admit")

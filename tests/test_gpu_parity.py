@@ -526,3 +526,84 @@ def test_viscous_heating_rejects_bad_flag(sph):
     c = cases.tank_c1()
     with pytest.raises(sph.SphError):
         sph.Solver(c, viscous_heating=2)
+
+
+# ---------------------------------------------------------------------------
+# several fluid materials (eq. 22 with k_i, k_j and cp_i per particle)
+# ---------------------------------------------------------------------------
+
+MATS = [(0.13, 2000.0), (0.45, 1300.0)]
+
+
+def _two_material_tank(seed=3):
+    """The ragged tank split at x = 20 mm into two materials, the left one
+    5 K warmer, so conduction runs across the material boundary."""
+    c = ragged_tank(seed=seed)
+    left = c.xf[:, 0] < 0.02
+    c.Tf = np.where(left, c.Tf + 5.0, c.Tf)
+    c.material = np.where(left, 0, 1).astype(np.int32)
+    c.params["materials"] = list(MATS)
+    k = np.array([m[0] for m in MATS])[c.material]
+    cp = np.array([m[1] for m in MATS])[c.material]
+    return c, k, cp
+
+
+@pytest.mark.parametrize("precision,bar,tau", [("mixed", 1e-5, 1e-5), ("fp64", 1e-10, 1e-11)])
+def test_two_materials_parity(sph, ora, precision, bar, tau):
+    c, k, cp = _two_material_tank()
+    say("two materials", precision, c.nf)
+    dt, nac = fixed_dt(c)
+    o = ora.State(c, k=k, cp=cp, fixed_dt_ad=dt, fixed_nac=nac)
+    ro = o.step(want_rates=True)
+    s = sph.Solver(c, precision=precision, fixed_dt_ad=dt, fixed_nac=nac)
+    s.step(1)
+    rg = s.reduce()
+    g = s.get_fluid()
+    fid = s.dump("fluid_ids").astype(np.int64)
+    st = s.dump("fluid_state").reshape(c.nf, 16)[np.argsort(fid)]
+    s.close()
+    e = _normalised_errors(c, o, g)
+    say("normalised errors", precision, e)
+    assert max(e.values()) <= bar, e
+    R = ro["rates"]
+    dT = np.abs(st[:, 15] - R["dTdt"])
+    assert np.all(dT <= tau * R["S_T"] + 1e-300), np.max(dT / (R["S_T"] + 1e-300))
+    # conduction across the boundary is a visible part of the rates here
+    iface = np.abs(c.xf[:, 0] - 0.02) < 2e-3
+    assert np.median(np.abs(R["dTdt"][iface])) > 1e3 * tau * np.median(R["S_T"][iface])
+    assert rg["thermal"] == pytest.approx(ro["thermal"], rel=1e-12 if precision == "fp64" else 1e-9)
+    assert rg["heat_step"] == pytest.approx(ro["heat_step"], rel=1e-10 if precision == "fp64" else 1e-5)
+
+
+def test_identical_materials_equal_one_material(sph):
+    """Two materials with the fluid's own k and cp, or a one-entry table,
+    give the one-material solve bit for bit."""
+    base = cases.tank_c1(seed=9)
+    k, cp = base.params["k_f"], base.params["cp_f"]
+    a = sph.Solver(base)
+    a.step(3)
+    ga, ra = a.get_fluid(), a.reduce()
+    a.close()
+    for mats in ([(k, cp), (k, cp)], [(k, cp)]):
+        c = cases.tank_c1(seed=9)
+        c.params["materials"] = mats
+        c.material = (np.arange(c.nf) % len(mats)).astype(np.int32)
+        b = sph.Solver(c)
+        b.step(3)
+        gb, rb = b.get_fluid(), b.reduce()
+        b.close()
+        for key in ("x", "v", "rho", "T"):
+            assert np.array_equal(ga[key], gb[key]), (len(mats), key)
+        assert ra["thermal"] == rb["thermal"] and ra["heat_total"] == rb["heat_total"]
+
+
+def test_material_arguments_checked(sph):
+    c = cases.tank_c1()
+    c.params["materials"] = list(MATS)
+    c.material = np.full(c.nf, 2, np.int32)           # only 0 and 1 exist
+    with pytest.raises(sph.SphError):
+        sph.Solver(c)
+    c.material = None
+    c.params["materials"] = [(0.13, -1.0)]
+    with pytest.raises(sph.SphError):
+        sph.Solver(c)

@@ -110,6 +110,27 @@ def test_alone_equals_in_mix_with_viscous_heating(sph):
         assert ra["diss_total"] == rm["diss_total"]
         assert (rm["diss_total"] > 0.0) == (q == 1)
 
+
+def test_alone_equals_in_mix_with_materials(sph):
+    """The middle request carries two fluid materials, so the batched viscous
+    launch takes its material variant for every slot; each request still
+    matches its solo run bitwise."""
+    reqs = _requests()
+    r = reqs[1]
+    r.params = dict(r.params, materials=[(0.13, 2000.0), (0.4, 1500.0)])
+    r.material = (r.xf[:, 0] > r.xf[:, 0].mean()).astype(np.int32)
+    steps = [5, 4, 6]
+    say("serving: alone vs mix, one slot with two materials")
+    alone = {q: _run_pool(sph, [reqs[q]], [steps[q]], [0])[0] for q in range(3)}
+    mix = _run_pool(sph, reqs, steps, [0, 1, 2])
+    for q in range(3):
+        ga, ra = alone[q]
+        gm, rm = mix[q]
+        assert ra["rc"] == 0 and rm["rc"] == 0
+        for key in ("x", "v", "rho", "T"):
+            assert np.array_equal(ga[key], gm[key]), (q, key)
+        assert ra["thermal"] == rm["thermal"]
+
 def test_solver_equals_pool_slot(sph):
     c = _requests()[0]
     say("serving: solver vs pool")
@@ -163,4 +184,24 @@ def test_faulted_slot_does_not_disturb_others(sph):
     g = pool.get_fluid(a)
     for key in ("x", "v", "rho", "T"):
         assert np.array_equal(g[key], ref[0][key])
+    pool.close()
+
+
+def test_poll_right_after_admit_sees_a_clean_slot(sph):
+    """A poll issued before the admitted slot's upload has run on the pool's
+    stream must wait for it, not read what the reused memory held before
+    (here a freed block of -1 words under a busy stream)."""
+    import torch
+    pool = sph.Pool(1 << 40, max_slots=2)
+    with torch.cuda.stream(pool.stream):
+        junk = torch.full((64 << 20,), -1, dtype=torch.int32, device="cuda")
+        del junk
+        torch.cuda._sleep(20_000_000)               # keep the pool's stream busy for a while
+    c = cases.serving_tank(4000, 200.0, 0.025, 0.7e-4, seed=3)
+    s = pool.admit(c, 2)
+    done, rep = pool.poll(s)
+    assert not done, rep
+    pool.step(2)
+    rep = _wait(pool, s)
+    assert rep["rc"] == 0 and rep["step"] == 2
     pool.close()
