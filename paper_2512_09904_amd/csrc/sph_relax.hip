@@ -92,19 +92,34 @@ __device__ __forceinline__ double ls_flank2(const RelaxShape& g, double px, doub
 // the own arc (radial distance) and the neighbours' arcs (their end points).
 // The point distances are compared squared and rooted once: sqrt is
 // correctly rounded and monotonic, so this is the minimum of their roots.
-__device__ double ls_gear2d(const RelaxShape& g, const d2v* E, double px, double pz) {
-  const double r = sqrt(px * px + pz * pz);
-  const double u = g.zu * atan2(pz, px) + 0.25 + g.phase;   // zu = teeth / 2 pi
-  const int k = (int)floor(2.0 * u);
-  const int n2 = 2 * g.teeth;
-  // phase in [0, 1) keeps k in [-teeth - 1, teeth + 2]: one wrap each way
+__device__ __forceinline__ void ls_sector(const d2v* E, int n2, int k, d2v e[4]) {
+  // phase in [0, 1) keeps k in [-teeth - 1, teeth + 3]: one wrap each way
   int j0 = k - 1;
   j0 += j0 < 0 ? n2 : 0;
-  d2v e[4];
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     const int j = j0 + m;
     e[m] = E[min(max(j >= n2 ? j - n2 : j, 0), n2 - 1)];   // the clamp only guards a non-finite point
+  }
+}
+
+__device__ double ls_gear2d(const RelaxShape& g, const d2v* E, double px, double pz) {
+  const double r = sqrt(px * px + pz * pz);
+  const int n2 = 2 * g.teeth;
+  // half-pitch k = floor(2u), u = zu theta + 1/4 + phase (zu = teeth / 2 pi):
+  // estimated from an FP32 angle, then settled by the sides of its flanks
+  // (the point lies in half-pitch k when it is on or left of flank k and
+  // right of flank k + 1)
+  const double ue = g.zu * (double)atan2f((float)pz, (float)px) + 0.25 + g.phase;
+  int k = (int)floor(2.0 * ue);
+  d2v e[4];
+  ls_sector(E, n2, k, e);
+  if (e[1].x * pz - e[1].y * px < 0.0) {
+    k -= 1;
+    ls_sector(E, n2, k, e);
+  } else if (e[2].x * pz - e[2].y * px >= 0.0) {
+    k += 1;
+    ls_sector(E, n2, k, e);
   }
   double b2 = INFINITY;
 #pragma unroll
@@ -118,7 +133,7 @@ __device__ double ls_gear2d(const RelaxShape& g, const d2v* E, double px, double
     b2 = fmin(b2, ax * ax + az * az);
   }
   const double best = fmin(sqrt(b2), fabs(r - (even ? g.size[0] : g.size[1])));
-  const bool in = r <= g.size[1] || (r <= g.size[0] && u - floor(u) < 0.5);
+  const bool in = r <= g.size[1] || (r <= g.size[0] && even);
   return in ? -best : best;
 }
 
