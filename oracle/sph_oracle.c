@@ -791,6 +791,16 @@ void ora_timestep(const ora_params* P, int32_t nbody, const ora_body* B, int64_t
                   const double* x0, const int32_t* body, int64_t nf, const double* v,
                   double* dt_ad, double* dt, int32_t* n_ac, double* vmax) {
   double h = ora_h(P);
+  ora_timestep_T(P, nbody, B, ns, x0, body, nf, v, 0.5 * P->rho0 * P->cp_f * h * h / P->k_f, dt_ad, dt,
+                 n_ac, vmax);
+}
+
+/* eq. 25 with the thermal bound of eq. 26, dt_T = 0.5 rho C_p h^2 / k (rho
+   read as rho0), applied as dt_ad <= dt_T before the sub-steps are counted */
+void ora_timestep_T(const ora_params* P, int32_t nbody, const ora_body* B, int64_t ns,
+                    const double* x0, const int32_t* body, int64_t nf, const double* v, double dt_T,
+                    double* dt_ad, double* dt, int32_t* n_ac, double* vmax) {
+  double h = ora_h(P);
   double vm = 0.0;
   for (int64_t i = 0; i < nf; ++i) {
     double s = sqrt(dot3(v + 3 * i, v + 3 * i));
@@ -818,6 +828,7 @@ void ora_timestep(const ora_params* P, int32_t nbody, const ora_body* B, int64_t
   double visc = h * h / P->nu;
   double adv = vm > 0.0 ? h / vm : visc;
   double tad = P->cfl_ad * (adv < visc ? adv : visc);
+  if (dt_T < tad) tad = dt_T;
   double tac = P->cfl_ac * h / (P->c0 + vm);
   double n = ceil(tad / tac);
   if (n < 1.0) n = 1.0;
@@ -911,7 +922,13 @@ int ora_step_kc(const ora_params* P, int32_t nbody, const ora_body* B, int64_t n
   /* 5. time step (Section 2.8) */
   double dt_ad, dt, vmax0;
   int32_t n_ac;
-  ora_timestep(P, nbody, B, ns, x0, body, nf, v, &dt_ad, &dt, &n_ac, &vmax0);
+  double dtT = INFINITY;
+  for (int64_t i = 0; i < nf; ++i) {
+    double hh = ora_h(P);
+    double d = 0.5 * P->rho0 * cpf[i] * hh * hh / kf[i];
+    if (d < dtT) dtT = d;
+  }
+  ora_timestep_T(P, nbody, B, ns, x0, body, nf, v, dtT, &dt_ad, &dt, &n_ac, &vmax0);
   /* 6. viscous and heat rates, frozen for the step */
   ora_viscous(P, nb, nbody, B, body, v, rho, mass, vs, av, rates ? rates->S_visc : NULL, bFv, bTv);
   ora_heat(P, nb, nbody, B, body, rho, mass, kf, cpf, T, dTdt, rates ? rates->S_T : NULL, bq);

@@ -127,6 +127,10 @@ void ora_body_pose(int32_t nbody, const ora_body* B, int64_t ns, const double* x
 void ora_timestep(const ora_params* P, int32_t nbody, const ora_body* B, int64_t ns,
                   const double* x0, const int32_t* body, int64_t nf, const double* v,
                   double* dt_ad, double* dt, int32_t* n_ac, double* vmax);
+/* the same with the thermal bound dt_T of eq. 26 given (dt_ad <= dt_T) */
+void ora_timestep_T(const ora_params* P, int32_t nbody, const ora_body* B, int64_t ns,
+                    const double* x0, const int32_t* body, int64_t nf, const double* v, double dt_T,
+                    double* dt_ad, double* dt, int32_t* n_ac, double* vmax);
 int ora_step(const ora_params* P, int32_t nbody, const ora_body* B, int64_t nf, double* x,
              double* v, double* rho, double* T, double* drho, int64_t ns, const double* x0,
              const double* n0, const int32_t* body, double* t, ora_report* rep,

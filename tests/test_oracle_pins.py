@@ -405,6 +405,27 @@ def test_timestep_dual_criteria(ora):
     assert abs(d["dt"] * d["n_ac"] - d["dt_ad"]) < 1e-18
 
 
+def test_timestep_thermal_bound(ora):
+    """eq. 26: with a conductivity large enough, dt_ad is dt_T = 0.5 rho0 C_p
+    h^2 / k and the sub-steps are counted from it; for the oil it never binds."""
+    c = cases.tank_c1()
+    h = 1.3 * 2e-3
+    p = dict(c.params, k_f=5e4)
+    d = ora.timestep(p, c.bodies, c.xs0, c.body, c.vf)
+    dt_T = 0.5 * 870.0 * 2000.0 * h * h / 5e4
+    assert dt_T < 0.25 * h / d["vmax"]
+    assert d["dt_ad"] == pytest.approx(dt_T, rel=1e-15)
+    assert d["n_ac"] == math.ceil(dt_T / (0.6 * h / (22.5 + d["vmax"])))
+    d0 = ora.timestep(c.params, c.bodies, c.xs0, c.body, c.vf)
+    assert d0["dt_ad"] == pytest.approx(0.25 * h / d0["vmax"], rel=1e-15)
+    # per-particle materials: the most conductive one sets the bound
+    k = np.full(c.nf, 0.13)
+    k[7] = 5e4
+    s = ora.State(c, k=k, cp=np.full(c.nf, 2000.0))
+    r = s.step()
+    assert r["dt_ad"] == pytest.approx(dt_T, rel=1e-15)
+
+
 # --------------------------------------------------------------------------
 # P10, P16: mass and heat balance over full steps
 # --------------------------------------------------------------------------
