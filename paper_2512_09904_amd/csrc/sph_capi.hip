@@ -659,9 +659,13 @@ static int admit(sph_pool* P, const sph_params* p, int32_t nbody, const sph_body
   D.k_f = p->n_materials >= 1 ? p->mat_k[0] : p->k_f;
   D.cp_f = p->n_materials >= 1 ? p->mat_cp[0] : p->cp_f;
   D.nmat = pl.nmat;
+  D.dt_T = INFINITY;
   for (int m = 0; m < NMAT; ++m) {
     D.mk[m] = m < pl.nmat && p->n_materials > 0 ? p->mat_k[m] : D.k_f;
     D.mcp[m] = m < pl.nmat && p->n_materials > 0 ? p->mat_cp[m] : D.cp_f;
+    // eq. 26 with rho read as rho0
+    const double hh = p->h_over_dp * p->dp;
+    if (m < pl.nmat) D.dt_T = std::min(D.dt_T, 0.5 * p->rho0 * D.mcp[m] * hh * hh / D.mk[m]);
   }
   D.mass = p->rho0 * (p->dp * p->dp * p->dp);
   D.vol_w = p->dp * p->dp * p->dp;

@@ -64,6 +64,7 @@ struct SlotDesc {
   double cs_r;                         // cs rounded to the interaction type (frame of the offsets)
   double zref;                         // full-immersion reference of the contact factor
   double cfl_ad, cfl_ac, fixed_dt_ad, nu;
+  double dt_T;                         // thermal bound of eq. 26 over the materials
   double g[3], lo[3];
   double kW, kF;                       // W = kW (1-q/2)^4 (1+2q);  F = kF (1-q/2)^3
   double bc[NB][3], ba[NB][3], bom[NB], bT[NB], bk[NB], btip[NB];

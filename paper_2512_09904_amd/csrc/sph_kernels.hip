@@ -863,6 +863,7 @@ __global__ __launch_bounds__(BLOCK) void k_dt(const SlotDesc* table, LaunchTab t
     const double visc = h * h / S.nu;
     const double adv = vm > 0.0 ? h / vm : visc;
     tad = S.cfl_ad * (adv < visc ? adv : visc);
+    tad = fmin(tad, S.dt_T);   // eq. 26
     const double tac = S.cfl_ac * h / (S.c0 + vm);
     double nn = ceil(tad / tac);
     if (nn < 1.0) nn = 1.0;

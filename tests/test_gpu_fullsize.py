@@ -156,3 +156,60 @@ def test_fp64_mode_tracks_oracle_on_precision_tank(sph, ora):
     say("fp64 vs oracle after 40 steps", e)
     assert max(e.values()) <= 1e-9, e
     assert rg["t"] == pytest.approx(ro["t"], rel=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# the paper's two-slab conduction benchmark through the whole GPU solver
+# ---------------------------------------------------------------------------
+
+def test_two_slab_conduction_on_the_solver():
+    """Section 3.2 (Table 3) with two fluid materials: a block at rest without
+    gravity stays at rest (uniform density, no pressure), so only eq. 22
+    acts.  The materials share rho0 = 1000 with cp scaled to keep each side's
+    rho cp (1000 and 2000), which keeps the diffusivities, the effusivities and
+    the discrete rates of the benchmark.  Stepped by the solver's own time
+    step (eq. 25 with the thermal bound of eq. 26) to t = 2 and compared on the
+    centre line with the erf solution of the composite solid, within the
+    paper's 0.02."""
+    import json
+    import os
+    from scipy.special import erfc
+    from paper_2512_09904_amd import sph as S
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "slab_table3.json")))
+    s = cases.slab(nx=80, ny=40, nz=8, dx=g["dx"])
+    dx = g["dx"]
+    p = cases.default_params(dx, 1000.0, 1.0, 1e-3, 1.0, 1.0, (0, 0, 0), (1.0, 0.5, 0.1),
+                             h_over_dp=g["h_over_dx"], gravity=(0, 0, 0))
+    p["grid_lo"], p["grid_hi"] = s["lo"], s["hi"]
+    L, R = g["left"], g["right"]
+    p["materials"] = [(L["k"], L["rho"] * L["cp"] / 1000.0), (R["k"], R["rho"] * R["cp"] / 1000.0)]
+    n = len(s["x"])
+    right = s["x"][:, 0] > 0.5
+    c = cases.Case(name="two-slab", params=p, bodies=[cases.Body((5.0, 5.0, 5.0), (0.0, 1.0, 0.0), 0.0, 0.5, 1.0)],
+                   xf=s["x"], vf=np.zeros((n, 3)), rhof=np.full(n, 1000.0), Tf=s["T"].copy(),
+                   xs0=np.zeros((0, 3)), ns0=np.zeros((0, 3)), body=np.zeros(0, np.int32),
+                   material=right.astype(np.int32))
+    say("two-slab benchmark", n)
+    sol = S.Solver(c, precision="mixed")
+    t = 0.0
+    while t < g["t_end"] - 1e-12:
+        sol.step(1)
+        r = sol.reduce()
+        t = r["t"]
+    out = sol.get_fluid()
+    sol.close()
+    say("two-slab: t", t, "steps", r["step"], "dt_ad", r["dt_ad"], "vmax", r["vmax"])
+    # the block stayed at rest
+    assert r["vmax"] < 1e-8 and np.max(np.abs(out["x"] - s["x"])) < 1e-9
+    el = np.sqrt(L["k"] * L["rho"] * L["cp"])
+    er = np.sqrt(R["k"] * R["rho"] * R["cp"])
+    Tc = er / (el + er)
+    line = (np.abs(s["x"][:, 1] - 0.25) < 0.75 * dx) & (np.abs(s["x"][:, 2] - 0.05) < 0.75 * dx)
+    xl = s["x"][line, 0]
+    sel = (xl > 0.3) & (xl < 0.7)
+    xs = xl[sel]
+    exact = np.where(xs < 0.5, Tc * erfc((0.5 - xs) / (2 * np.sqrt(L["alpha"] * t))),
+                     1.0 - (1.0 - Tc) * erfc((xs - 0.5) / (2 * np.sqrt(R["alpha"] * t))))
+    err = np.max(np.abs(out["T"][line][sel] - exact))
+    say("two-slab max error on [0.3, 0.7]", err)
+    assert err <= g["criterion_max_abs_error_on_0.3_0.7"], err

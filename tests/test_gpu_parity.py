@@ -607,3 +607,29 @@ def test_material_arguments_checked(sph):
     c.params["materials"] = [(0.13, -1.0)]
     with pytest.raises(sph.SphError):
         sph.Solver(c)
+
+
+def test_thermal_bound_of_the_step(sph, ora):
+    """eq. 26 bounds dt_ad: a conductivity that makes dt_T bind gives the
+    oracle's step length and sub-step count, one material or several."""
+    c = cases.tank_c1(seed=2)
+    c.params["k_f"] = 5e4
+    o = ora.State(c)
+    ro = o.step()
+    s = sph.Solver(c)
+    s.step(1)
+    rg = s.reduce()
+    s.close()
+    h = 1.3 * 2e-3
+    assert ro["dt_ad"] == pytest.approx(0.5 * 870.0 * 2000.0 * h * h / 5e4, rel=1e-15)
+    assert rg["dt_ad"] == pytest.approx(ro["dt_ad"], rel=1e-15) and rg["n_ac"] == ro["n_ac"]
+    c = cases.tank_c1(seed=2)
+    c.params["materials"] = [(0.13, 2000.0), (5e4, 2000.0)]
+    c.material = (np.arange(c.nf) == 7).astype(np.int32)
+    k = np.where(c.material == 1, 5e4, 0.13)
+    ro = ora.State(c, k=k, cp=np.full(c.nf, 2000.0)).step()
+    s = sph.Solver(c)
+    s.step(1)
+    rg = s.reduce()
+    s.close()
+    assert rg["dt_ad"] == pytest.approx(ro["dt_ad"], rel=1e-15) and rg["n_ac"] == ro["n_ac"]
