@@ -633,3 +633,55 @@ def test_thermal_bound_of_the_step(sph, ora):
     rg = s.reduce()
     s.close()
     assert rg["dt_ad"] == pytest.approx(ro["dt_ad"], rel=1e-15) and rg["n_ac"] == ro["n_ac"]
+
+
+# ---------------------------------------------------------------------------
+# the all-FP32 mode of the precision study
+# ---------------------------------------------------------------------------
+
+def test_fp32_mode_one_step(sph, ora):
+    """All-FP32 mode (absolute FP32 positions, density and temperature) from
+    an FP32-representable state, one step at fixed dt against the FP64
+    oracle: neighbour sets equal but for pairs within 1e-5 of the cutoff
+    (FP32 distances); positions, density and temperature within 20 FP32 ulps
+    of their largest magnitude, and the velocity within what 20 ulps of the
+    absolute density imply through the pressure over the step's sub-steps
+    (dv <= n_ac dt 6 c0^2 dRho / (rho0 h)); mass to FP32 summation."""
+    c = ragged_tank(seed=5)
+    f32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+    c.xf, c.rhof, c.Tf, c.vf = f32(c.xf), f32(c.rhof), f32(c.Tf), f32(c.vf)
+    say("fp32 mode", c.nf)
+    dt, nac = fixed_dt(c)
+    s = sph.Solver(c, precision="fp32", fixed_dt_ad=dt, fixed_nac=nac)
+    fl, _ = s.neighbour_sets()
+    fid = s.dump("fluid_ids").astype(np.int64)
+    xs, _, _ = ora.body_pose(c.bodies, c.xs0, c.ns0, c.body, 0.0)
+    nb = ora.Nbr(c.params, c.xf, xs)
+    ref = nb.sets(0)
+    cut2 = (2.0 * c.params["h_over_dp"] * c.params["dp"]) ** 2
+    ndiff = 0
+    for i in range(c.nf):
+        for j in fl[i] ^ ref[i]:
+            d2 = float(np.sum((c.xf[i] - c.xf[j]) ** 2))
+            assert abs(d2 - cut2) <= 1e-5 * cut2, (i, j, d2, cut2)
+            ndiff += 1
+    s.step(1)
+    rg = s.reduce()
+    g = s.get_fluid()
+    s.close()
+    o = ora.State(c, fixed_dt_ad=dt, fixed_nac=nac)
+    ro = o.step()
+    umax, c0, rho0 = c.meta["umax"], c.params["c0"], c.params["rho0"]
+    Q = dict(x=c.params["dp"], v=umax, rho=rho0 * (umax / c0) ** 2, T=abs(c.bodies[0].T - c.Tf.mean()))
+    ulp = lambda a: float(np.spacing(np.float32(np.max(np.abs(a)))))
+    err = dict(x=np.max(np.abs(g["x"] - o.x)), v=np.max(np.abs(g["v"] - o.v)),
+               rho=np.max(np.abs(g["rho"] - o.rho)), T=np.max(np.abs(g["T"] - o.T)))
+    h = c.params["h_over_dp"] * c.params["dp"]
+    drho = 20 * ulp(o.rho)
+    bar = dict(x=20 * ulp(o.x), v=nac * (dt / nac) * 6.0 * c0 ** 2 * drho / (rho0 * h), rho=drho, T=20 * ulp(o.T))
+    say("fp32 mode: set differences", ndiff, "normalised errors", {k: err[k] / Q[k] for k in err},
+        "bars", {k: bar[k] / Q[k] for k in bar})
+    for k in err:
+        assert err[k] <= bar[k], (k, err[k], bar[k])
+    assert rg["n_ac"] == ro["n_ac"]
+    assert rg["mass"] == pytest.approx(ro["mass"], rel=1e-6)
