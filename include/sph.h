@@ -91,7 +91,10 @@ typedef struct {
   int32_t reserved;     /* must be 0 */
   int32_t n_materials;  /* 0: one fluid material (k_f, cp_f); 1..SPH_MAX_MATERIALS: the table below,
                            indexed by the per-particle material of sph_set_fluid / sph_pool_admit
-                           (eq. 22 with k_i, k_j, cp_i per particle; density and viscosity shared) */
+                           (eq. 22 with k_i, k_j, cp_i per particle; density and viscosity shared),
+                           k_f and cp_f then unused; every k and cp > 0, else SPH_ERR_ARG.  The
+                           advection step is also bounded by eq. 26, 0.5 rho0 cp h^2 / k, over the
+                           materials */
   int32_t reserved2;    /* must be 0 */
   double mat_k[SPH_MAX_MATERIALS];   /* thermal conductivity of each material [W/(m K)] */
   double mat_cp[SPH_MAX_MATERIALS];  /* specific heat of each material [J/(kg K)] */
