@@ -287,6 +287,50 @@ def relax_bench(args):
                       "bounded_last": rep["bounded_last"], "cpu_baseline": cpu}), flush=True)
 
 
+def contact_bench(args):
+    """Contact factor (eq. 24) of every solid particle of the gearbox proxy after
+    10 steps: the call (cell sort, neighbour build and the solid-centric
+    k_contact sweep) timed over `contact_calls` calls."""
+    import torch
+    from paper_2512_09904_amd import cases, sph
+    case = cases.gearbox(seed=0, dp=args.dp, omega_big=300.0, immersion=0.030, nu=1e-4)
+    log(f"contact case: nf={case.nf} ns={case.ns}")
+    s = sph.Solver(case, precision=args.precision)
+    s.step(10)
+    s.reduce()
+    s.contact_factor()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.contact_calls):
+        z, means = s.contact_factor()
+    wall = time.perf_counter() - t0
+    s.set_timing(True)
+    s.contact_factor()
+    kt = {k: float(np.mean(s.timing(k))) for k in ("contact", "build", "sumw", "cellsort") if len(s.timing(k))}
+    s.set_timing(False)
+    t = s.reduce()["t"]
+    g = s.get_fluid()
+    s.close()
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        O.build(force=False)
+        xs, _, _ = O.body_pose(case.bodies, case.xs0, case.ns0, case.body, t)
+        t1 = time.perf_counter()
+        zo = O.contact_factor(case.params, g["x"], g["rho"], xs)
+        tc = time.perf_counter() - t1
+        cores = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
+        cpu = {"value": case.ns / tc, "unit": "solid particles/s", "cores": cores, "kind": "oracle",
+               "sample": f"one contact-factor evaluation of the same {case.ns} solid particles, FP64 C oracle, "
+                         f"{tc:.2f} s", "max_abs_diff_vs_gpu": float(np.max(np.abs(zo - z)))}
+    ms = 1e3 * wall / args.contact_calls
+    print(json.dumps({"metric": "contact factor evaluations/s (eq. 24)", "value": 1e3 / ms, "unit": "calls/s",
+                      "ms_per_call": ms, "solid_particles_per_s": case.ns * 1e3 / ms, "precision": args.precision,
+                      "config": {"workload": f"gearbox proxy dp={args.dp * 1e3:.2f} mm after 10 steps",
+                                 "n_fluid": case.nf, "n_solid": case.ns},
+                      "kernel_ms": kt, "body_means": [float(m) for m in means], "cpu_baseline": cpu}), flush=True)
+
+
 def precision_study(args):
     """All-FP32 vs mixed FP32/FP64 vs FP64 on the churning tank (C1 geometry).
 
@@ -384,6 +428,9 @@ def main():
     ap.add_argument("--relax", action="store_true",
                     help="particle relaxation of the 40-tooth gear body instead of the solver bench")
     ap.add_argument("--relax-iters", type=int, default=50)
+    ap.add_argument("--contact", action="store_true",
+                    help="contact factor (eq. 24) of the gearbox proxy's solid particles instead of the solver bench")
+    ap.add_argument("--contact-calls", type=int, default=20)
     ap.add_argument("--precision-study", action="store_true",
                     help="churning tank in fp32 / mixed / fp64: drift of the conserved quantities")
     ap.add_argument("--ps-steps", type=int, default=100000)
@@ -419,6 +466,9 @@ def main():
         return
     if args.relax:
         relax_bench(args)
+        return
+    if args.contact:
+        contact_bench(args)
         return
 
     t0 = time.perf_counter()
