@@ -347,6 +347,32 @@ def test_capacity_error(sph):
     assert e.value.code == sph.SPH_ERR_CAPACITY
 
 
+
+def test_argument_errors(sph):
+    """Inputs the C ABI refuses with SPH_ERR_ARG before touching the device:
+    no fluid, h outside [1, 2] dp, a grid over 1024 cells per axis, a fixed
+    step without sub-steps, non-positive constants, too many bodies."""
+    say("argument errors")
+    bad = []
+    c = cases.tank_c1()
+    empty = c.copy()
+    empty.xf, empty.vf, empty.rhof, empty.Tf = np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0), np.zeros(0)
+    bad.append((empty, {}))
+    bad.append((c, dict(h_over_dp=2.5)))
+    big = c.copy()
+    big.params = dict(c.params, grid_hi=(c.params["grid_lo"][0] + 1100 * 2 * 1.3 * c.params["dp"],
+                                         c.params["grid_hi"][1], c.params["grid_hi"][2]))
+    bad.append((big, {}))
+    bad.append((c, dict(fixed_dt_ad=1e-4, fixed_nac=0)))
+    bad.append((c, dict(nu=0.0)))
+    many = c.copy()
+    many.bodies = list(c.bodies) * 5          # 10 bodies, at most 8
+    bad.append((many, {}))
+    for case, over in bad:
+        with pytest.raises(sph.SphError) as e:
+            sph.Solver(case, **over)
+        assert e.value.code == sph.SPH_ERR_ARG, (over, e.value)
+
 def test_nonfinite_is_latched(sph):
     c = cases.tank_c1()
     say("non-finite latch")
