@@ -76,6 +76,36 @@ def test_fullsize_one_step(sph, ora, gearbox):
         assert bg["heat_rate"] == pytest.approx(bo["heat_rate"], rel=1e-3)
 
 
+
+@pytest.mark.timeout(600)
+def test_fullsize_five_steps(sph, ora, gearbox):
+    """Five advection steps of the full gearbox proxy at the oracle's first
+    step length: the state stays within the one-step bar (1e-5 normalised)
+    and per-body torque and heat flow within 1e-3."""
+    c = gearbox
+    d = ora.timestep(c.params, c.bodies, c.xs0, c.body, c.vf)
+    say("full-size five steps", d)
+    o = ora.State(c, fixed_dt_ad=d["dt_ad"], fixed_nac=d["n_ac"])
+    for _ in range(5):
+        ro = o.step()
+    s = sph.Solver(c, precision="mixed", fixed_dt_ad=d["dt_ad"], fixed_nac=d["n_ac"])
+    s.step(5)
+    rg = s.reduce()
+    g = s.get_fluid()
+    s.close()
+    umax, c0, rho0 = c.meta["umax"], c.params["c0"], c.params["rho0"]
+    e = dict(x=np.max(np.abs(g["x"] - o.x)) / c.params["dp"],
+             v=np.max(np.abs(g["v"] - o.v)) / umax,
+             rho=np.max(np.abs(g["rho"] - o.rho)) / (rho0 * (umax / c0) ** 2),
+             T=np.max(np.abs(g["T"] - o.T)) / 20.0)
+    say("full-size five-step normalised errors", e)
+    assert max(e.values()) <= 1e-5, e
+    assert rg["step"] == 5 and rg["t"] == pytest.approx(o.t, rel=1e-14)
+    for bg, bo in zip(rg["bodies"], ro["bodies"]):
+        ts = np.abs(bo["torque"]).max()
+        assert np.max(np.abs(bg["torque"] - bo["torque"])) <= 1e-3 * ts
+        assert bg["heat_rate"] == pytest.approx(bo["heat_rate"], rel=1e-3)
+
 def _gpu_state(s, nf):
     """Fluid state in original order from the raw dump: position = anchor + drift
     (the fold the next step starts with), and the carried continuity rate."""
