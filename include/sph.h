@@ -83,8 +83,8 @@ typedef struct {
   int32_t nac_max;      /* cap on sub-steps; dt_ad is shortened to nac_max dt_ac when hit */
   int32_t free_surface; /* 1: eq. 14 (max with the carried density), 0: eq. 15 */
   int32_t precision;    /* SPH_PREC_* */
-  int32_t max_fluid_nbrs; /* neighbour row capacity, 0 = 128 */
-  int32_t max_solid_nbrs; /* solid neighbour row capacity, 0 = 96 */
+  int32_t max_fluid_nbrs; /* neighbour row capacity, 0 = 128; rounded up to a multiple of 16 */
+  int32_t max_solid_nbrs; /* solid neighbour row capacity, 0 = 96; rounded up to a multiple of 16 */
   int32_t viscous_heating; /* 1: add the viscous dissipation Phi = 2 eta S:S of eq. 23 (S the strain
                               rate from the SPH velocity gradient over fluid and wall neighbours) to
                               dT/dt as Phi/(rho cp); 0: the paper's model, conduction only */

@@ -98,8 +98,9 @@ static int make_plan(const sph_params* p, int prec, int64_t nf, int64_t ns, Plan
   P->ns = ns;
   P->ncells = (int32_t)ncell;
   // capacities are rounded up to multiples of 4 (rows are walked 4 at a time)
-  P->kf = ((p->max_fluid_nbrs > 0 ? p->max_fluid_nbrs : 128) + 7) & ~7;
-  P->ks = ((p->max_solid_nbrs > 0 ? p->max_solid_nbrs : 96) + 7) & ~7;
+  // multiples of sixteen: the sweeps read whole row groups of up to 16 entries
+  P->kf = ((p->max_fluid_nbrs > 0 ? p->max_fluid_nbrs : 128) + 15) & ~15;
+  P->ks = ((p->max_solid_nbrs > 0 ? p->max_solid_nbrs : 96) + 15) & ~15;
   if (P->kf > 1024 || P->ks > 1024) return fail(SPH_ERR_ARG, "neighbour capacity above 1024");
   P->nslices = (int32_t)ceil_div(nf, WAVE);
   P->rowlen_f = (int64_t)P->nslices * P->kf * WAVE;
