@@ -20,8 +20,9 @@
 namespace sphk {
 
 // Rows are walked ROW_UNROLL entries at a time (SOLID_UNROLL for the wall
-// rows, CONT_UNROLL in the continuity sweep, which runs faster with sixteen
-// gathers in flight at two waves per SIMD), and the next group's indices are
+// rows, VISC_SOLID_UNROLL for the viscous/heat sweep's wall rows, CONT_UNROLL
+// in the continuity sweep, which runs faster with sixteen gathers in flight
+// at two waves per SIMD: group sizes measured per sweep), and the next group's indices are
 // loaded before the current group's gathers are consumed, so a wavefront
 // keeps two dependent loads in flight.  Entries past a row's count are loaded
 // from the row's capacity (always in bounds: capacities are multiples of
@@ -29,7 +30,8 @@ namespace sphk {
 // the count) and replaced by a null entry: own index, F = 0, which adds
 // exactly zero to every sum.
 #define ROW_UNROLL 8
-#define SOLID_UNROLL 4
+#define SOLID_UNROLL 8
+#define VISC_SOLID_UNROLL 4
 #define CONT_UNROLL 16
 
 // A block's window of the fluid anchors: the WIN particles around the
@@ -1001,24 +1003,24 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
       const GLB Real4* lv = gpc<Real4>(S.lev);
       const Real Vw = (Real)S.vol_w;
       const Real rc = rcp(rhoi * (Real)cpI);
-      uint32_t wn[SOLID_UNROLL];
+      uint32_t wn[VISC_SOLID_UNROLL];
 #pragma unroll
-      for (int u = 0; u < SOLID_UNROLL; ++u) wn[u] = ldnt(R + (int64_t)u * WAVE);
-      for (int k0 = 0; k0 < n; k0 += SOLID_UNROLL) {
-        Real4 owu[SOLID_UNROLL], vqu[SOLID_UNROLL], lqu[SOLID_UNROLL];
+      for (int u = 0; u < VISC_SOLID_UNROLL; ++u) wn[u] = ldnt(R + (int64_t)u * WAVE);
+      for (int k0 = 0; k0 < n; k0 += VISC_SOLID_UNROLL) {
+        Real4 owu[VISC_SOLID_UNROLL], vqu[VISC_SOLID_UNROLL], lqu[VISC_SOLID_UNROLL];
 #pragma unroll
-        for (int u = 0; u < SOLID_UNROLL; ++u) {
+        for (int u = 0; u < VISC_SOLID_UNROLL; ++u) {
           const uint32_t w = k0 + u < n ? wn[u] : 0u;
           owu[u] = so[w];
           vqu[u] = vw[w];
           lqu[u] = lv[w];
         }
-        if (k0 + SOLID_UNROLL < n) {
+        if (k0 + VISC_SOLID_UNROLL < n) {
 #pragma unroll
-          for (int u = 0; u < SOLID_UNROLL; ++u) wn[u] = ldnt(R + (int64_t)(k0 + SOLID_UNROLL + u) * WAVE);
+          for (int u = 0; u < VISC_SOLID_UNROLL; ++u) wn[u] = ldnt(R + (int64_t)(k0 + VISC_SOLID_UNROLL + u) * WAVE);
         }
 #pragma unroll
-        for (int u = 0; u < SOLID_UNROLL; ++u) {
+        for (int u = 0; u < VISC_SOLID_UNROLL; ++u) {
         if (k0 + u >= n) break;
         const Real4 ow = owu[u], vq = vqu[u], lq = lqu[u];
         Real rx, ry, rz;
