@@ -20,7 +20,17 @@
  *  - integrator inside the dual-criteria step: position Verlet with
  *    half-step density updates; pair geometry, body pose, viscous and heat
  *    rates frozen for the advection step; temperature by explicit Euler;
- *  - torque on a body: sum over wall pairs of (x_w - c_B) x (-f_iw).
+ *  - torque on a body: sum over wall pairs of (x_w - c_B) x (-f_iw);
+ *  - viscous dissipation (eq. 23, optional): S from the SPH velocity
+ *    gradient over fluid and wall neighbours;
+ *  - thermal step bound (eq. 26): dt_ad <= 0.5 rho0 C_p h^2 / k;
+ *  - relaxation (Section 2.2): exterior kernel-gradient integral on cells of
+ *    edge h/4 with a linear outside fraction; confinement to phi <= -dp/2.
+ *
+ * Parity unpinned: the magnitude of the wall viscous torque (literal eq. 18,
+ * wall particles at the body's velocity) has no closed form to pin to at
+ * the resolutions used; its sign and the direction of its convergence with
+ * resolution are pinned (rotating sphere), its magnitude is not.
  */
 #include "sph_oracle.h"
 
