@@ -131,7 +131,12 @@ def cpu_baseline(case, steps=6):
     """The FP64 oracle on the host cores, on a bounded sample of the same workload."""
     from oracle import oracle as O
     O.build(force=False)
-    o = O.State(case)
+    mats = case.params.get("materials")
+    if mats and case.material is not None:
+        m = np.asarray(mats, dtype=np.float64)[case.material]
+        o = O.State(case, k=m[:, 0], cp=m[:, 1])
+    else:
+        o = O.State(case)
     nb = O.Nbr(case.params, case.xf, O.body_pose(case.bodies, case.xs0, case.ns0, case.body, 0.0)[0])
     pf = int(nb.csr(0)[0][-1])
     ps = int(nb.csr(1)[0][-1])
@@ -415,6 +420,8 @@ def main():
                     help="gearbox: the 1.5 mm proxy at 300 rad/s (default); full: the 1 mm proxy at 600 rad/s")
     ap.add_argument("--viscous-heating", action="store_true",
                     help="add the viscous dissipation heating of eq. 23 (off in the paper's model)")
+    ap.add_argument("--materials", action="store_true",
+                    help="two fluid materials (eq. 22 with k_i, cp_i), split at the box's mid-plane x")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--calib-copy", action="store_true", help="run one 1 GiB device copy (counter calibration)")
@@ -480,6 +487,9 @@ def main():
     case = cases.gearbox(seed=0, dp=dp, omega_big=om, immersion=imm, nu=nu)
     if args.viscous_heating:
         case.params["viscous_heating"] = 1
+    if args.materials:
+        case.params["materials"] = [(case.params["k_f"], case.params["cp_f"]), (0.45, 1300.0)]
+        case.material = (case.xf[:, 0] > 0.5 * (case.xf[:, 0].min() + case.xf[:, 0].max())).astype(np.int32)
     log(f"case: nf={case.nf} ns={case.ns} generated in {time.perf_counter() - t0:.1f} s")
     s = sph.Solver(case, precision=args.precision)
     log("initialised")
@@ -597,7 +607,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"gearbox proxy dp={dp * 1e3:.2f} mm, two toothed disks 20/40 teeth at "
                                f"-{2 * om:.0f}/{om:.0f} rad/s, {imm * 1e3:.0f} mm immersion, nu={nu:g}"
-                               + (", viscous dissipation heating" if args.viscous_heating else ""),
+                               + (", viscous dissipation heating" if args.viscous_heating else "")
+                               + (", two fluid materials" if args.materials else ""),
                    "n_fluid": case.nf, "n_solid": case.ns, "n_ac_last": n_ac, "pairs_per_sweep": int(pairs),
                    "pair_sweeps_per_step": round(sweeps, 3), "precision": args.precision, "parallelism": "single GPU"},
         "sweep_latency": sweep_lat,
