@@ -225,8 +225,9 @@ typedef struct {
  * for the neighbours missing beyond the surface; dt = 0.25 sqrt(h / max|F_p|)
  * (eq. 8); x += F_p dt^2 / 2 (eq. 9); a particle ending at phi > -dp/2 is put
  * back on the level -dp/2 along the unit normal (static confinement).  The
- * solver's solid particles take no part.  Only positions change (read them with sph_get_fluid; the density re-initialisation
- * of each build also runs).  Call between steps; synchronises.  SPH_ERR_ARG
+ * solver's solid particles take no part.  Only positions change (read them
+ * with sph_get_fluid; the density re-initialisation of each build also
+ * runs).  Call between steps; synchronises.  SPH_ERR_ARG
  * for a bad shape or iterations < 1, SPH_ERR_DOMAIN if a particle leaves the
  * grid, SPH_ERR_STATE before sph_init or after a latched fault. */
 int sph_relax(sph_solver* s, const sph_shape* shape, int32_t iterations, sph_relax_report* report);
