@@ -44,8 +44,8 @@ def _requests():
             cases.serving_tank(4000, 200.0, 0.025, 0.7e-4, seed=3)]
 
 
-def _run_pool(sph, reqs, steps, stagger, max_slots=4):
-    pool = sph.Pool(1 << 40, max_slots=max_slots)
+def _run_pool(sph, reqs, steps, stagger, max_slots=4, precision="mixed"):
+    pool = sph.Pool(1 << 40, max_slots=max_slots, precision=precision)
     out = {}
     slots = {}
     pending = list(range(len(reqs)))
@@ -143,6 +143,24 @@ def test_solver_equals_pool_slot(sph):
     for key in ("x", "v", "rho", "T"):
         assert np.array_equal(g[key], gp[key]), key
     assert r["bodies"][1]["torque_axis"] == rp["bodies"][1]["torque_axis"]
+
+
+def test_fp64_pool_mix_equals_fp64_solver(sph):
+    """In FP64 mode too, a request batched with others gives the solver's
+    own result bit for bit."""
+    reqs = _requests()
+    say("serving: fp64 pool mix vs fp64 solver")
+    s = sph.Solver(reqs[2], precision="fp64")
+    s.step(4)
+    r = s.reduce()
+    g = s.get_fluid()
+    s.close()
+    mix = _run_pool(sph, reqs, [3, 5, 4], [0, 1, 1], precision="fp64")
+    gm, rm = mix[2]
+    assert rm["rc"] == 0 and rm["step"] == 4
+    for key in ("x", "v", "rho", "T"):
+        assert np.array_equal(g[key], gm[key]), key
+    assert r["thermal"] == rm["thermal"] and r["heat_total"] == rm["heat_total"]
 
 
 def test_admission_respects_budget(sph):
