@@ -1426,42 +1426,70 @@ __global__ __launch_bounds__(FINAL_BLOCK) void k_final(const SlotDesc* table, La
   const int nq = NGLOB + S.nbody * 13 + (S.diss ? 1 : 0);
   const int q_diss = NGLOB + S.nbody * 13;
   const int wv = threadIdx.x / WAVE, ln = threadIdx.x % WAVE;
-  for (int qi = wv; qi < nq; qi += FINAL_BLOCK / WAVE) {
+  // each wavefront reduces QPW quantities at once (QPW x 8 independent loads
+  // in flight per lane), each one's partials added in the same fixed order
+  constexpr int QPW = 3;
+  for (int q0 = wv * QPW; q0 < nq; q0 += (FINAL_BLOCK / WAVE) * QPW) {
     // quantity qi: global k, or body b component c (7 viscous then 6 pressure)
     // partials are quantity-major: src[q * nblk + block]
-    const double* src;
-    bool is_max = false;
-    if (qi < NGLOB) {
-      src = S.glob_part + (size_t)qi * nblk;
-      is_max = qi == 4;
-    } else if (qi == q_diss) {
-      src = S.glob_part + (size_t)NGLOB * nblk;
-    } else {
-      const int b = (qi - NGLOB) / 13, c = (qi - NGLOB) % 13;
-      src = c < 7 ? S.visc_part + (size_t)(b * 7 + c) * nblk : S.press_part + (size_t)(b * 6 + c - 7) * nblk;
-    }
-    const GLB double* q = gpc<double>(src);
-    if (is_max) {
-      double m = 0.0;
-      for (int k = ln; k < nblk; k += WAVE) m = fmax(m, q[k]);
+    const GLB double* qs[QPW];
+    bool use[QPW], mx[QPW];
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, WAVE));
-      if (ln == 0) res[qi] = m;
-    } else {
-      // eight independent loads in flight per lane, then added in order
-      KS ks = {0.0, 0.0};
-      for (int k0 = 0; k0 < nblk; k0 += 8 * WAVE) {
-        double x[8];
+    for (int t = 0; t < QPW; ++t) {
+      const int qi = q0 + t;
+      use[t] = qi < nq;
+      mx[t] = qi == 4;
+      const double* src = S.glob_part;
+      if (!use[t]) {
+      } else if (qi < NGLOB) {
+        src = S.glob_part + (size_t)qi * nblk;
+      } else if (qi == q_diss) {
+        src = S.glob_part + (size_t)NGLOB * nblk;
+      } else {
+        const int b = (qi - NGLOB) / 13, c = (qi - NGLOB) % 13;
+        src = c < 7 ? S.visc_part + (size_t)(b * 7 + c) * nblk : S.press_part + (size_t)(b * 6 + c - 7) * nblk;
+      }
+      qs[t] = gpc<double>(src);
+    }
+    KS ks[QPW];
+    double m[QPW];
+#pragma unroll
+    for (int t = 0; t < QPW; ++t) {
+      ks[t] = KS{0.0, 0.0};
+      m[t] = 0.0;
+    }
+    for (int k0 = 0; k0 < nblk; k0 += 8 * WAVE) {
+      double x[QPW][8];
+#pragma unroll
+      for (int t = 0; t < QPW; ++t)
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int k = k0 + u * WAVE + ln;
-          x[u] = k < nblk ? q[k] : 0.0;
+          x[t][u] = use[t] && k < nblk ? qs[t][k] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) ks_add(ks, x[u]);
+      for (int t = 0; t < QPW; ++t) {
+        if (mx[t]) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) m[t] = fmax(m[t], x[t][u]);
+        } else {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) ks_add(ks[t], x[t][u]);
+        }
       }
-      ks = wave_ks(ks);
-      if (ln == 0) res[qi] = ks.s + ks.c;
+    }
+#pragma unroll
+    for (int t = 0; t < QPW; ++t) {
+      if (!use[t]) continue;
+      if (mx[t]) {
+        double v = m[t];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
+        if (ln == 0) res[q0 + t] = v;
+      } else {
+        const KS w = wave_ks(ks[t]);
+        if (ln == 0) res[q0 + t] = w.s + w.c;
+      }
     }
   }
   __syncthreads();
