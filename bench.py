@@ -416,8 +416,9 @@ def main():
     ap.add_argument("--timed-steps", type=int, default=20, help="steps of the per-kernel event-timed pass")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64", "fp32"])
     ap.add_argument("--dp", type=float, default=1.5e-3, help="particle spacing of the gearbox proxy")
-    ap.add_argument("--workload", default="gearbox", choices=["gearbox", "full"],
-                    help="gearbox: the 1.5 mm proxy at 300 rad/s (default); full: the 1 mm proxy at 600 rad/s")
+    ap.add_argument("--workload", default="gearbox", choices=["gearbox", "full", "fine"],
+                    help="gearbox: the 1.5 mm proxy at 300 rad/s (default); full: the 1 mm proxy at 600 rad/s; "
+                         "fine: the full proxy at dp = 0.8 mm (about 5.9 M particles)")
     ap.add_argument("--viscous-heating", action="store_true",
                     help="add the viscous dissipation heating of eq. 23 (off in the paper's model)")
     ap.add_argument("--materials", action="store_true",
@@ -479,9 +480,9 @@ def main():
         return
 
     t0 = time.perf_counter()
-    if args.workload == "full":
-        # the 1 mm proxy: 40-tooth gear at 600 rad/s, 50 mm immersion, nu = 2.2e-4
-        om, imm, nu, dp = 600.0, 0.050, 2.2e-4, 1e-3
+    if args.workload in ("full", "fine"):
+        # the full-size proxy: 40-tooth gear at 600 rad/s, 50 mm immersion, nu = 2.2e-4
+        om, imm, nu, dp = 600.0, 0.050, 2.2e-4, (1e-3 if args.workload == "full" else 0.8e-3)
     else:
         om, imm, nu, dp = 300.0, 0.030, 1e-4, args.dp
     case = cases.gearbox(seed=0, dp=dp, omega_big=om, immersion=imm, nu=nu)
@@ -560,7 +561,11 @@ def main():
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
         ent = tr.get(dom, {})
-        if tr.get("kernel_sha") == kernel_hash() and tr.get("precision") == args.precision:
+        # counters are per launch of one workload: they stand only for that one
+        wl = {"n_fluid": case.nf, "n_solid": case.ns, "viscous_heating": int(args.viscous_heating),
+              "n_materials": 2 if args.materials else 1}
+        if (tr.get("kernel_sha") == kernel_hash() and tr.get("precision") == args.precision
+                and tr.get("workload") == wl):
             traffic = ent.get("bytes_per_launch")
     if dom == "build":
         roofline = {"bound": "alu", "achieved": kern["build"]["fp64_tflops"], "peak": FP64_PEAK_TFLOPS,

@@ -339,6 +339,73 @@ def test_domain_error_at_init(sph):
     assert e.value.code == sph.SPH_ERR_DOMAIN
 
 
+def corner_blobs(seed=7):
+    """Four jittered fluid blocks in the corners of a grid of 1024 x 1024 x 4
+    cells (the largest extent per axis), with a static plate under one and a
+    small plate turning about the vertical under another: cells 0 and 1023,
+    the top Morton bits and the clipped neighbour stencils at the grid's edge."""
+    dp, hod = 2e-3, 1.3
+    cs = 2.0 * hod * dp
+    lo = np.zeros(3)
+    hi = np.array([1023.9 * cs, 1023.9 * cs, 3.5 * cs])
+    rng = np.random.default_rng(seed)
+    I, J, K = np.meshgrid(np.arange(6), np.arange(6), np.arange(5), indexing="ij")
+    blk = (np.stack([I.ravel(), J.ravel(), K.ravel()], 1) + 0.5) * dp
+    corners = [(0.5 * dp, 0.5 * dp), (hi[0] - 7 * dp, 2 * dp), (0.5 * dp, hi[1] - 7 * dp),
+               (hi[0] - 7 * dp, hi[1] - 7 * dp)]
+    xf = np.concatenate([blk + [cx, cy, 2 * dp] for cx, cy in corners])
+    xf = xf + rng.uniform(-0.05, 0.05, xf.shape) * dp
+    nf = len(xf)
+    I, J = np.meshgrid(np.arange(8), np.arange(8), indexing="ij")
+    still = (np.stack([I.ravel(), J.ravel(), np.zeros(I.size)], 1) + 0.5) * dp
+    still = still + [corners[0][0], corners[0][1], 0.0]
+    I, J = np.meshgrid(np.arange(4), np.arange(4), indexing="ij")
+    spin = (np.stack([I.ravel(), J.ravel(), np.zeros(I.size)], 1) + 0.5) * dp
+    spin = spin + [corners[1][0] + dp, corners[1][1] + dp, 0.0]
+    xs0 = np.concatenate([still, spin])
+    ns0 = np.tile([0.0, 0.0, 1.0], (len(xs0), 1))
+    body = np.concatenate([np.zeros(len(still), np.int32), np.ones(len(spin), np.int32)])
+    T_oil, T_wall = 313.15, 333.15
+    bodies = [cases.Body(center=(0.0, 0.0, 0.0), axis=(0.0, 0.0, 1.0), omega=0.0, T=T_wall, k=20.0),
+              cases.Body(center=(corners[1][0] + 3 * dp, corners[1][1] + 3 * dp, 0.0),
+                         axis=(0.0, 0.0, 1.0), omega=20.0, T=T_wall, k=20.0)]
+    params = cases.default_params(dp, 870.0, 5.0, 1e-4, 0.13, 2000.0, lo, hi, h_over_dp=hod)
+    params["grid_lo"], params["grid_hi"] = tuple(lo), tuple(hi)
+    return cases.Case(name="corner_blobs", params=params, bodies=bodies, xf=xf,
+                      vf=rng.uniform(-0.05, 0.05, (nf, 3)),
+                      rhof=870.0 * (1.0 + 1e-3 * rng.uniform(-1, 1, nf)),
+                      Tf=T_oil + rng.uniform(-5, 5, nf), xs0=xs0, ns0=ns0, body=body,
+                      meta=dict(umax=0.5, seed=seed))
+
+
+def test_grid_at_maximum_extent(sph, ora):
+    """Cells, order and neighbour sets bit-exact, then one step within the
+    mixed-precision bar, on a grid of 1024 cells along x and y."""
+    c = corner_blobs()
+    rc, cell = ora.cells(c.params, c.xf)
+    assert rc == 0 and cell[:, 0].max() == 1023 and cell[:, 1].max() == 1023 and cell.min() == 0
+    say("grid at maximum extent", c.nf, c.ns)
+    s = sph.Solver(c, precision="mixed")
+    assert s.dump("fluid_cell").size == c.nf
+    fid = s.dump("fluid_ids").astype(np.int64)
+    rc, order = ora.sort_order(c.params, c.xf, np.arange(c.nf, dtype=np.uint32))
+    assert np.array_equal(fid, order)
+    mort = np.array([ora.morton3(*cc) for cc in cell[fid]], dtype=np.uint32)
+    assert np.array_equal(s.dump("fluid_cell"), mort)
+    assert np.any((mort >> 27) & 3 == 3)            # the top x and y bits of the key
+    xs, _, _ = ora.body_pose(c.bodies, c.xs0, c.ns0, c.body, 0.0)
+    nb = ora.Nbr(c.params, c.xf, xs)
+    fl, so = s.neighbour_sets()
+    assert fl == nb.sets(0)
+    assert so == nb.sets(1)
+    s.close()
+    o, ro, g, st, rg = _one_step(sph, ora, c, "mixed")
+    e = _normalised_errors(c, o, g)
+    say("normalised errors", e)
+    assert max(e.values()) <= 1e-5, e
+    assert rg["n_ac"] == ro["n_ac"]
+
+
 def test_capacity_error(sph):
     c = cases.tank_c1()
     say("capacity error")
