@@ -4,6 +4,7 @@
 // build, and the move with level-set confinement.  Launched by sph_relax; one
 // iteration is sort/build -> relax_force -> relax_max -> relax_move.
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "sph_device.h"
@@ -23,8 +24,11 @@ __constant__ uint32_t qcells[QMAX];
 static int qcells_count = 0;
 static bool qcells_loaded[64] = {};
 
-// the table, built on the host and copied to the current device once
+// the table, built on the host and copied to the current device once (under
+// a lock: solvers on different host threads may start a relaxation together)
+static std::mutex qcells_mutex;
 static hipError_t qcells_init(int* count) {
+  std::lock_guard<std::mutex> lock(qcells_mutex);
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;

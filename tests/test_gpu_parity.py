@@ -406,6 +406,44 @@ def test_grid_at_maximum_extent(sph, ora):
     assert rg["n_ac"] == ro["n_ac"]
 
 
+@pytest.mark.parametrize("hod,caps", [(1.0, {}), (2.0, dict(max_fluid_nbrs=320, max_solid_nbrs=256))])
+def test_smoothing_length_extremes(sph, ora, hod, caps):
+    """h at both ends of the accepted range [1, 2] dp (26 and about 250
+    neighbours in the bulk, a cell edge of 2 and 4 dp): sets bit-exact,
+    kernel sums and the re-initialised density against the oracle's own
+    lattice constant, then one step within the mixed bar."""
+    c = ragged_tank(seed=3)
+    c.params["h_over_dp"] = hod
+    say("smoothing length", hod, c.nf)
+    s = sph.Solver(c, precision="mixed", **caps)
+    fid = s.dump("fluid_ids").astype(np.int64)
+    rc, order = ora.sort_order(c.params, c.xf, np.arange(c.nf, dtype=np.uint32))
+    assert rc == 0 and np.array_equal(fid, order)
+    xs, _, _ = ora.body_pose(c.bodies, c.xs0, c.ns0, c.body, 0.0)
+    nb = ora.Nbr(c.params, c.xf, xs)
+    fl, so = s.neighbour_sets()
+    assert fl == nb.sets(0)
+    assert so == nb.sets(1)
+    sw = ora.sum_w(c.params, nb)
+    assert np.allclose(s.dump("sumw")[np.argsort(fid)], sw, rtol=1e-12, atol=0)
+    S0 = ora.lattice_sum0(hod)
+    rho_ref = np.maximum(c.rhof, c.params["rho0"] * c.params["dp"] ** 3 * sw / S0)
+    assert np.max(np.abs(s.get_fluid()["rho"] - rho_ref) / c.params["rho0"]) <= 2e-7
+    s.close()
+    dt, nac = fixed_dt(c)
+    o = ora.State(c, fixed_dt_ad=dt, fixed_nac=nac)
+    ro = o.step()
+    s = sph.Solver(c, precision="mixed", fixed_dt_ad=dt, fixed_nac=nac, **caps)
+    s.step(1)
+    rg = s.reduce()
+    g = s.get_fluid()
+    s.close()
+    e = _normalised_errors(c, o, g)
+    say("normalised errors", hod, e)
+    assert max(e.values()) <= 1e-5, e
+    assert rg["n_ac"] == ro["n_ac"]
+
+
 def test_capacity_error(sph):
     c = cases.tank_c1()
     say("capacity error")
