@@ -13,12 +13,16 @@ namespace sphk {
 
 // Cells of the exterior-integral quadrature: the cube [-2h, 2h]^3 cut into
 // 16^3 cells of edge h/4, cell (a, b, c) centred at (a + 1/2, b + 1/2, c + 1/2)
-// h/4 from the particle, a, b, c in [-8, 8).  Only cells with key
-// (2a+1)^2 + (2b+1)^2 + (2c+1)^2 = (distance / (h/8))^2 below 264 can lie
-// within 2h (256) plus a rounding margin; they are listed by ascending key
-// (ties by linear index), so the cells nearer than a distance form a prefix.
-// Entry: key << 12 | (a+8) << 8 | (b+8) << 4 | (c+8).
-constexpr int QK = 8, QN = 2 * QK, QKEY_MAX = 264, QMAX = 2400;
+// h/4 from the particle, a, b, c in [-8, 8).  They are visited by blocks of
+// 2 x 2 x 2 cells: block (A, B, C), A, B, C in [-4, 4), holds the cells
+// a in {2A, 2A + 1} (and likewise b, c), its centre at (2A + 1, 2B + 1, 2C + 1)
+// h/4, every cell centre within sqrt(3)/2 h/4 of it.  Only blocks with key
+// (2A+1)^2 + (2B+1)^2 + (2C+1)^2 = (distance / (h/4))^2 below 81 can hold a
+// cell within 2h (8 h/4) of the particle; they are listed by ascending key
+// (ties by linear index), so the blocks nearer than a distance form a prefix.
+// Entry: key << 12 | (A+4) << 8 | (B+4) << 4 | (C+4).
+constexpr int QK = 8, QKEY_MAX = 81, QMAX = 512;
+constexpr double QHALFDIAG = 0.87;   // >= sqrt(3)/2: cell centre to block centre, in units of h/4
 __constant__ uint32_t qcells[QMAX];
 
 static int qcells_count = 0;
@@ -35,13 +39,14 @@ static hipError_t qcells_init(int* count) {
   if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
   if (!qcells_loaded[dev]) {
     std::vector<uint64_t> v;
-    for (int a = -QK; a < QK; ++a)
-      for (int b = -QK; b < QK; ++b)
-        for (int c = -QK; c < QK; ++c) {
+    const int BK = QK / 2;
+    for (int a = -BK; a < BK; ++a)
+      for (int b = -BK; b < BK; ++b)
+        for (int c = -BK; c < BK; ++c) {
           const uint32_t key = (uint32_t)((2 * a + 1) * (2 * a + 1) + (2 * b + 1) * (2 * b + 1) + (2 * c + 1) * (2 * c + 1));
           if (key >= (uint32_t)QKEY_MAX) continue;
-          const uint32_t lin = (uint32_t)(((a + QK) * QN + (b + QK)) * QN + (c + QK));
-          const uint32_t ent = key << 12 | (uint32_t)(a + QK) << 8 | (uint32_t)(b + QK) << 4 | (uint32_t)(c + QK);
+          const uint32_t lin = (uint32_t)(((a + BK) * QK + (b + BK)) * QK + (c + BK));
+          const uint32_t ent = key << 12 | (uint32_t)(a + BK) << 8 | (uint32_t)(b + BK) << 4 | (uint32_t)(c + BK);
           v.push_back((uint64_t)key << 44 | (uint64_t)lin << 32 | ent);
         }
     std::sort(v.begin(), v.end());
@@ -58,6 +63,13 @@ static hipError_t qcells_init(int* count) {
 }
 
 // Every level-set evaluation is FP64.
+
+// LDS written by some lanes of a wavefront, then read by others
+__device__ __forceinline__ void relax_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // signed distance of the extrusion along y (|y| <= half) of a cross-section
 // with signed distance d2
@@ -173,11 +185,13 @@ __global__ __launch_bounds__(BLOCK) void k_relax_force(const SlotDesc* table, La
   typedef typename P::Real4 Real4;
   __shared__ double red[BLOCK / WAVE];
   __shared__ d2v E[2 * MAX_TEETH];
+  __shared__ uint32_t blk_all[BLOCK / WAVE][WAVE];   // active quadrature blocks of a wavefront
   SLOT_PROLOGUE(DOM_FLUID);
   ls_flank_table(g, E);
   __syncthreads();
   const int i = lb * BLOCK + threadIdx.x;
   const int lane = threadIdx.x & (WAVE - 1);
+  uint32_t* blk = blk_all[threadIdx.x / WAVE];
   const bool live_i = i < S.nf;
   const double h = S.h, del = 0.25 * h, vol = S.vol_w, p0 = 1.0;
   double sx = 0.0, sy = 0.0, sz = 0.0;
@@ -221,12 +235,13 @@ __global__ __launch_bounds__(BLOCK) void k_relax_force(const SlotDesc* table, La
     const double qphi = __shfl(phx, src, WAVE);
     // phi is a distance (1-Lipschitz): phi(y) <= phi(x) + |x - y|, so a cell
     // with phi(x) + |x - y| <= -edge/2 lies wholly inside.  Skip the prefix of
-    // cells surely that near (key below (2 lim / edge)^2, less a margin); the
-    // test below catches the rest.
+    // blocks whose every cell is surely that near (block distance plus its
+    // half-diagonal below lim, less a margin); the tests below catch the rest.
     int s0 = 0;
     const double lim = -0.5 * del - qphi;
-    if (lim > 0.0) {
-      const double kl = 4.0 * (lim / del) * (lim / del) * (1.0 - 1e-9);
+    if (lim > QHALFDIAG * del) {
+      const double rb = lim / del - QHALFDIAG;
+      const double kl = rb * rb * (1.0 - 1e-9);
       int lo = 0, hi = nq;                       // first entry with key >= kl
       while (lo < hi) {
         const int mid = (lo + hi) >> 1;
@@ -236,24 +251,62 @@ __global__ __launch_bounds__(BLOCK) void k_relax_force(const SlotDesc* table, La
       s0 = lo;
     }
     double ax = 0.0, ay = 0.0, az = 0.0;
-    for (int q = s0 + lane; q < nq; q += WAVE) {
-      const uint32_t ent = qcells[q];
-      const int a = (int)((ent >> 8) & 15u) - QK, b = (int)((ent >> 4) & 15u) - QK, c = (int)(ent & 15u) - QK;
-      const double yx = qx + del * ((double)a + 0.5), yy = qy + del * ((double)b + 0.5),
-                   yz = qz + del * ((double)c + 0.5);
-      const double ex = qx - yx, ey = qy - yy, ez = qz - yz;
-      const double r2 = (ex * ex + ey * ey) + ez * ez;
-      if (!(r2 < cut * cut)) continue;
-      const double rr = sqrt(r2);
-      if (qphi + rr <= -0.5 * del) continue;
-      const double f = fmin(0.5 + ls_phi(g, E, yx, yy, yz) * inv_del, 1.0);
-      if (!(f > 0.0)) continue;
-      const double t = 1.0 - 0.5 * rr * inv_h;
-      const double F = S.kF * t * t * t;
-      const double w = F * (f * dv);
-      ax += w * ex;
-      ay += w * ey;
-      az += w * ez;
+    for (int s = s0; s < nq; s += WAVE) {
+      // one block per lane: its centre's phi bounds all its cells, so a block
+      // with phi(centre) + half-diagonal <= -edge/2 has no cell outside, and
+      // one with phi(centre) - half-diagonal >= edge/2 has every cell wholly
+      // outside (fraction 1, no evaluation of its cells)
+      const int q = s + lane;
+      uint32_t ent = 0;
+      bool act = false, full = false;
+      if (q < nq) {
+        ent = qcells[q];
+        const int A = (int)((ent >> 8) & 15u) - QK / 2, B = (int)((ent >> 4) & 15u) - QK / 2,
+                  C = (int)(ent & 15u) - QK / 2;
+        const double cx = qx + del * (double)(2 * A + 1), cy = qy + del * (double)(2 * B + 1),
+                     cz = qz + del * (double)(2 * C + 1);
+        const double ex = qx - cx, ey = qy - cy, ez = qz - cz;
+        const double rc = sqrt((ex * ex + ey * ey) + ez * ez);
+        if (rc - QHALFDIAG * del < cut && qphi + rc + QHALFDIAG * del > -0.5 * del) {
+          const double pc = ls_phi(g, E, cx, cy, cz);
+          full = pc - QHALFDIAG * del >= 0.5 * del;
+          act = !full && pc + QHALFDIAG * del > -0.5 * del;
+        }
+      }
+      const uint64_t mm = __ballot(act), mf = __ballot(full);
+      if (!(mm | mf)) continue;
+      // the blocks' codes compacted in lane order, those that need their
+      // cells' level set first, then their cells spread over the lanes
+      const int nm = __popcll(mm);
+      if (act) blk[__builtin_amdgcn_mbcnt_hi((uint32_t)(mm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mm, 0u))] = ent;
+      if (full) blk[nm + __builtin_amdgcn_mbcnt_hi((uint32_t)(mf >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mf, 0u))] = ent;
+      relax_lds_sync();
+      const int ncm = 8 * nm, ncell = 8 * (nm + __popcll(mf));
+      for (int k = lane; k < ncell; k += WAVE) {
+        const uint32_t eb = blk[k >> 3];
+        const int a = 2 * ((int)((eb >> 8) & 15u) - QK / 2) + (k & 1);
+        const int b = 2 * ((int)((eb >> 4) & 15u) - QK / 2) + ((k >> 1) & 1);
+        const int c = 2 * ((int)(eb & 15u) - QK / 2) + ((k >> 2) & 1);
+        const double yx = qx + del * ((double)a + 0.5), yy = qy + del * ((double)b + 0.5),
+                     yz = qz + del * ((double)c + 0.5);
+        const double ex = qx - yx, ey = qy - yy, ez = qz - yz;
+        const double r2 = (ex * ex + ey * ey) + ez * ez;
+        if (!(r2 < cut * cut)) continue;
+        const double rr = sqrt(r2);
+        if (qphi + rr <= -0.5 * del) continue;
+        double f = 1.0;
+        if (k < ncm) {
+          f = fmin(0.5 + ls_phi(g, E, yx, yy, yz) * inv_del, 1.0);
+          if (!(f > 0.0)) continue;
+        }
+        const double t = 1.0 - 0.5 * rr * inv_h;
+        const double F = S.kF * t * t * t;
+        const double w = F * (f * dv);
+        ax += w * ex;
+        ay += w * ey;
+        az += w * ez;
+      }
+      relax_lds_sync();
     }
     ax = wave_sum(ax);
     ay = wave_sum(ay);
