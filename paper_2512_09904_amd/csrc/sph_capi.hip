@@ -1079,31 +1079,23 @@ extern "C" int sph_contact_factor(sph_solver* s, double* zeta, double* body_mean
   LCHK(read_ctl(P, S, &c, true));
   if (c.flags) return fail(flag_code(c.flags), "contact factor build faulted");
   const size_t ns = (size_t)S.plan.ns;
-  std::vector<double> z(ns);
-  std::vector<uint32_t> sid(ns);
-  std::vector<int32_t> body(ns);
-  if (ns) {
-    LCHK(d2h(z.data(), S.d.zeta, ns * 8));
-    LCHK(d2h(sid.data(), S.d.sid, ns * 4));
-    LCHK(d2h(body.data(), S.d.body, ns * 4));
+  // the kernel wrote the values in the original order: one read-back
+  std::vector<double> tmp;
+  double* z = zeta;
+  if (!z && body_mean) {
+    tmp.resize(ns);
+    z = tmp.data();
   }
-  if (zeta)
-    for (size_t k = 0; k < ns; ++k) zeta[sid[k]] = z[k];
+  if (z && ns) LCHK(d2h(z, S.d.zeta, ns * 8));
   if (body_mean) {
     // mean per body over its particles in their original order, compensated
-    std::vector<double> zo(ns);
-    std::vector<int32_t> bo(ns);
-    for (size_t k = 0; k < ns; ++k) {
-      zo[sid[k]] = z[k];
-      bo[sid[k]] = body[k];
-    }
     for (int b = 0; b < S.nbody; ++b) {
       double sum = 0.0, comp = 0.0;
       int64_t cnt = 0;
       for (size_t k = 0; k < ns; ++k) {
-        if (bo[k] != b) continue;
-        const double t = sum + zo[k];
-        comp += std::fabs(sum) >= std::fabs(zo[k]) ? (sum - t) + zo[k] : (zo[k] - t) + sum;
+        if (s->body[k] != b) continue;
+        const double t = sum + z[k];
+        comp += std::fabs(sum) >= std::fabs(z[k]) ? (sum - t) + z[k] : (z[k] - t) + sum;
         sum = t;
         ++cnt;
       }

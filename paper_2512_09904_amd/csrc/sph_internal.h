@@ -96,7 +96,7 @@ struct SlotDesc {
   uint32_t *sidb;
   void *xwb, *nwb, *vwb, *levb;
   uint32_t *scell, *sperm;
-  double *zeta;         // contact factor per sorted solid particle
+  double *zeta;         // contact factor per solid particle, original order
   uint64_t *skey;
   // cells
   uint32_t *rank, *cnt_f, *cnt_s, *start_f, *start_s, *bsum_f, *bsum_s;

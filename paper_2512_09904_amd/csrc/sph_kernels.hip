@@ -836,7 +836,7 @@ __global__ __launch_bounds__(BLOCK) void k_contact(const SlotDesc* table, Launch
           }
         }
       }
-  S.zeta[w] = z / S.zref;
+  S.zeta[S.sid[w]] = z / S.zref;   // in the caller's original order (sid is a permutation)
 }
 
 // ---------------------------------------------------------------------------
