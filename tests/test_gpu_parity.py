@@ -549,6 +549,27 @@ def test_contact_factor_matches_oracle(sph, ora, precision, tol):
     s.close()
 
 
+def test_contact_factor_optional_outputs(sph):
+    """Either output of sph_contact_factor may be NULL; the other is then the
+    same bit for bit (values in the case's solid order, means per body)."""
+    c = cases.tank_c1(seed=6)
+    say("contact factor optional outputs", c.ns)
+    s = sph.Solver(c)
+    s.step(5)
+    z, mean = s.contact_factor()
+    z1 = np.zeros(c.ns)
+    m1 = np.zeros(len(c.bodies))
+    L = sph.lib()
+    assert L.sph_contact_factor(s.h, sph._p(z1), None) == 0
+    assert L.sph_contact_factor(s.h, None, sph._p(m1)) == 0
+    assert L.sph_contact_factor(s.h, None, None) == 0
+    s.close()
+    assert np.array_equal(z1, z)
+    assert np.array_equal(m1, mean)
+    for b in range(len(c.bodies)):
+        assert mean[b] == pytest.approx(float(np.mean(z[c.body == b])), rel=1e-14)
+
+
 def test_contact_factor_leaves_the_solve_unchanged(sph):
     """The contact factor's extra sort and build reproduce the next step's
     own exactly: stepping with a contact-factor call in between is bitwise
