@@ -22,6 +22,11 @@ namespace sphk {
 // (ties by linear index), so the blocks nearer than a distance form a prefix.
 // Entry: key << 12 | (A+4) << 8 | (B+4) << 4 | (C+4).
 constexpr int QK = 8, QKEY_MAX = 81, QMAX = 512;
+// workgroups per block of particles in the force kernel, and the first row
+// of the per-block partials that holds their maxima (rows RELAX_ROW to
+// RELAX_ROW + RQ - 1, free between advection steps)
+constexpr int RQ = 4, RELAX_ROW = NGLOB + 1 - RQ;
+static_assert(RQ == BLOCK / WAVE && RELAX_ROW >= 0, "one integrating wavefront per residue of the lane");
 constexpr double QHALFDIAG = 0.87;   // >= sqrt(3)/2: cell centre to block centre, in units of h/4
 __constant__ uint32_t qcells[QMAX];
 
@@ -186,12 +191,24 @@ __global__ __launch_bounds__(BLOCK) void k_relax_force(const SlotDesc* table, La
   __shared__ double red[BLOCK / WAVE];
   __shared__ d2v E[2 * MAX_TEETH];
   __shared__ uint32_t blk_all[BLOCK / WAVE][WAVE];   // active quadrature blocks of a wavefront
-  SLOT_PROLOGUE(DOM_FLUID);
+  // RQ workgroups per block of BLOCK particles: workgroup `quarter` takes its
+  // WAVE particles, every wavefront forms their neighbour sums and wavefront
+  // w integrates the exterior of the particles with lane % RQ == w (so the
+  // serial per-particle work is spread over RQ times more wavefronts)
+  const int vb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+  const int quarter = vb % RQ, vblk = vb / RQ;
+  int sk = 0;
+  for (int s = 1; s < tab.n; ++s)
+    if (vblk >= tab.blk0[DOM_FLUID][s]) sk = s;
+  const int lb = vblk - tab.blk0[DOM_FLUID][sk];
+  const SlotDesc& S = table[tab.slot[sk]];
+  if (!live(S)) return;
   ls_flank_table(g, E);
   __syncthreads();
-  const int i = lb * BLOCK + threadIdx.x;
-  const int lane = threadIdx.x & (WAVE - 1);
-  uint32_t* blk = blk_all[threadIdx.x / WAVE];
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+  const int i = lb * BLOCK + quarter * WAVE + lane;
+  const bool mine = (lane % RQ) == wv;
+  uint32_t* blk = blk_all[wv];
   const bool live_i = i < S.nf;
   const double h = S.h, del = 0.25 * h, vol = S.vol_w, p0 = 1.0;
   double sx = 0.0, sy = 0.0, sz = 0.0;
@@ -226,7 +243,7 @@ __global__ __launch_bounds__(BLOCK) void k_relax_force(const SlotDesc* table, La
   }
   // exterior integral, one particle at a time across the wavefront
   double Ix = 0.0, Iy = 0.0, Iz = 0.0;
-  uint64_t todo = __ballot(need);
+  uint64_t todo = __ballot(need && mine);
   const double dv = del * del * del, cut = 2.0 * h, inv_h = 1.0 / h, inv_del = 1.0 / del;
   while (todo) {
     const int src = __builtin_ctzll(todo);
@@ -318,7 +335,7 @@ __global__ __launch_bounds__(BLOCK) void k_relax_force(const SlotDesc* table, La
     }
   }
   double amag = 0.0;
-  if (live_i) {
+  if (live_i && mine) {
     const double c = -(2.0 / S.mass) * vol * p0;
     Real4 a;
     a.x = (Real)(c * (sx + Ix));
@@ -334,7 +351,8 @@ __global__ __launch_bounds__(BLOCK) void k_relax_force(const SlotDesc* table, La
   if (lane == 0) red[threadIdx.x / WAVE] = amag;
   __syncthreads();
   if (threadIdx.x == 0)
-    S.glob_part[(size_t)4 * S.nblk[DOM_FLUID] + lb] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    S.glob_part[(size_t)(RELAX_ROW + quarter) * S.nblk[DOM_FLUID] + lb] =
+        fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
 // K: max |F_p| over the blocks, the step of eq. 8, dt = 0.25 sqrt(h / max|F_p|)
@@ -343,9 +361,9 @@ __global__ __launch_bounds__(FINAL_BLOCK) void k_relax_max(const SlotDesc* table
   SLOT_PROLOGUE(DOM_SLOT);
   (void)lb;
   const int nblk = S.nblk[DOM_FLUID];
-  const GLB double* q = gpc<double>(S.glob_part + (size_t)4 * nblk);
+  const GLB double* q = gpc<double>(S.glob_part + (size_t)RELAX_ROW * nblk);
   double m = 0.0;
-  for (int k = threadIdx.x; k < nblk; k += FINAL_BLOCK) m = fmax(m, q[k]);
+  for (int k = threadIdx.x; k < RQ * nblk; k += FINAL_BLOCK) m = fmax(m, q[k]);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, WAVE));
   if (threadIdx.x % WAVE == 0) red[threadIdx.x / WAVE] = m;
@@ -417,6 +435,7 @@ hipError_t launch_relax(int prec, int kid, int iter, const SlotDesc* T, const La
   }
   if (kid != SPH_K_RELAX_FORCE && kid != SPH_K_RELAX_MOVE) return hipErrorInvalidValue;
   const bool force = kid == SPH_K_RELAX_FORCE;
+  const dim3 gq(RQ * nblk);
   int nq = 0;
   if (force) {
     const hipError_t e = qcells_init(&nq);
@@ -424,15 +443,15 @@ hipError_t launch_relax(int prec, int kid, int iter, const SlotDesc* T, const La
   }
   switch (prec) {
     case SPH_PREC_MIXED:
-      if (force) hipLaunchKernelGGL(k_relax_force<PMixed>, gr, b, 0, st, T, L, g, nq);
+      if (force) hipLaunchKernelGGL(k_relax_force<PMixed>, gq, b, 0, st, T, L, g, nq);
       else hipLaunchKernelGGL(k_relax_move<PMixed>, gr, b, 0, st, T, L, g);
       break;
     case SPH_PREC_FP64:
-      if (force) hipLaunchKernelGGL(k_relax_force<PF64>, gr, b, 0, st, T, L, g, nq);
+      if (force) hipLaunchKernelGGL(k_relax_force<PF64>, gq, b, 0, st, T, L, g, nq);
       else hipLaunchKernelGGL(k_relax_move<PF64>, gr, b, 0, st, T, L, g);
       break;
     case SPH_PREC_FP32:
-      if (force) hipLaunchKernelGGL(k_relax_force<PF32>, gr, b, 0, st, T, L, g, nq);
+      if (force) hipLaunchKernelGGL(k_relax_force<PF32>, gq, b, 0, st, T, L, g, nq);
       else hipLaunchKernelGGL(k_relax_move<PF32>, gr, b, 0, st, T, L, g);
       break;
     default: return hipErrorInvalidValue;
