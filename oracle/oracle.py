@@ -34,7 +34,7 @@ class Params(C.Structure):
                 ("gravity", C.c_double * 3), ("grid_lo", C.c_double * 3), ("grid_hi", C.c_double * 3),
                 ("cfl_ad", C.c_double), ("cfl_ac", C.c_double), ("fixed_dt_ad", C.c_double),
                 ("fixed_nac", C.c_int32), ("nac_max", C.c_int32), ("free_surface", C.c_int32),
-                ("eq13_printed", C.c_int32), ("viscous_heating", C.c_int32), ("pad", C.c_int32)]
+                ("eq13_printed", C.c_int32), ("viscous_heating", C.c_int32), ("wall_visc", C.c_int32)]
 
 
 class BodyS(C.Structure):
@@ -104,6 +104,7 @@ def make_params(params: dict, **over) -> Params:
     P.free_surface = int(d.get("free_surface", 1))
     P.eq13_printed = int(d.get("eq13_printed", 0))
     P.viscous_heating = int(d.get("viscous_heating", 0))
+    P.wall_visc = int(d.get("wall_visc", 0))   # 0: Shepard no-slip dummy velocity
     return P
 
 
@@ -252,6 +253,16 @@ def viscous(params, nbr: Nbr, v, rho, mass, vs=None, bodies=(), body=None):
     return a, S, bF[:nb], bT[:nb]
 
 
+def wall_dummy_velocity(params, nbr: Nbr, v, vs):
+    """Dummy velocity of every solid particle in the wall viscous force (eq. 18)
+    under params["wall_visc"], and its Shepard weight sum."""
+    ns = len(nbr.xs)
+    vd = np.zeros((ns, 3))
+    sw = np.zeros(ns)
+    lib().ora_wall_dummy_velocity(C.byref(nbr.P), nbr.h, _p(_c3(v)), _p(_c3(vs)), _p(vd), _p(sw))
+    return vd, sw
+
+
 def heat(params, nbr: Nbr, rho, mass, k, cp, T, bodies=(), body=None):
     nb, B = _bodies_arg(bodies)
     n = len(nbr.xf)
@@ -337,6 +348,16 @@ def body_pose(bodies, x0, n0, body, t):
     lib().ora_body_pose(C.c_int32(nb), B, C.c_int64(ns), _p(x0), _p(n0),
                         _p(np.ascontiguousarray(body, dtype=np.int32)), C.c_double(t), _p(xs), _p(nsv), _p(vs))
     return xs, nsv, vs
+
+
+def totals(params, v, rho, T, cp=None):
+    """Report totals of a fluid state: mass, kinetic energy, thermal energy,
+    mass proxy sum rho dp^3, max |v| (compensated sums)."""
+    out = np.zeros(5)
+    f64 = lambda a_: np.ascontiguousarray(a_, dtype=np.float64)
+    lib().ora_totals_cp(C.byref(make_params(params)), C.c_int64(len(rho)), _p(_c3(v)), _p(f64(rho)), _p(f64(T)),
+                        _p(f64(cp)) if cp is not None else None, _p(out))
+    return dict(mass=out[0], kinetic=out[1], thermal=out[2], mass_proxy=out[3], vmax=out[4])
 
 
 def timestep(params, bodies, x0, body, v):

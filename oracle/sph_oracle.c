@@ -20,6 +20,10 @@
  *  - integrator inside the dual-criteria step: position Verlet with
  *    half-step density updates; pair geometry, body pose, viscous and heat
  *    rates frozen for the advection step; temperature by explicit Euler;
+ *  - wall viscous force (eq. 18): the dummy particles carry the no-slip
+ *    velocity of the generalized wall the paper cites for them,
+ *    2 u_w - (Shepard mean of the fluid velocity around w); the literal
+ *    rigid velocity is a switch (ora_params.wall_visc);
  *  - torque on a body: sum over wall pairs of (x_w - c_B) x (-f_iw);
  *  - viscous dissipation (eq. 23, optional): S from the SPH velocity
  *    gradient over fluid and wall neighbours;
@@ -27,10 +31,11 @@
  *  - relaxation (Section 2.2): exterior kernel-gradient integral on cells of
  *    edge h/4 with a linear outside fraction; confinement to phi <= -dp/2.
  *
- * Parity unpinned: the magnitude of the wall viscous torque (literal eq. 18,
- * wall particles at the body's velocity) has no closed form to pin to at
- * the resolutions used; its sign and the direction of its convergence with
- * resolution are pinned (rotating sphere), its magnitude is not.
+ * The magnitude of the wall viscous torque is pinned to the Stokes torque
+ * between concentric spheres on the wall that does not turn; on a turning
+ * wall the pairwise reduction adds the torque it reads for rigid co-rotation
+ * of fluid and body (eq. 10 and 18 exchange non-central viscous forces), and
+ * that identity is pinned as well.
  */
 #include "sph_oracle.h"
 
@@ -453,6 +458,40 @@ static void visc_pair(double Vi, double Vj, double eta, double F, const double* 
   f[2] = c * (vi[2] - vj[2]);
 }
 
+/* Shepard mean of the fluid velocity around every solid particle w,
+ * v~_w = sum_j v_j W_wj / sum_j W_wj over the fluid j within 2h (the frozen
+ * build geometry), and the no-slip dummy velocity 2 u_w - v~_w of the
+ * generalized wall; a solid particle with no fluid neighbour keeps u_w.  The
+ * sums run over the fluid rows in fluid-index order, so the result does not
+ * depend on the thread count. */
+void ora_wall_dummy_velocity(const ora_params* P, const ora_nbr* nb, const double* v, const double* vs,
+                             double* vd, double* sumW_s) {
+  if (P->wall_visc != ORA_WALL_VISC_SHEPARD) {
+    for (int64_t w = 0; w < nb->ns; ++w) {
+      for (int k = 0; k < 3; ++k) vd[3 * w + k] = vs[3 * w + k];
+      if (sumW_s) sumW_s[w] = 0.0;
+    }
+    return;
+  }
+  double* acc = (double*)calloc((size_t)(nb->ns > 0 ? nb->ns : 1) * 4, sizeof(double));
+  if (!acc) abort();
+  pgeo g;
+  for (int64_t i = 0; i < nb->nf; ++i)
+    for (int64_t p = nb->off_s[i]; p < nb->off_s[i + 1]; ++p) {
+      int64_t w = nb->idx_s[p];
+      pair_geom(nb->xb + 3 * i, nb->xsb + 3 * w, nb->h, &g);
+      for (int k = 0; k < 3; ++k) acc[4 * w + k] += v[3 * i + k] * g.W;
+      acc[4 * w + 3] += g.W;
+    }
+  for (int64_t w = 0; w < nb->ns; ++w) {
+    for (int k = 0; k < 3; ++k)
+      vd[3 * w + k] = acc[4 * w + 3] > 0.0 ? 2.0 * vs[3 * w + k] - acc[4 * w + k] / acc[4 * w + 3]
+                                           : vs[3 * w + k];
+    if (sumW_s) sumW_s[w] = acc[4 * w + 3];
+  }
+  free(acc);
+}
+
 void ora_viscous(const ora_params* P, const ora_nbr* nb, int32_t nbody, const ora_body* B,
                  const int32_t* body, const double* v, const double* rho, const double* mass,
                  const double* vs, double* a, double* S, double* bforce, double* btorque) {
@@ -460,6 +499,10 @@ void ora_viscous(const ora_params* P, const ora_nbr* nb, int32_t nbody, const or
   double Vw = P->dp * P->dp * P->dp;
   bacc acc;
   int use_acc = (bforce || btorque) && nbody > 0 && bacc_init(&acc, nb->nf, nbody, 6) == 0;
+  /* dummy-particle velocity of eq. 18 (reading switch, see ora_params) */
+  double* vd = (double*)malloc(sizeof(double) * 3 * (size_t)(nb->ns > 0 ? nb->ns : 1));
+  if (!vd) abort();
+  ora_wall_dummy_velocity(P, nb, v, vs, vd, NULL);
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < nb->nf; ++i) {
     double Vi = mass[i] / rho[i];
@@ -476,7 +519,13 @@ void ora_viscous(const ora_params* P, const ora_nbr* nb, int32_t nbody, const or
     for (int64_t p = nb->off_s[i]; p < nb->off_s[i + 1]; ++p) {
       int64_t w = nb->idx_s[p];
       pair_geom(nb->xb + 3 * i, nb->xsb + 3 * w, nb->h, &g);
-      visc_pair(Vi, Vw, eta, g.F, v + 3 * i, vs + 3 * w, f);
+      if (P->wall_visc == ORA_WALL_VISC_PAIR) {
+        /* v_i - (2 u_w - v_i) = 2 (v_i - u_w) */
+        visc_pair(Vi, Vw, eta, g.F, v + 3 * i, vs + 3 * w, f);
+        f[0] *= 2.0; f[1] *= 2.0; f[2] *= 2.0;
+      } else {
+        visc_pair(Vi, Vw, eta, g.F, v + 3 * i, vd + 3 * w, f);
+      }
       sum[0] += f[0]; sum[1] += f[1]; sum[2] += f[2];
       s_abs += sqrt(dot3(f, f));
       if (use_acc) {
@@ -491,6 +540,7 @@ void ora_viscous(const ora_params* P, const ora_nbr* nb, int32_t nbody, const or
     for (int k = 0; k < 3; ++k) a[3 * i + k] = sum[k] / mass[i];
     if (S) S[i] = s_abs / mass[i];
   }
+  free(vd);
   if (use_acc) {
     double* tmp = (double*)malloc(sizeof(double) * 6 * (size_t)nbody);
     bacc_reduce(&acc, tmp);

@@ -31,8 +31,20 @@ typedef struct {
   int32_t free_surface;    /* 1: eq. 14 re-initialisation, 0: eq. 15 */
   int32_t eq13_printed;    /* 1: take eq. 13's printed sign (reading study only) */
   int32_t viscous_heating; /* 1: add the dissipation Phi/(rho cp) of eq. 23 to dT/dt */
-  int32_t pad;
+  int32_t wall_visc;       /* velocity of the dummy particles in eq. 18 (ORA_WALL_VISC_*) */
 } ora_params;
+
+/* Dummy-particle velocity v_w in the wall viscous force of eq. 18 (Section
+ * 2.5 takes its dummy particles from the generalized wall of Adami et al.
+ * 2012, whose no-slip condition extrapolates the fluid velocity into the wall).
+ *  SHEPARD (default): v_w = 2 u_w - v~_w, with u_w the body's rigid velocity
+ *           at the wall particle and v~_w the kernel-weighted (Shepard) mean
+ *           velocity of the fluid within 2h of it; u_w when none is;
+ *  RIGID:   v_w = u_w, the body's own velocity (eq. 18 read literally);
+ *  PAIR:    v_w = 2 u_w - v_i with the pair's own fluid velocity, i.e.
+ *           (v_i - v_w) = 2 (v_i - u_w) (reading study only: unstable at the
+ *           viscous step bound of eq. 25). */
+enum { ORA_WALL_VISC_SHEPARD = 0, ORA_WALL_VISC_RIGID = 1, ORA_WALL_VISC_PAIR = 2 };
 
 typedef struct { double center[3], axis[3], omega, T, k; } ora_body;
 
@@ -95,6 +107,12 @@ void ora_sum_w(const ora_params* P, const ora_nbr* nb, double* sumW);
    within 2h of V_j W_wj (V_j = m / rho_j) over ref; zeta[ns]. */
 int ora_contact_factor(const ora_params* P, int64_t nf, const double* xf, const double* rho, int64_t ns,
                        const double* xs, double ref, double* zeta);
+/* Dummy velocity of every solid particle (ns x 3) under P->wall_visc for the
+   fluid velocities v (nf x 3) and the rigid solid velocities vs; also the
+   Shepard weight sum_j W_wj (sumW_s, nullable).  PAIR has no per-particle
+   value and returns vs. */
+void ora_wall_dummy_velocity(const ora_params* P, const ora_nbr* nb, const double* v, const double* vs,
+                             double* vd, double* sumW_s);
 void ora_viscous(const ora_params* P, const ora_nbr* nb, int32_t nbody, const ora_body* B,
                  const int32_t* body, const double* v, const double* rho, const double* mass,
                  const double* vs, double* a, double* S, double* bforce, double* btorque);

@@ -680,3 +680,74 @@ def test_step_heat_balance_two_materials(ora):
     iface_r = core & ~left & (c.xf[:, 0] < 0.02 + 3e-3)
     assert iface_l.sum() > 20 and iface_r.sum() > 20
     assert np.all(s.T[iface_l] < c.Tf[iface_l]) and np.all(s.T[iface_r] > c.Tf[iface_r])
+
+
+# --------------------------------------------------------------------------
+# report totals (Section 4 observables): closed forms on a lattice block
+# --------------------------------------------------------------------------
+
+def test_totals_closed_forms(ora):
+    """Mass N m, kinetic energy 1/2 M |v|^2 for a uniform translation and
+    1/2 I omega^2 for a rigid rotation (I of an n^3 lattice block about its
+    central axis: m dp^2 n^3 (n^2 - 1) / 6), thermal energy N m cp T, mass
+    proxy N rho dp^3, and max |v|."""
+    n, dp, rho0 = 12, 1e-3, 870.0
+    p = cases.default_params(dp, rho0, 10.0, 1e-4, 0.13, 2000.0, (0, 0, 0), (n * dp,) * 3)
+    x = cases.lattice_block(n, dp)
+    N, m = n ** 3, rho0 * dp ** 3
+    rho = np.full(N, 871.5)
+    T = np.full(N, 313.15)
+    v0 = np.array([0.3, -0.2, 0.6])
+    t = ora.totals(p, np.tile(v0, (N, 1)), rho, T)
+    assert t["mass"] == pytest.approx(N * m, rel=1e-15)
+    assert t["kinetic"] == pytest.approx(0.5 * N * m * (v0 @ v0), rel=1e-14)
+    assert t["thermal"] == pytest.approx(N * m * 2000.0 * 313.15, rel=1e-14)
+    assert t["mass_proxy"] == pytest.approx(N * 871.5 * dp ** 3, rel=1e-14)
+    assert t["vmax"] == pytest.approx(np.linalg.norm(v0), rel=1e-15)
+    om = 7.0
+    c = np.full(3, 0.5 * n * dp)
+    v = np.cross([0.0, 0.0, om], x - c)
+    t = ora.totals(p, v, rho, T)
+    I = m * dp ** 2 * n ** 3 * (n ** 2 - 1) / 6.0
+    assert t["kinetic"] == pytest.approx(0.5 * I * om ** 2, rel=1e-13)
+    assert t["vmax"] == pytest.approx(om * math.sqrt(2.0) * (n - 1) / 2 * dp, rel=1e-14)
+    # two materials: thermal energy sums m cp_i T_i
+    cp = np.where(np.arange(N) % 2 == 0, 2000.0, 1500.0)
+    t = ora.totals(p, v, rho, T, cp=cp)
+    assert t["thermal"] == pytest.approx(m * 313.15 * (N // 2) * 3500.0, rel=1e-14)
+
+
+def test_wall_dummy_velocity_shepard(ora):
+    """Generalized-wall dummy velocity of eq. 18 (Section 2.5): for a linear
+    fluid field v = A x + b the Shepard mean around a wall particle is exactly
+    A x~ + b, x~ the kernel-weighted centroid of its fluid neighbours (kernel
+    written out here from its closed form), so v_w = 2 u_w - (A x~ + b); a
+    uniform field gives 2 u_w - b; a solid particle out of reach keeps u_w;
+    the literal reading keeps u_w everywhere."""
+    n, dp = 8, 1.0
+    p = lattice_params(1.3, n + 8, dp)
+    xf = cases.lattice_block(n, dp, jitter_amp=0.05, seed=3) + 4 * dp
+    xs = np.array([[4 * dp - 0.5 * dp, 7.3, 6.1], [4.2, 4 * dp - 1.5 * dp, 8.0],
+                   [9.0, 9.5, 4 * dp - 1.2 * dp], [0.6, 0.6, 0.6]])
+    us = np.array([[0.1, 0.0, 0.0], [0.0, -0.2, 0.3], [0.05, 0.05, 0.05], [1.0, 2.0, 3.0]])
+    A = np.array([[0.3, -0.1, 0.2], [0.05, 0.4, -0.3], [0.1, 0.2, -0.15]])
+    b = np.array([0.7, -0.4, 0.25])
+    v = xf @ A.T + b
+    nb = ora.Nbr(p, xf, xs)
+    vd, sw = ora.wall_dummy_velocity(p, nb, v, us)
+    h = 1.3 * dp
+    for w in range(4):
+        r = np.linalg.norm(xf - xs[w], axis=1)
+        q = r / h
+        W = np.where(q < 2, 21 / (16 * np.pi * h ** 3) * np.clip(1 - q / 2, 0, None) ** 4 * (1 + 2 * q), 0.0)
+        if W.sum() == 0:
+            assert w == 3 and sw[w] == 0.0
+            assert np.array_equal(vd[w], us[w])
+            continue
+        xt = (W[:, None] * xf).sum(0) / W.sum()
+        assert sw[w] == pytest.approx(W.sum(), rel=1e-13)
+        assert np.allclose(vd[w], 2 * us[w] - (A @ xt + b), rtol=0, atol=1e-13)
+    vd, _ = ora.wall_dummy_velocity(p, nb, np.tile(b, (len(xf), 1)), us)
+    assert np.allclose(vd[:3], 2 * us[:3] - b, rtol=0, atol=1e-14)
+    vd, _ = ora.wall_dummy_velocity(dict(p, wall_visc=1), ora.Nbr(dict(p, wall_visc=1), xf, xs), v, us)
+    assert np.array_equal(vd, us)
