@@ -61,6 +61,21 @@ typedef struct {
   void* user;
 } sph_allocator;
 
+/* Velocity v_w of the dummy particles in the wall viscous force of eq. 18.
+ * Section 2.5 takes its dummy particles from the generalized wall boundary of
+ * Adami, Hu and Adams (2012), whose no-slip condition extrapolates the fluid
+ * velocity into the wall:
+ *   SPH_WALL_VISC_SHEPARD (0, default): v_w = 2 u_w - v~_w, u_w the body's
+ *     rigid velocity at the wall particle, v~_w the kernel-weighted (Shepard)
+ *     mean velocity of the fluid particles within 2h of it (u_w when there
+ *     are none).  The sums are exact (fixed point, 2^-52 c0 per term), so
+ *     their order does not matter; a fluid speed above 4 c0 lies outside
+ *     their range and latches the capacity fault;
+ *   SPH_WALL_VISC_RIGID (1): v_w = u_w, eq. 18 read literally (the wall then
+ *     slips at the resolutions of the paper).
+ * The Riemann wall problem of eq. 16-19 always takes u_w. */
+enum { SPH_WALL_VISC_SHEPARD = 0, SPH_WALL_VISC_RIGID = 1 };
+
 /* fluid materials of one solve (thermal properties of eq. 22) */
 #define SPH_MAX_MATERIALS 8
 
@@ -88,7 +103,8 @@ typedef struct {
   int32_t viscous_heating; /* 1: add the viscous dissipation Phi = 2 eta S:S of eq. 23 (S the strain
                               rate from the SPH velocity gradient over fluid and wall neighbours) to
                               dT/dt as Phi/(rho cp); 0: the paper's model, conduction only */
-  int32_t reserved;     /* must be 0 */
+  int32_t wall_visc;    /* velocity of the dummy particles in the wall viscous force (eq. 18, SPH_WALL_VISC_*);
+                           0: the no-slip dummy velocity of the generalized wall Section 2.5 cites */
   int32_t n_materials;  /* 0: one fluid material (k_f, cp_f); 1..SPH_MAX_MATERIALS: the table below,
                            indexed by the per-particle material of sph_set_fluid / sph_pool_admit
                            (eq. 22 with k_i, k_j, cp_i per particle; density and viscosity shared),
@@ -111,7 +127,9 @@ typedef struct {
   double t;             /* simulated time */
   int64_t step;         /* completed advection steps */
   int32_t n_ac;         /* acoustic sub-steps of the last step */
-  int32_t flags;        /* latched fault bits: 1 domain, 2 non-finite, 4 capacity */
+  int32_t flags;        /* latched fault bits: 1 domain, 2 non-finite, 4 capacity (a neighbour row
+                           overflowed, a fluid particle touched more than two bodies, or a fluid
+                           speed exceeded 4 c0) */
   double dt_ad, dt;     /* last advection step and sub-step */
   double vmax;          /* max |v| of the fluid at the end of the step */
   double mass;          /* sum of fluid masses */
@@ -245,7 +263,7 @@ enum {
   SPH_K_CLEAR = 0, SPH_K_POSE, SPH_K_FOLD, SPH_K_SCAN1, SPH_K_SCAN2, SPH_K_SCAN3, SPH_K_SCATTER,
   SPH_K_CELLSORT, SPH_K_REORDER, SPH_K_BUILD, SPH_K_DT, SPH_K_VISC_HEAT, SPH_K_HALF_A,
   SPH_K_MOMENTUM, SPH_K_CONTINUITY, SPH_K_END, SPH_K_FINAL, SPH_K_SUMW, SPH_K_CONTACT,
-  SPH_K_RELAX_FORCE, SPH_K_RELAX_MAX, SPH_K_RELAX_MOVE, SPH_K_COUNT
+  SPH_K_RELAX_FORCE, SPH_K_RELAX_MAX, SPH_K_RELAX_MOVE, SPH_K_WALLVEL, SPH_K_COUNT
 };
 
 /* dump selectors; arrays are in the device's cell-sorted order unless noted */
@@ -260,7 +278,8 @@ enum {
   SPH_DUMP_SOLID_OFFSET = 8,/* double [ns][4]: the same for the sorted solids */
   SPH_DUMP_FLUID_STATE = 9, /* double [nf][16]: anchor(3) drift(3) v(3) rho drho T a_visc(3) dTdt */
   SPH_DUMP_SOLID_STATE = 10,/* double [ns][13]: x(3) n(3) v(3) lever(3) body */
-  SPH_DUMP_SUMW = 11        /* double [nf]: kernel sum of the last build */
+  SPH_DUMP_SUMW = 11,       /* double [nf]: kernel sum of the last build */
+  SPH_DUMP_SOLID_DUMMY = 12 /* double [ns][4]: dummy velocity of eq. 18 (3), Shepard weight dp^3 sum W */
 };
 
 /* ---- serving: many solves stepped together -------------------------------- */

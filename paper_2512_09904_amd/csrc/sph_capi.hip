@@ -77,7 +77,9 @@ static int make_plan(const sph_params* p, int prec, int64_t nf, int64_t ns, Plan
     return fail(SPH_ERR_ARG, "particle counts out of range");
   if (p->fixed_dt_ad > 0 && p->fixed_nac < 1) return fail(SPH_ERR_ARG, "fixed_nac must be >= 1");
   if (p->viscous_heating != 0 && p->viscous_heating != 1) return fail(SPH_ERR_ARG, "viscous_heating must be 0 or 1");
-  if (p->reserved != 0 || p->reserved2 != 0) return fail(SPH_ERR_ARG, "reserved fields must be 0");
+  if (p->wall_visc != SPH_WALL_VISC_SHEPARD && p->wall_visc != SPH_WALL_VISC_RIGID)
+    return fail(SPH_ERR_ARG, "wall_visc must be SPH_WALL_VISC_SHEPARD or SPH_WALL_VISC_RIGID");
+  if (p->reserved2 != 0) return fail(SPH_ERR_ARG, "reserved2 must be 0");
   if (p->n_materials < 0 || p->n_materials > SPH_MAX_MATERIALS)
     return fail(SPH_ERR_ARG, "n_materials must be in [0, 8]");
   for (int m = 0; m < p->n_materials; ++m)
@@ -188,6 +190,8 @@ static size_t carve(const Plan& P, void* base, SlotDesc* d) {
   C.take(D.scell, ns * 4);
   C.take(D.sperm, ns * 4);
   C.take(D.zeta, ns * 8);
+  C.take(D.wacc, ns * 4 * 8);
+  C.takev(D.vd, 4 * ns * rs);
   C.take(D.skey, ns * 8);
   C.take(D.rank, nc * 4);
   C.take(D.cnt_f, nc * 4);
@@ -432,6 +436,7 @@ static int enqueue_sort_build(sph_pool* P, const LaunchTab& T) {
   LCHK(launch(P, T, SPH_K_REORDER, 1, 0));
   LCHK(launch(P, T, SPH_K_BUILD, 0, 0));
   LCHK(launch(P, T, SPH_K_SUMW, 0, 0));
+  LCHK(launch(P, T, SPH_K_WALLVEL, 1, 0));
   return SPH_OK;
 }
 
@@ -646,6 +651,7 @@ static int admit(sph_pool* P, const sph_params* p, int32_t nbody, const sph_body
   for (int a = 0; a < 3; ++a) D.dims[a] = pl.dims[a];
   D.free_surface = p->free_surface ? 1 : 0;
   D.diss = p->viscous_heating;
+  D.wall_rigid = p->wall_visc == SPH_WALL_VISC_RIGID ? 1 : 0;
   D.fixed_nac = p->fixed_nac;
   for (int d = 0; d < NDOM; ++d) D.nblk[d] = pl.nblk[d];
   D.rowlen_f = pl.rowlen_f;
@@ -1204,6 +1210,7 @@ static size_t dump_bytes(const SlotHost& S, int what) {
     case SPH_DUMP_FLUID_STATE: return nf * 16 * 8;
     case SPH_DUMP_SOLID_STATE: return ns * 13 * 8;
     case SPH_DUMP_SUMW: return nf * 8;
+    case SPH_DUMP_SOLID_DUMMY: return ns * 4 * 8;
     default: return 0;
   }
 }
@@ -1333,6 +1340,13 @@ extern "C" int sph_debug_dump(sph_solver* s, int32_t what, void* buf, size_t byt
       return SPH_OK;
     }
     case SPH_DUMP_SUMW: return d2h(buf, D.sumW, nf * 8);
+    case SPH_DUMP_SOLID_DUMMY: {
+      std::vector<char> r(4 * ns * rs);
+      LCHK(d2h(r.data(), D.vd, r.size()));
+      double* o = (double*)buf;
+      for (size_t k = 0; k < 4 * ns; ++k) o[k] = get_as_double(r.data(), k, rs);
+      return SPH_OK;
+    }
     default: return fail(SPH_ERR_ARG, "unknown dump selector");
   }
 }

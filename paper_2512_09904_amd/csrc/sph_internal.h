@@ -69,7 +69,8 @@ struct SlotDesc {
   double kW, kF;                       // W = kW (1-q/2)^4 (1+2q);  F = kF (1-q/2)^3
   double bc[NB][3], ba[NB][3], bom[NB], bT[NB], bk[NB], btip[NB];
   double mk[NMAT], mcp[NMAT];          // conductivity and specific heat per fluid material
-  int32_t nmat, pad1;                  // materials (1: every particle takes k_f, cp_f)
+  int32_t nmat;                        // materials (1: every particle takes k_f, cp_f)
+  int32_t wall_rigid;                  // eq. 18 with the rigid wall velocity (no Shepard extrapolation)
   SlotCtl* ctl;
   // fluid state (sorted order) and its gather buffers
   void *xa, *drift, *vr, *vrn, *drho, *T, *ah;
@@ -97,6 +98,10 @@ struct SlotDesc {
   void *xwb, *nwb, *vwb, *levb;
   uint32_t *scell, *sperm;
   double *zeta;         // contact factor per solid particle, original order
+  // Shepard sums around each sorted solid particle (fixed point, 2^-52 units):
+  // [4 w + k] = sum over its fluid neighbours of W dp^3 v_k / c0 (k < 3), W dp^3 (k = 3)
+  int64_t *wacc;
+  void *vd;             // dummy velocity of eq. 18 per sorted solid particle (vx, vy, vz, dp^3 sum W)
   uint64_t *skey;
   // cells
   uint32_t *rank, *cnt_f, *cnt_s, *start_f, *start_s, *bsum_f, *bsum_s;

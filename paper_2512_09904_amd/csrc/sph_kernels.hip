@@ -471,6 +471,10 @@ __global__ __launch_bounds__(BLOCK) void k_reorder(const SlotDesc* table, Launch
     gp<Real4>(S.lev)[k] = gpc<Real4>(S.levb)[s];
     S.body[k] = S.bodyb[s];
     S.sid[k] = S.sidb[s];
+    // the Shepard sums of eq. 18's dummy velocity start from zero each build
+    GLB u4* acc = gp<u4>(S.wacc + 4 * (size_t)k);
+    acc[0] = u4(0u);
+    acc[1] = u4(0u);
   }
 }
 
@@ -710,7 +714,21 @@ __global__ __launch_bounds__(BLOCK) void k_build(const SlotDesc* table, LaunchTa
 // perfect-lattice sum S0 (eq. 14 with a free surface, eq. 15 without).  Each
 // pair's d^2 is formed exactly as in the cutoff test; the rows are walked in
 // order (fluid, then solid) so the sum is reproducible.
+//
+// The same fluid-solid pairs also feed the Shepard sums of the wall's
+// no-slip dummy velocity (eq. 18 with the generalized wall of Section 2.5):
+// every pair adds W dp^3 v_i / c0 and W dp^3 to its solid particle's four
+// accumulators as fixed-point integers (units of 2^-52), so the sums are
+// exact and the same whatever order the atomics land in.  |v_i| <= 4 c0 and
+// at most ~1200 fluid particles within 2h keep them inside int64.
 // ---------------------------------------------------------------------------
+constexpr double FIX_ONE = 4503599627370496.0;   // 2^52
+constexpr double FIX_VMAX = 4.0;                 // |v| / c0 range of the sums
+
+__device__ __forceinline__ void fix_add(int64_t* a, double x) {
+  atomicAdd((unsigned long long*)a, (unsigned long long)(long long)__builtin_rint(x * FIX_ONE));
+}
+
 template <class P>
 __global__ __launch_bounds__(BLOCK) void k_sumw(const SlotDesc* table, LaunchTab tab) {
 #pragma clang fp contract(off)
@@ -756,17 +774,36 @@ __global__ __launch_bounds__(BLOCK) void k_sumw(const SlotDesc* table, LaunchTab
       }
     }
   }
+  GLB Real4* vr = gp<Real4>(S.vr);
+  Real4 v = vr[i];
+  const double dp3 = S.dp * S.dp * S.dp;
   {
     const int n = (int)S.nsc[i];
     const GLB uint32_t* R = gpc<uint32_t>(S.srec) + slice * (int64_t)S.ks * WAVE + lane;
     const GLB Pos4* xw = gpc<Pos4>(S.xw);
+    const bool shep = !S.wall_rigid;
+    const double ic0 = 1.0 / S.c0;
+    double fv[3] = {(double)v.x * ic0, (double)v.y * ic0, (double)v.z * ic0};
+    if (shep && n > 0) {
+      bool in = true;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        in = in && fabs(fv[a]) <= FIX_VMAX;
+        fv[a] = fmin(fmax(fv[a], -FIX_VMAX), FIX_VMAX);
+      }
+      if (!in) raise_flag(S, F_CAPACITY);
+    }
     uint32_t wn[SOLID_UNROLL];
 #pragma unroll
     for (int u = 0; u < SOLID_UNROLL; ++u) wn[u] = ldnt(R + (int64_t)u * WAVE);
     for (int k = 0; k < n; k += SOLID_UNROLL) {
       Pos4 xq[SOLID_UNROLL];
+      uint32_t wq[SOLID_UNROLL];
 #pragma unroll
-      for (int u = 0; u < SOLID_UNROLL; ++u) xq[u] = xw[k + u < n ? wn[u] : 0u];
+      for (int u = 0; u < SOLID_UNROLL; ++u) {
+        wq[u] = k + u < n ? wn[u] : 0u;
+        xq[u] = xw[wq[u]];
+      }
       if (k + SOLID_UNROLL < n) {
 #pragma unroll
         for (int u = 0; u < SOLID_UNROLL; ++u) wn[u] = ldnt(R + (int64_t)(k + SOLID_UNROLL + u) * WAVE);
@@ -777,19 +814,54 @@ __global__ __launch_bounds__(BLOCK) void k_sumw(const SlotDesc* table, LaunchTab
         const Pos s2 = ddx * ddx + ddy * ddy;
         const Pos d2 = s2 + ddz * ddz;
         const double w = kernel_W_d2((double)d2, inv_h, kW);
-        if (k + u < n) sw += w;
+        if (k + u < n) {
+          sw += w;
+          if (shep) {
+            int64_t* a = S.wacc + 4 * (size_t)wq[u];
+            const double wd = w * dp3;
+            fix_add(a + 0, wd * fv[0]);
+            fix_add(a + 1, wd * fv[1]);
+            fix_add(a + 2, wd * fv[2]);
+            fix_add(a + 3, wd);
+          }
+        }
       }
     }
   }
   S.sumW[i] = sw;
-  GLB Real4* vr = gp<Real4>(S.vr);
-  Real4 v = vr[i];
-  const double dp3 = S.dp * S.dp * S.dp;
   const double rre = S.rho0 * (dp3 * sw) / S.S0;
   const double rcur = P::kRel ? S.rho0 + (double)v.w : (double)v.w;
   const double rn = S.free_surface ? fmax(rcur, rre) : rre;
   v.w = P::kRel ? (Real)(rn - S.rho0) : (Real)rn;
   vr[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// K: dummy velocity of every solid particle for the wall viscous force
+// (eq. 18): v_w = 2 u_w - v~_w with v~_w = c0 (sum W dp^3 v/c0) / (sum W dp^3)
+// the Shepard mean of the fluid velocity around it (the rigid velocity u_w
+// when no fluid is within 2h, or with the literal reading of eq. 18).
+// ---------------------------------------------------------------------------
+template <class P>
+__global__ __launch_bounds__(BLOCK) void k_wallvel(const SlotDesc* table, LaunchTab tab) {
+  typedef typename P::Real Real;
+  typedef typename P::Real4 Real4;
+  SLOT_PROLOGUE(DOM_SOLID);
+  const int w = lb * BLOCK + threadIdx.x;
+  if (w >= S.ns) return;
+  const Real4 u = gpc<Real4>(S.vw)[w];
+  Real4 o = u;
+  o.w = (Real)0;
+  const GLB int64_t* a = gpc<int64_t>(S.wacc) + 4 * (size_t)w;
+  const int64_t sw = a[3];
+  if (!S.wall_rigid && sw > 0) {
+    const double q = S.c0 / (double)sw;
+    o.x = (Real)(2.0 * (double)u.x - (double)a[0] * q);
+    o.y = (Real)(2.0 * (double)u.y - (double)a[1] * q);
+    o.z = (Real)(2.0 * (double)u.z - (double)a[2] * q);
+    o.w = (Real)((double)sw / FIX_ONE);
+  }
+  gp<Real4>(S.vd)[w] = o;
 }
 
 // ---------------------------------------------------------------------------
@@ -999,7 +1071,8 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
       wall = n > 0;
       const GLB uint32_t* R = gpc<uint32_t>(S.srec) + slice * (int64_t)S.ks * WAVE + lane;
       const GLB Real4* so = gpc<Real4>(S.so);
-      const GLB Real4* vw = gpc<Real4>(S.vw);
+      const GLB Real4* vdw = gpc<Real4>(S.vd);   // dummy velocity of eq. 18
+      const GLB Real4* vw = gpc<Real4>(S.vw);    // rigid velocity (velocity gradient of eq. 23)
       const GLB Real4* lv = gpc<Real4>(S.lev);
       const Real Vw = (Real)S.vol_w;
       const Real rc = rcp(rhoi * (Real)cpI);
@@ -1007,13 +1080,14 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
 #pragma unroll
       for (int u = 0; u < VISC_SOLID_UNROLL; ++u) wn[u] = ldnt(R + (int64_t)u * WAVE);
       for (int k0 = 0; k0 < n; k0 += VISC_SOLID_UNROLL) {
-        Real4 owu[VISC_SOLID_UNROLL], vqu[VISC_SOLID_UNROLL], lqu[VISC_SOLID_UNROLL];
+        Real4 owu[VISC_SOLID_UNROLL], vqu[VISC_SOLID_UNROLL], lqu[VISC_SOLID_UNROLL], vgu[VISC_SOLID_UNROLL];
 #pragma unroll
         for (int u = 0; u < VISC_SOLID_UNROLL; ++u) {
           const uint32_t w = k0 + u < n ? wn[u] : 0u;
           owu[u] = so[w];
-          vqu[u] = vw[w];
+          vqu[u] = vdw[w];
           lqu[u] = lv[w];
+          if (DISS) vgu[u] = vw[w];
         }
         if (k0 + VISC_SOLID_UNROLL < n) {
 #pragma unroll
@@ -1035,7 +1109,7 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
         const Real Kiw = (Real)(4.0 * kI * S.bk[b] / (kI + S.bk[b]));
         const Real term = Vw * Kiw * (Real)(Ti - (Temp)S.bT[b]) * Fk;
         hs += term;
-        if (DISS) grad_add(G, Vw * Fk, vq.x - vi.x, vq.y - vi.y, vq.z - vi.z, rx, ry, rz);
+        if (DISS) grad_add(G, Vw * Fk, vgu[u].x - vi.x, vgu[u].y - vi.y, vgu[u].z - vi.z, rx, ry, rz);
         // force of the fluid on the body is -m_i times this pair's acceleration
         const double gx = -(double)m * fx, gy = -(double)m * fy, gz = -(double)m * fz;
         const double lx = lq.x, ly = lq.y, lz = lq.z;
@@ -1561,6 +1635,7 @@ int grid_domain(int kid, int which) {
       return DOM_CELL;
     case SPH_K_POSE:
     case SPH_K_CONTACT:
+    case SPH_K_WALLVEL:
       return DOM_SOLID;
     case SPH_K_SCAN2:
     case SPH_K_DT:
@@ -1594,6 +1669,7 @@ static hipError_t launch_p(int kid, int which, int sub, const SlotDesc* T, const
     case SPH_K_BUILD: hipLaunchKernelGGL(k_build<P>, g, b, 0, st, T, L); break;
     case SPH_K_SUMW: hipLaunchKernelGGL(k_sumw<P>, g, b, 0, st, T, L); break;
     case SPH_K_CONTACT: hipLaunchKernelGGL(k_contact<P>, g, b, 0, st, T, L); break;
+    case SPH_K_WALLVEL: hipLaunchKernelGGL(k_wallvel<P>, g, b, 0, st, T, L); break;
     case SPH_K_DT: hipLaunchKernelGGL(k_dt, g, b, 0, st, T, L); break;
     case SPH_K_VISC_HEAT:
       if (L.flags & TAB_MAT) {

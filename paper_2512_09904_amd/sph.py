@@ -22,11 +22,11 @@ MAX_BODIES = 8
 
 KERNELS = ["clear", "pose", "fold", "scan1", "scan2", "scan3", "scatter", "cellsort", "reorder", "build",
            "dt", "visc_heat", "half_a", "momentum", "continuity", "end", "final", "sumw", "contact",
-           "relax_force", "relax_max", "relax_move"]
+           "relax_force", "relax_max", "relax_move", "wallvel"]
 K = {n: i for i, n in enumerate(KERNELS)}
 
 DUMP = dict(fluid_ids=1, solid_ids=2, fluid_cell=3, nbr_count=4, nbr_fluid=5, nbr_solid=6, fluid_offset=7,
-            solid_offset=8, fluid_state=9, solid_state=10, sumw=11)
+            solid_offset=8, fluid_state=9, solid_state=10, sumw=11, solid_dummy=12)
 
 
 class SphError(RuntimeError):
@@ -42,7 +42,7 @@ class Params(C.Structure):
                 ("cfl_ac", C.c_double), ("fixed_dt_ad", C.c_double), ("fixed_nac", C.c_int32),
                 ("nac_max", C.c_int32), ("free_surface", C.c_int32), ("precision", C.c_int32),
                 ("max_fluid_nbrs", C.c_int32), ("max_solid_nbrs", C.c_int32), ("viscous_heating", C.c_int32),
-                ("reserved", C.c_int32), ("n_materials", C.c_int32), ("reserved2", C.c_int32),
+                ("wall_visc", C.c_int32), ("n_materials", C.c_int32), ("reserved2", C.c_int32),
                 ("mat_k", C.c_double * 8), ("mat_cp", C.c_double * 8)]
 
 
@@ -184,6 +184,7 @@ def params_struct(params: dict, precision="mixed", fixed_dt_ad=None, fixed_nac=N
     P.max_fluid_nbrs = int(d.get("max_fluid_nbrs", 0))
     P.max_solid_nbrs = int(d.get("max_solid_nbrs", 0))
     P.viscous_heating = int(d.get("viscous_heating", 0))
+    P.wall_visc = int(d.get("wall_visc", 0))
     mats = d.get("materials") or []
     P.n_materials = len(mats)
     for m, (k, cp) in enumerate(mats):

@@ -681,6 +681,73 @@ def test_viscous_heating_rejects_bad_flag(sph):
 
 
 # ---------------------------------------------------------------------------
+# the wall's no-slip dummy velocity (eq. 18 with the generalized wall)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision,tol", [("mixed", 1e-6), ("fp64", 1e-13)])
+def test_wall_dummy_velocity_matches_oracle(sph, ora, precision, tol):
+    """Per solid particle, the dummy velocity 2 u_w - (Shepard mean of the
+    fluid velocity) of a sheared tank at its first build, within tol Umax of
+    the oracle's (mixed: FP32 velocities and storage; FP64 mode: the
+    fixed-point sums are exact to 2^-52 c0 per term), and the Shepard weight
+    dp^3 sum W within tol relative.  Solid particles without fluid keep their
+    rigid velocity exactly."""
+    c = _sheared(ragged_tank(seed=4), 5)
+    say("dummy velocity parity", precision, c.ns)
+    s = sph.Solver(c, precision=precision)
+    sid = s.dump("solid_ids").astype(np.int64)
+    d = s.dump("solid_dummy").reshape(c.ns, 4)
+    st = s.dump("solid_state").reshape(c.ns, 13)
+    s.close()
+    vd = np.empty((c.ns, 3))
+    vd[sid] = d[:, :3]
+    sw = np.empty(c.ns)
+    sw[sid] = d[:, 3]
+    vrig = np.empty((c.ns, 3))
+    vrig[sid] = st[:, 6:9]
+    xs, _, vs = ora.body_pose(c.bodies, c.xs0, c.ns0, c.body, 0.0)
+    nb = ora.Nbr(c.params, c.xf, xs)
+    vo, swo = ora.wall_dummy_velocity(c.params, nb, c.vf, vs)
+    dp3 = c.params["dp"] ** 3
+    wet = swo > 0
+    assert wet.sum() > 1000 and (~wet).sum() > 1000
+    umax = c.meta["umax"]
+    err = np.max(np.abs(vd - vo)) / umax
+    say("dummy velocity max error / Umax", err)
+    assert err <= tol, err
+    assert np.allclose(sw, swo * dp3, rtol=tol, atol=0)
+    assert np.array_equal(vd[~wet], vrig[~wet])
+
+
+@pytest.mark.parametrize("precision,bar,tau", [("mixed", 1e-5, 1e-5), ("fp64", 1e-10, 1e-11)])
+def test_literal_wall_velocity_parity(sph, ora, precision, bar, tau):
+    """The literal reading of eq. 18 (SPH_WALL_VISC_RIGID) against the oracle's
+    same switch: one step of a sheared tank, state and viscous rates."""
+    c = _sheared(ragged_tank(seed=6), 9)
+    dt, nac = fixed_dt(c)
+    o = ora.State(c, fixed_dt_ad=dt, fixed_nac=nac, wall_visc=1)
+    ro = o.step(want_rates=True)
+    s = sph.Solver(c, precision=precision, fixed_dt_ad=dt, fixed_nac=nac, wall_visc=1)
+    s.step(1)
+    g = s.get_fluid()
+    fid = s.dump("fluid_ids").astype(np.int64)
+    st = s.dump("fluid_state").reshape(c.nf, 16)[np.argsort(fid)]
+    s.close()
+    e = _normalised_errors(c, o, g)
+    say("literal wall normalised errors", precision, e)
+    assert max(e.values()) <= bar, e
+    R = ro["rates"]
+    dv = np.max(np.abs(st[:, 12:15] - R["a_visc"]), axis=1)
+    assert np.all(dv <= tau * R["S_visc"] + 1e-300), np.max(dv / (R["S_visc"] + 1e-300))
+
+
+def test_wall_visc_rejects_unknown_reading(sph):
+    with pytest.raises(sph.SphError) as e:
+        sph.Solver(cases.tank_c1(), wall_visc=2)
+    assert e.value.code == sph.SPH_ERR_ARG
+
+
+# ---------------------------------------------------------------------------
 # several fluid materials (eq. 22 with k_i, k_j and cp_i per particle)
 # ---------------------------------------------------------------------------
 
