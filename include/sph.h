@@ -19,9 +19,10 @@
  * thread-local message for the last failure.  Host arrays passed in are
  * borrowed for the duration of the call only and copied; vectors are n x 3,
  * row-major (x0 y0 z0 x1 ...), FP64.  Output buffers are owned by the caller.
- * Device memory is obtained through the sph_allocator given at creation (or
- * hipMalloc/hipFree when it is NULL); all GPU work is enqueued on the HIP
- * stream given at creation (caller-owned; NULL means the legacy default
+ * Device memory is obtained only through the sph_allocator given at creation
+ * (required: sph_create and sph_pool_create return SPH_ERR_ARG without one;
+ * the library never calls hipMalloc itself); all GPU work is enqueued on the
+ * HIP stream given at creation (caller-owned; NULL means the legacy default
  * stream, which cannot be graph-captured).  Units are SI; temperatures in K.
  * Gravity points along -z in the workloads but is a parameter.
  */
@@ -162,13 +163,17 @@ const char* sph_last_error(void);
 
 /* ---- one solve ----------------------------------------------------------- */
 /* Create a solver; nothing is allocated on the device before sph_init.
- * SPH_ERR_ARG for h_over_dp outside [1, 2], non-positive constants, or a grid
- * with more than 1024 cells per axis or 2^26 cells in total. */
+ * SPH_ERR_ARG for h_over_dp outside [1, 2], non-positive constants, a grid
+ * with more than 1024 cells per axis or 2^26 cells in total, or a NULL
+ * allocator (or one without alloc or free). */
 int sph_create(const sph_params* p, const sph_allocator* a, void* hip_stream, sph_solver** out);
-/* Bodies: n in [1, SPH_MAX_BODIES]; axis need not be unit length. */
+/* Bodies (Section 4, Tables 5-6: each gear turns at a prescribed speed about
+ * its shaft and is held at a fixed temperature): n in [1, SPH_MAX_BODIES];
+ * axis need not be unit length. */
 int sph_set_bodies(sph_solver* s, int32_t n, const sph_body* b);
-/* Fluid particles: positions, velocities, densities, temperatures and material
- * indices (nullable: all 0; each below max(n_materials, 1)); copied at sph_init. */
+/* Fluid particles (the lubricant of Section 4, properties of Table 6):
+ * positions, velocities, densities, temperatures and material indices
+ * (nullable: all 0; each below max(n_materials, 1)); copied at sph_init. */
 int sph_set_fluid(sph_solver* s, int64_t n, const double* x, const double* v, const double* rho,
                   const double* T, const int32_t* material);
 /* Solid particles at t = 0 in the world frame: positions, unit normals pointing
@@ -182,10 +187,14 @@ int sph_init(sph_solver* s);
 /* Enqueue n advection steps; asynchronous.  Device faults are latched and
  * reported by the next sph_reduce; after a fault, sph_step returns SPH_ERR_STATE. */
 int sph_step(sph_solver* s, int32_t n_adv_steps);
-/* Synchronise and read the reports (per_body may be NULL; else nbody entries).
- * Returns the latched fault as SPH_ERR_DOMAIN / _NONFINITE / _CAPACITY. */
+/* Synchronise and read the reports (per_body may be NULL; else nbody entries):
+ * the observables of Section 4, torque and churning power per shaft and the
+ * oil's thermal energy (its mean temperature), with the heat drawn from the
+ * bodies.  Returns the latched fault as SPH_ERR_DOMAIN / _NONFINITE /
+ * _CAPACITY. */
 int sph_reduce(sph_solver* s, sph_report* r, sph_body_report* per_body);
-/* Synchronise and read the fluid state in the order given to sph_set_fluid.
+/* Synchronise and read the fluid fields (Section 4: the oil distribution and
+ * temperature fields) in the order given to sph_set_fluid.
  * x = anchor + drift; any pointer may be NULL. */
 int sph_get_fluid(sph_solver* s, double* x, double* v, double* rho, double* T);
 /* Use a captured hipGraph per advection step (default on) or eager launches. */
@@ -195,7 +204,7 @@ int sph_set_timing(sph_solver* s, int32_t enable);
 /* Durations in ms of the recorded launches of kernel `kernel` (SPH_K_*), oldest
  * first; *count receives the number recorded (may exceed max).  Synchronises. */
 int sph_get_timing(sph_solver* s, int32_t kernel, int32_t max, float* ms, int32_t* count);
-/* Contact factor (Section 2.5, eq. 24) of every solid particle at the
+/* Contact factor (Section 2.7, eq. 24) of every solid particle at the
  * current time t: zeta_w = sum over fluid j with |x_w - x_j| < 2h of
  * V_j W(|x_w - x_j|) (V_j = m / rho_j), divided by the full-immersion
  * reference, the perfect-lattice kernel sum over the wall's outer half-space
@@ -205,7 +214,8 @@ int sph_get_timing(sph_solver* s, int32_t kernel, int32_t max, float* ms, int32_
  * without particles; may be NULL).  Runs the cell sort and neighbour build of
  * the current state on the solver's stream (the next step's own build then
  * reproduces them exactly, so stepping is unaffected) and synchronises.
- * SPH_ERR_STATE before sph_init or after a latched fault. */
+ * SPH_ERR_STATE before sph_init; after a latched fault, that fault's own code
+ * (SPH_ERR_DOMAIN / _NONFINITE / _CAPACITY), as sph_reduce returns it. */
 int sph_contact_factor(sph_solver* s, double* zeta, double* body_mean);
 
 /* An analytic shape bounding the particle relaxation (Section 2.2, eq. 5):
@@ -247,7 +257,8 @@ typedef struct {
  * with sph_get_fluid; the density re-initialisation of each build also
  * runs).  Call between steps; synchronises.  SPH_ERR_ARG
  * for a bad shape or iterations < 1, SPH_ERR_DOMAIN if a particle leaves the
- * grid, SPH_ERR_STATE before sph_init or after a latched fault. */
+ * grid, SPH_ERR_STATE before sph_init; after a latched fault, that fault's own
+ * code, as sph_reduce returns it. */
 int sph_relax(sph_solver* s, const sph_shape* shape, int32_t iterations, sph_relax_report* report);
 /* Raw device state for parity tests (SPH_DUMP_*); bytes must be >= the size
  * reported by sph_dump_size.  Synchronises. */

@@ -28,6 +28,16 @@ def build(force: bool = True) -> str:
     return LIB
 
 
+def set_threads(n: int) -> int:
+    """Set the OpenMP thread count of the oracle's later calls from this
+    thread; returns the previous count."""
+    lib()
+    gomp = C.CDLL("libgomp.so.1")
+    prev = int(gomp.omp_get_max_threads())
+    gomp.omp_set_num_threads(C.c_int(int(n)))
+    return prev
+
+
 class Params(C.Structure):
     _fields_ = [("dp", C.c_double), ("h_over_dp", C.c_double), ("rho0", C.c_double),
                 ("c0", C.c_double), ("nu", C.c_double), ("k_f", C.c_double), ("cp_f", C.c_double),
@@ -56,7 +66,7 @@ class BodyReport(C.Structure):
 
 class Rates(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("a_visc", "dTdt", "sumW", "S_visc", "S_T", "a_p", "S_p", "S_rho",
-                                          "G", "phi", "S_G")]
+                                          "G", "phi", "S_G", "bscale")]
 
 
 _lib = None
@@ -407,7 +417,8 @@ class State:
             rates = Rates()
             for name, shape in (("a_visc", (nf, 3)), ("dTdt", (nf,)), ("sumW", (nf,)), ("S_visc", (nf,)),
                                 ("S_T", (nf,)), ("a_p", (nf, 3)), ("S_p", (nf,)), ("S_rho", (nf,)),
-                                ("G", (nf, 3, 3)), ("phi", (nf,)), ("S_G", (nf,))):
+                                ("G", (nf, 3, 3)), ("phi", (nf,)), ("S_G", (nf,)),
+                                ("bscale", (max(1, self.nb), 13))):
                 arr = np.zeros(shape)
                 rates_np[name] = arr
                 setattr(rates, name, arr.ctypes.data)

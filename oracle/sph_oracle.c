@@ -111,7 +111,7 @@ double ora_lattice_sum0(double h_over_dp) {
 /* Perfect-lattice kernel sum, in units of dp^3, over the sites of the open
    half-space x > 0 as seen from a site on the plane x = 0: the kernel sum of
    a wall particle whose whole outer side is filled with fluid at rho0.  It is
-   the full-immersion reference of the contact factor (Section 2.5, eq. 24). */
+   the full-immersion reference of the contact factor (Section 2.7, eq. 24). */
 double ora_lattice_halfspace(double h_over_dp) {
   int R = (int)ceil(2.0 * h_over_dp) + 1;
   double s = 0.0;
@@ -402,7 +402,7 @@ void ora_sum_w(const ora_params* P, const ora_nbr* nb, double* sumW) {
 /* per-body accumulation helper: per-particle contributions, then a serial
  * compensated sum in particle order so the result is independent of threads */
 typedef struct { double* buf; int64_t nf; int32_t nbody; int32_t width; } bacc;
-/* Contact factor of every solid particle (Section 2.5, eq. 24): the sum of
+/* Contact factor of every solid particle (Section 2.7, eq. 24): the sum of
    V_j W(|x_w - x_j|) over the fluid particles j within 2h of solid w, with
    V_j = m / rho_j, divided by the full-immersion reference ref (the same sum
    for the fluid filling the wall's outer half-space at rho0).  The fluid
@@ -492,13 +492,18 @@ void ora_wall_dummy_velocity(const ora_params* P, const ora_nbr* nb, const doubl
   free(acc);
 }
 
-void ora_viscous(const ora_params* P, const ora_nbr* nb, int32_t nbody, const ora_body* B,
-                 const int32_t* body, const double* v, const double* rho, const double* mass,
-                 const double* vs, double* a, double* S, double* bforce, double* btorque) {
+/* babs (nullable, nbody x 6): per body, the sums over its wall pairs of the
+ * absolute values of the force (3) and torque (3) components' terms, the
+ * scale against which a differently rounded sum is judged. */
+static void viscous_abs(const ora_params* P, const ora_nbr* nb, int32_t nbody, const ora_body* B,
+                        const int32_t* body, const double* v, const double* rho, const double* mass,
+                        const double* vs, double* a, double* S, double* bforce, double* btorque,
+                        double* babs) {
   double eta = P->rho0 * P->nu;
   double Vw = P->dp * P->dp * P->dp;
   bacc acc;
-  int use_acc = (bforce || btorque) && nbody > 0 && bacc_init(&acc, nb->nf, nbody, 6) == 0;
+  const int32_t width = babs ? 12 : 6;
+  int use_acc = (bforce || btorque || babs) && nbody > 0 && bacc_init(&acc, nb->nf, nbody, width) == 0;
   /* dummy-particle velocity of eq. 18 (reading switch, see ora_params) */
   double* vd = (double*)malloc(sizeof(double) * 3 * (size_t)(nb->ns > 0 ? nb->ns : 1));
   if (!vd) abort();
@@ -535,6 +540,8 @@ void ora_viscous(const ora_params* P, const ora_nbr* nb, int32_t nbody, const or
         for (int k = 0; k < 3; ++k) l[k] = nb->xsb[3 * w + k] - B[b].center[k];
         cross3(l, fb, tq);
         for (int k = 0; k < 3; ++k) { o[k] += fb[k]; o[3 + k] += tq[k]; }
+        if (babs)
+          for (int k = 0; k < 3; ++k) { o[6 + k] += fabs(fb[k]); o[9 + k] += fabs(tq[k]); }
       }
     }
     for (int k = 0; k < 3; ++k) a[3 * i + k] = sum[k] / mass[i];
@@ -542,15 +549,25 @@ void ora_viscous(const ora_params* P, const ora_nbr* nb, int32_t nbody, const or
   }
   free(vd);
   if (use_acc) {
-    double* tmp = (double*)malloc(sizeof(double) * 6 * (size_t)nbody);
+    double* tmp = (double*)malloc(sizeof(double) * (size_t)width * (size_t)nbody);
+    if (!tmp) abort();
     bacc_reduce(&acc, tmp);
-    for (int32_t b = 0; b < nbody; ++b)
+    for (int32_t b = 0; b < nbody; ++b) {
       for (int k = 0; k < 3; ++k) {
-        if (bforce) bforce[3 * b + k] = tmp[6 * b + k];
-        if (btorque) btorque[3 * b + k] = tmp[6 * b + 3 + k];
+        if (bforce) bforce[3 * b + k] = tmp[width * b + k];
+        if (btorque) btorque[3 * b + k] = tmp[width * b + 3 + k];
       }
+      if (babs)
+        for (int k = 0; k < 6; ++k) babs[6 * b + k] = tmp[width * b + 6 + k];
+    }
     free(tmp);
   }
+}
+
+void ora_viscous(const ora_params* P, const ora_nbr* nb, int32_t nbody, const ora_body* B,
+                 const int32_t* body, const double* v, const double* rho, const double* mass,
+                 const double* vs, double* a, double* S, double* bforce, double* btorque) {
+  viscous_abs(P, nb, nbody, B, body, v, rho, mass, vs, a, S, bforce, btorque, NULL);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -560,12 +577,16 @@ void ora_viscous(const ora_params* P, const ora_nbr* nb, int32_t nbody, const or
 /* holds the fixed temperature and conductivity of its body.  bheat[b] is the  */
 /* heat flow into the fluid from body b: sum m_i cp_i (wall part of dT_i/dt).  */
 /* ------------------------------------------------------------------------ */
-void ora_heat(const ora_params* P, const ora_nbr* nb, int32_t nbody, const ora_body* B,
-              const int32_t* body, const double* rho, const double* mass, const double* k,
-              const double* cp, const double* T, double* dTdt, double* S, double* bheat) {
+/* babs (nullable, nbody): per body, the sum of the absolute values of the
+ * terms of its heat flow. */
+static void heat_abs(const ora_params* P, const ora_nbr* nb, int32_t nbody, const ora_body* B,
+                     const int32_t* body, const double* rho, const double* mass, const double* k,
+                     const double* cp, const double* T, double* dTdt, double* S, double* bheat,
+                     double* babs) {
   double Vw = P->dp * P->dp * P->dp;
   bacc acc;
-  int use_acc = bheat && nbody > 0 && bacc_init(&acc, nb->nf, nbody, 1) == 0;
+  const int32_t width = babs ? 2 : 1;
+  int use_acc = (bheat || babs) && nbody > 0 && bacc_init(&acc, nb->nf, nbody, width) == 0;
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < nb->nf; ++i) {
     double rc = 1.0 / (rho[i] * cp[i]);
@@ -587,12 +608,32 @@ void ora_heat(const ora_params* P, const ora_nbr* nb, int32_t nbody, const ora_b
       double term = Vw * Kiw * (T[i] - B[b].T) * g.F;
       sum += term;
       s_abs += fabs(term);
-      if (use_acc) bacc_at(&acc, i, b)[0] += mass[i] * cp[i] * (rc * term);
+      if (use_acc) {
+        double* o = bacc_at(&acc, i, b);
+        const double q = mass[i] * cp[i] * (rc * term);
+        o[0] += q;
+        if (babs) o[1] += fabs(q);
+      }
     }
     dTdt[i] = rc * sum;
     if (S) S[i] = rc * s_abs;
   }
-  if (use_acc) bacc_reduce(&acc, bheat);
+  if (use_acc) {
+    double* tmp = (double*)malloc(sizeof(double) * (size_t)width * (size_t)nbody);
+    if (!tmp) abort();
+    bacc_reduce(&acc, tmp);
+    for (int32_t b = 0; b < nbody; ++b) {
+      if (bheat) bheat[b] = tmp[width * b];
+      if (babs) babs[b] = tmp[width * b + 1];
+    }
+    free(tmp);
+  }
+}
+
+void ora_heat(const ora_params* P, const ora_nbr* nb, int32_t nbody, const ora_body* B,
+              const int32_t* body, const double* rho, const double* mass, const double* k,
+              const double* cp, const double* T, double* dTdt, double* S, double* bheat) {
+  heat_abs(P, nb, nbody, B, body, rho, mass, k, cp, T, dTdt, S, bheat, NULL);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -693,14 +734,16 @@ void ora_pair_force(const ora_params* P, const double* xi, const double* xj, con
   visc_pair(Vi, Vj, P->rho0 * P->nu, g.F, vi, vj, f + 3);
 }
 
-void ora_momentum(const ora_params* P, const ora_nbr* nb, int32_t nbody, const ora_body* B,
-                  const int32_t* body, const double* v, const double* rho, const double* mass,
-                  const double* nsv, const double* vs, double* a, double* S, double* bforce,
-                  double* btorque) {
+/* babs as for the viscous sweep: sums of |force| and |torque| component terms */
+static void momentum_abs(const ora_params* P, const ora_nbr* nb, int32_t nbody, const ora_body* B,
+                         const int32_t* body, const double* v, const double* rho, const double* mass,
+                         const double* nsv, const double* vs, double* a, double* S, double* bforce,
+                         double* btorque, double* babs) {
   (void)nsv; (void)vs;
   double Vw = P->dp * P->dp * P->dp;
   bacc acc;
-  int use_acc = (bforce || btorque) && nbody > 0 && bacc_init(&acc, nb->nf, nbody, 6) == 0;
+  const int32_t width = babs ? 12 : 6;
+  int use_acc = (bforce || btorque || babs) && nbody > 0 && bacc_init(&acc, nb->nf, nbody, width) == 0;
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < nb->nf; ++i) {
     double Vi = mass[i] / rho[i];
@@ -732,21 +775,34 @@ void ora_momentum(const ora_params* P, const ora_nbr* nb, int32_t nbody, const o
         for (int k = 0; k < 3; ++k) l[k] = nb->xsb[3 * w + k] - B[b].center[k];
         cross3(l, fb, tq);
         for (int k = 0; k < 3; ++k) { o[k] += fb[k]; o[3 + k] += tq[k]; }
+        if (babs)
+          for (int k = 0; k < 3; ++k) { o[6 + k] += fabs(fb[k]); o[9 + k] += fabs(tq[k]); }
       }
     }
     for (int k = 0; k < 3; ++k) a[3 * i + k] = sum[k] / mass[i];
     if (S) S[i] = s_abs / mass[i];
   }
   if (use_acc) {
-    double* tmp = (double*)malloc(sizeof(double) * 6 * (size_t)nbody);
+    double* tmp = (double*)malloc(sizeof(double) * (size_t)width * (size_t)nbody);
+    if (!tmp) abort();
     bacc_reduce(&acc, tmp);
-    for (int32_t b = 0; b < nbody; ++b)
+    for (int32_t b = 0; b < nbody; ++b) {
       for (int k = 0; k < 3; ++k) {
-        if (bforce) bforce[3 * b + k] = tmp[6 * b + k];
-        if (btorque) btorque[3 * b + k] = tmp[6 * b + 3 + k];
+        if (bforce) bforce[3 * b + k] = tmp[width * b + k];
+        if (btorque) btorque[3 * b + k] = tmp[width * b + 3 + k];
       }
+      if (babs)
+        for (int k = 0; k < 6; ++k) babs[6 * b + k] = tmp[width * b + 6 + k];
+    }
     free(tmp);
   }
+}
+
+void ora_momentum(const ora_params* P, const ora_nbr* nb, int32_t nbody, const ora_body* B,
+                  const int32_t* body, const double* v, const double* rho, const double* mass,
+                  const double* nsv, const double* vs, double* a, double* S, double* bforce,
+                  double* btorque) {
+  momentum_abs(P, nb, nbody, B, body, v, rho, mass, nsv, vs, a, S, bforce, btorque, NULL);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -950,9 +1006,14 @@ int ora_step_kc(const ora_params* P, int32_t nbody, const ora_body* B, int64_t n
   double* bFp = calloc(3 * (size_t)(nbody > 0 ? nbody : 1), sizeof(double));
   double* bTp = calloc(3 * (size_t)(nbody > 0 ? nbody : 1), sizeof(double));
   ksum* kFp = calloc(6 * (size_t)(nbody > 0 ? nbody : 1), sizeof(ksum));
+  /* scales of the body quantities (rates->bscale): |terms| of the viscous part
+     (6), the heat flow (1) and the pressure part summed over the sub-steps (6) */
+  double* babs = calloc(13 * (size_t)(nbody > 0 ? nbody : 1), sizeof(double));
+  double* bsub = calloc(6 * (size_t)(nbody > 0 ? nbody : 1), sizeof(double));
+  const int want_scale = rates && rates->bscale && nbody > 0;
   ora_nbr* nb = NULL;
   if (!xs || !nsv || !vs || !mass || !kf || !cpf || !sumW || !av || !ap || !dTdt || !bq || !bFv ||
-      !bTv || !bFp || !bTp || !kFp) { rc = ORA_ERR_OOM; goto done; }
+      !bTv || !bFp || !bTp || !kFp || !babs || !bsub) { rc = ORA_ERR_OOM; goto done; }
   if (P->viscous_heating) {
     G = malloc(sizeof(double) * 9 * nfz);
     phi = malloc(sizeof(double) * nfz);
@@ -990,8 +1051,20 @@ int ora_step_kc(const ora_params* P, int32_t nbody, const ora_body* B, int64_t n
   }
   ora_timestep_T(P, nbody, B, ns, x0, body, nf, v, dtT, &dt_ad, &dt, &n_ac, &vmax0);
   /* 6. viscous and heat rates, frozen for the step */
-  ora_viscous(P, nb, nbody, B, body, v, rho, mass, vs, av, rates ? rates->S_visc : NULL, bFv, bTv);
-  ora_heat(P, nb, nbody, B, body, rho, mass, kf, cpf, T, dTdt, rates ? rates->S_T : NULL, bq);
+  {
+    double* vabs = want_scale ? malloc(sizeof(double) * 6 * (size_t)nbody) : NULL;
+    double* habs = want_scale ? malloc(sizeof(double) * (size_t)nbody) : NULL;
+    if (want_scale && (!vabs || !habs)) { free(vabs); free(habs); rc = ORA_ERR_OOM; goto done; }
+    viscous_abs(P, nb, nbody, B, body, v, rho, mass, vs, av, rates ? rates->S_visc : NULL, bFv, bTv, vabs);
+    heat_abs(P, nb, nbody, B, body, rho, mass, kf, cpf, T, dTdt, rates ? rates->S_T : NULL, bq, habs);
+    if (want_scale)
+      for (int32_t b = 0; b < nbody; ++b) {
+        for (int k = 0; k < 6; ++k) babs[13 * b + k] = vabs[6 * b + k];
+        babs[13 * b + 6] = habs[b];
+      }
+    free(vabs);
+    free(habs);
+  }
   /* viscous dissipation heating, eq. 23 (off in the paper's model) */
   ksum kd = {0, 0};
   if (P->viscous_heating) {
@@ -1008,9 +1081,13 @@ int ora_step_kc(const ora_params* P, int32_t nbody, const ora_body* B, int64_t n
       rho[i] += 0.5 * dt * drho[i];
       for (int k = 0; k < 3; ++k) x[3 * i + k] += 0.5 * dt * v[3 * i + k];
     }
-    ora_momentum(P, nb, nbody, B, body, v, rho, mass, nsv, vs, ap, rates ? rates->S_p : NULL, bFp, bTp);
+    momentum_abs(P, nb, nbody, B, body, v, rho, mass, nsv, vs, ap, rates ? rates->S_p : NULL, bFp, bTp,
+                 want_scale ? bsub : NULL);
     for (int32_t b = 0; b < nbody; ++b)
       for (int k = 0; k < 3; ++k) { kadd(&kFp[6 * b + k], bFp[3 * b + k]); kadd(&kFp[6 * b + 3 + k], bTp[3 * b + k]); }
+    if (want_scale)
+      for (int32_t b = 0; b < nbody; ++b)
+        for (int k = 0; k < 6; ++k) babs[13 * b + 7 + k] += bsub[6 * b + k];
     for (int64_t i = 0; i < nf; ++i)
       for (int k = 0; k < 3; ++k) {
         v[3 * i + k] += dt * (ap[3 * i + k] + av[3 * i + k] + P->gravity[k]);
@@ -1052,6 +1129,9 @@ int ora_step_kc(const ora_params* P, int32_t nbody, const ora_body* B, int64_t n
     if (rates->dTdt) memcpy(rates->dTdt, dTdt, sizeof(double) * (size_t)nf);
     if (rates->sumW) memcpy(rates->sumW, sumW, sizeof(double) * (size_t)nf);
     if (rates->a_p) memcpy(rates->a_p, ap, sizeof(double) * 3 * (size_t)nf);
+    if (want_scale)
+      for (int32_t b = 0; b < nbody; ++b)
+        for (int k = 0; k < 13; ++k) rates->bscale[13 * b + k] = k < 7 ? babs[13 * b + k] : babs[13 * b + k] / (double)n_ac;
     if (P->viscous_heating) {
       if (rates->G) memcpy(rates->G, G, sizeof(double) * 9 * (size_t)nf);
       if (rates->phi) memcpy(rates->phi, phi, sizeof(double) * (size_t)nf);
@@ -1061,7 +1141,7 @@ int ora_step_kc(const ora_params* P, int32_t nbody, const ora_body* B, int64_t n
 done:
   ora_nbr_free(nb);
   free(xs); free(nsv); free(vs); free(mass); free(kf); free(cpf); free(sumW); free(av); free(ap);
-  free(dTdt); free(bq); free(bFv); free(bTv); free(bFp); free(bTp); free(kFp);
+  free(dTdt); free(bq); free(bFv); free(bTv); free(bFp); free(bTp); free(kFp); free(babs); free(bsub);
   free(G); free(phi); free(SG);
   return rc;
 }

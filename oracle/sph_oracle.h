@@ -70,6 +70,10 @@ typedef struct {
   double *G;        /* nf*9 velocity gradient G[a][b] = d v_a / d x_b (viscous heating only) */
   double *phi;      /* nf   dissipation 2 eta S:S (viscous heating only) */
   double *S_G;      /* nf   sum of |velocity-gradient pair terms| (viscous heating only) */
+  double *bscale;   /* nbody*13: per body, the sums of |terms| of its 13 reported parts: viscous
+                       force (3) and torque (3), heat flow (1), pressure force (3) and torque (3),
+                       the pressure part summed over the sub-steps and divided by n_ac like the
+                       report */
 } ora_rates;
 
 /* Neighbour sets and the frozen pair geometry of one advection step. */
@@ -103,7 +107,7 @@ void ora_nbr_free(ora_nbr* nb);
 
 /* --- sweeps over frozen neighbour sets ----------------------------------- */
 void ora_sum_w(const ora_params* P, const ora_nbr* nb, double* sumW);
-/* Contact factor per solid particle (Section 2.5, eq. 24): sum over fluid j
+/* Contact factor per solid particle (Section 2.7, eq. 24): sum over fluid j
    within 2h of V_j W_wj (V_j = m / rho_j) over ref; zeta[ns]. */
 int ora_contact_factor(const ora_params* P, int64_t nf, const double* xf, const double* rho, int64_t ns,
                        const double* xs, double ref, double* zeta);

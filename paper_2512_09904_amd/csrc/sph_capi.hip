@@ -303,7 +303,10 @@ struct SlotHost {
   bool ev_recorded = false;
   hipEvent_t ev_admit = nullptr;   // the slot's upload has completed on the main stream
   std::vector<uint32_t> morton_of_rank;
+  // host sources of the slot's stream-ordered uploads: they must outlive the
+  // copies, so neither is resized or reassigned while the slot is admitted
   std::vector<char> staging;
+  SlotCtl ctl_staged{};
 };
 
 struct TimedLaunch {
@@ -317,7 +320,6 @@ struct sph_pool {
   hipStream_t stream = nullptr;
   hipStream_t copy_stream = nullptr;
   sph_allocator alloc{};
-  bool have_alloc = false;
   int prec = 0;
   size_t budget = 0, used = 0;
   int max_slots = 1;
@@ -348,18 +350,16 @@ struct sph_solver {
 // ---------------------------------------------------------------------------
 // device memory
 // ---------------------------------------------------------------------------
+// Every device allocation goes through the caller's allocator (the pool
+// refuses to be created without one); the library never allocates by itself.
 static void* dev_alloc(sph_pool* P, size_t bytes) {
   if (bytes == 0) bytes = 256;
-  if (P->have_alloc) return P->alloc.alloc(bytes, (void*)P->stream, P->alloc.user);
-  void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
-  return p;
+  return P->alloc.alloc(bytes, (void*)P->stream, P->alloc.user);
 }
 
 static void dev_free(sph_pool* P, void* ptr) {
   if (!ptr) return;
-  if (P->have_alloc) P->alloc.free(ptr, (void*)P->stream, P->alloc.user);
-  else (void)hipFree(ptr);
+  P->alloc.free(ptr, (void*)P->stream, P->alloc.user);
 }
 
 static void drop_graph(sph_pool* P) {
@@ -514,12 +514,10 @@ extern "C" int sph_pool_create(size_t budget, int32_t max_slots, int32_t precisi
   *out = nullptr;
   if (max_slots < 1 || max_slots > MAX_SLOTS) return fail(SPH_ERR_ARG, "max_slots must be in [1, 32]");
   if (precision < 0 || precision > 2) return fail(SPH_ERR_ARG, "unknown precision");
+  if (!a || !a->alloc || !a->free) return fail(SPH_ERR_ARG, "an allocator with alloc and free is required");
   sph_pool* P = new sph_pool();
   P->stream = (hipStream_t)stream;
-  if (a && a->alloc && a->free) {
-    P->alloc = *a;
-    P->have_alloc = true;
-  }
+  P->alloc = *a;
   P->prec = precision;
   P->budget = budget;
   P->max_slots = max_slots;
@@ -734,15 +732,11 @@ static int admit(sph_pool* P, const sph_params* p, int32_t nbody, const sph_body
     S = SlotHost();
     return rc;
   }
-  SlotCtl ctl;
-  std::memset(&ctl, 0, sizeof(ctl));
-  ctl.target = target;
-  // the control block and table entry are staged in host memory that lives as
-  // long as the slot (the copies are stream-ordered)
-  const size_t tail = S.staging.size();
-  S.staging.resize(tail + sizeof(SlotCtl));
-  std::memcpy(S.staging.data() + tail, &ctl, sizeof(ctl));
-  HIPCHK(hipMemcpyAsync(D.ctl, S.staging.data() + tail, sizeof(SlotCtl), hipMemcpyHostToDevice, P->stream));
+  // the control block and table entry are copied from host memory that lives
+  // as long as the slot (the copies are stream-ordered)
+  std::memset(&S.ctl_staged, 0, sizeof(SlotCtl));
+  S.ctl_staged.target = target;
+  HIPCHK(hipMemcpyAsync(D.ctl, &S.ctl_staged, sizeof(SlotCtl), hipMemcpyHostToDevice, P->stream));
   HIPCHK(hipMemcpyAsync(P->d_table + s, &S.d, sizeof(SlotDesc), hipMemcpyHostToDevice, P->stream));
   HIPCHK(hipEventCreateWithFlags(&S.ev_done, hipEventDisableTiming));
   // polls read the control block on the copy stream; they must not see the
@@ -880,12 +874,7 @@ extern "C" int sph_pool_release(sph_pool* P, int32_t slot) {
   // later use of the memory on the same stream.  Launches from here on no
   // longer include the slot.
   P->comp_dirty = true;
-  if (P->have_alloc) {
-    dev_free(P, S.arena);
-  } else {
-    HIPCHK(hipStreamSynchronize(P->stream));
-    dev_free(P, S.arena);
-  }
+  dev_free(P, S.arena);
   if (S.ev_done) (void)hipEventDestroy(S.ev_done);
   if (S.ev_admit) (void)hipEventDestroy(S.ev_admit);
   P->used -= S.bytes;

@@ -40,6 +40,10 @@ struct SlotCtl {
   double relax_amax, relax_dt, relax_first;   // particle relaxation: max |F_p|, step
   int32_t relax_bounded, relax_pad;           // particles put back by the confinement
   double cum[NB][3];     // time integrals: axial torque, energy, heat
+  // Neumaier compensation terms of the running totals (cum, heat_total,
+  // diss_total): the reported value is the sum plus its compensation
+  double cum_c[NB][3];
+  double heat_c, diss_c;
   sph_report rep;
   sph_body_report brep[NB];
 };

@@ -865,7 +865,7 @@ __global__ __launch_bounds__(BLOCK) void k_wallvel(const SlotDesc* table, Launch
 }
 
 // ---------------------------------------------------------------------------
-// K: contact factor of every solid particle (Section 2.5, eq. 24) after a
+// K: contact factor of every solid particle (Section 2.7, eq. 24) after a
 // build at the current time, FP64: the sum of V_j W_wj (V_j = m / rho_j) over
 // the fluid particles within 2h of the solid particle, over the full-immersion
 // reference (the lattice kernel sum over the wall's outer half-space).  The
@@ -1584,12 +1584,19 @@ __global__ __launch_bounds__(FINAL_BLOCK) void k_final(const SlotDesc* table, La
     br.torque_axis = a[0] * br.torque[0] + a[1] * br.torque[1] + a[2] * br.torque[2];
     br.power = -S.bom[b] * br.torque_axis;
     br.heat_rate = r[6];
-    C->cum[b][0] += tad * br.torque_axis;
-    C->cum[b][1] += tad * br.power;
-    C->cum[b][2] += tad * br.heat_rate;
-    br.torque_axis_int = C->cum[b][0];
-    br.energy_int = C->cum[b][1];
-    br.heat_int = C->cum[b][2];
+    // running totals over up to 1e5 steps: compensated like the block sums
+    const double inc[3] = {tad * br.torque_axis, tad * br.power, tad * br.heat_rate};
+    double tot[3];
+    for (int k = 0; k < 3; ++k) {
+      KS acc{C->cum[b][k], C->cum_c[b][k]};
+      ks_add(acc, inc[k]);
+      C->cum[b][k] = acc.s;
+      C->cum_c[b][k] = acc.c;
+      tot[k] = acc.s + acc.c;
+    }
+    br.torque_axis_int = tot[0];
+    br.energy_int = tot[1];
+    br.heat_int = tot[2];
     qsum += br.heat_rate;
     finite = finite && isfinite(br.torque_axis) && isfinite(br.heat_rate) && isfinite(br.force[0]) &&
              isfinite(br.force[1]) && isfinite(br.force[2]);
@@ -1598,9 +1605,14 @@ __global__ __launch_bounds__(FINAL_BLOCK) void k_final(const SlotDesc* table, La
   C->step += 1;
   C->substeps += C->n_ac;
   const double hs = tad * qsum;
-  C->heat_total += hs;
   const double ds = S.diss ? tad * res[q_diss] : 0.0;
-  C->diss_total += ds;
+  KS heat{C->heat_total, C->heat_c}, diss{C->diss_total, C->diss_c};
+  ks_add(heat, hs);
+  ks_add(diss, ds);
+  C->heat_total = heat.s;
+  C->heat_c = heat.c;
+  C->diss_total = diss.s;
+  C->diss_c = diss.c;
   sph_report& R = C->rep;
   R.t = C->t;
   R.step = C->step;
@@ -1613,10 +1625,10 @@ __global__ __launch_bounds__(FINAL_BLOCK) void k_final(const SlotDesc* table, La
   R.mass_proxy = res[3];
   R.vmax = res[4];
   R.heat_step = hs;
-  R.heat_total = C->heat_total;
+  R.heat_total = heat.s + heat.c;
   R.substeps = C->substeps;
   R.diss_step = ds;
-  R.diss_total = C->diss_total;
+  R.diss_total = diss.s + diss.c;
   finite = finite && isfinite(res[1]) && isfinite(res[2]) && isfinite(res[3]) && isfinite(ds);
   if (!finite) C->flags |= F_NONFINITE;
   R.flags = (int32_t)C->flags;

@@ -52,3 +52,19 @@ def test_error_strings_and_arg_checks_without_gpu():
     assert "h_over_dp" in L.sph_last_error().decode()
     huge = sph.params_struct(c.params, grid_hi=(10.0, 0.1, 0.1))
     assert L.sph_create(ctypes.byref(huge), None, None, ctypes.byref(h)) == sph.SPH_ERR_ARG
+
+
+def test_an_allocator_is_required_without_gpu():
+    """The library allocates device memory only through the caller's
+    allocator: creating a solver or a pool without one is an argument error,
+    answered before any HIP call."""
+    from paper_2512_09904_amd import cases, sph
+    L = sph.lib()
+    c = cases.tank_c1()
+    P = sph.params_struct(c.params)
+    h = ctypes.c_void_p()
+    assert L.sph_create(ctypes.byref(P), None, None, ctypes.byref(h)) == sph.SPH_ERR_ARG
+    assert "allocator" in L.sph_last_error().decode()
+    assert not h.value
+    assert L.sph_pool_create(ctypes.c_size_t(1 << 30), 4, 0, None, None, ctypes.byref(h)) == sph.SPH_ERR_ARG
+    assert not h.value

@@ -5,6 +5,7 @@ and the independent fact it is pinned to (closed forms, lattice constants,
 brute force, special cases, invariants).  None of these values comes from the
 HIP library.
 """
+import dataclasses
 import json
 import math
 import os
@@ -494,7 +495,7 @@ def test_slab_conduction_matches_erf_solution(ora):
 
 
 # --------------------------------------------------------------------------
-# contact factor (Section 2.5, eq. 24)
+# contact factor (Section 2.7, eq. 24)
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("hod", [1.3, 1.0])
@@ -751,3 +752,50 @@ def test_wall_dummy_velocity_shepard(ora):
     assert np.allclose(vd[:3], 2 * us[:3] - b, rtol=0, atol=1e-14)
     vd, _ = ora.wall_dummy_velocity(dict(p, wall_visc=1), ora.Nbr(dict(p, wall_visc=1), xf, xs), v, us)
     assert np.array_equal(vd, us)
+
+
+# --------------------------------------------------------------------------
+# scales of the body reports: sums of the absolute values of their terms
+# --------------------------------------------------------------------------
+
+def test_body_scales_bound_the_reports(ora):
+    """On the tank, each body's scale (sum of |terms|) bounds the magnitude of
+    its force, torque and heat flow component by component (triangle
+    inequality), and is positive for every body with wall pairs."""
+    c = cases.tank_c1()
+    c.vf = 0.4 * np.sin(c.xf[:, [1, 2, 0]] * 150.0 + np.array([0.3, 1.1, 2.0]))
+    r = ora.State(c).step(want_rates=True)
+    sc = r["rates"]["bscale"]
+    for b, br in enumerate(r["bodies"]):
+        assert np.all(sc[b] > 0), b
+        assert np.all(np.abs(br["force"]) <= (sc[b, 0:3] + sc[b, 7:10]) * (1 + 1e-12))
+        assert np.all(np.abs(br["torque"]) <= (sc[b, 3:6] + sc[b, 10:13]) * (1 + 1e-12))
+        assert abs(br["heat_rate"]) <= sc[b, 6] * (1 + 1e-12)
+
+
+def test_body_scales_of_a_single_wall_pair(ora):
+    """One fluid particle sliding along one static wall particle, no gravity, at
+    the reference density: no pressure acts (p = P_R = 0, and the tangential
+    motion leaves the density unchanged), so the force, torque and heat flow
+    are each one pair term, and the scales equal their magnitudes exactly."""
+    base = cases.tank_c1()
+    dp = base.params["dp"]
+    p = dict(base.params)
+    p["gravity"] = (0.0, 0.0, 0.0)
+    p["grid_lo"] = (-0.05, -0.05, -0.05)
+    p["grid_hi"] = (0.05, 0.05, 0.05)
+    c = dataclasses.replace(
+        base, params=p,
+        bodies=[cases.Body(center=(0.004, -0.003, 0.002), axis=(0.0, 1.0, 0.0), omega=0.0, T=333.15, k=20.0)],
+        xf=np.array([[0.0, 0.0, 1.1 * dp]]), vf=np.array([[0.3, -0.2, 0.0]]), rhof=np.array([p["rho0"]]),
+        Tf=np.array([313.15]), xs0=np.zeros((1, 3)), ns0=np.array([[0.0, 0.0, 1.0]]),
+        body=np.zeros(1, np.int32))
+    o = ora.State(c, fixed_dt_ad=1e-5, fixed_nac=3)
+    r = o.step(want_rates=True)
+    sc = r["rates"]["bscale"][0]
+    br = r["bodies"][0]
+    assert np.all(sc[7:13] == 0.0)
+    assert np.array_equal(sc[0:3], np.abs(br["force"]))
+    assert np.array_equal(sc[3:6], np.abs(br["torque"]))
+    assert sc[6] == abs(br["heat_rate"]) and sc[6] > 0
+    assert np.abs(br["force"][0]) > 0 and np.abs(br["torque"]).max() > 0
