@@ -29,7 +29,6 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
-GATHER_PEAK = 256 * 2.4e9
 # the solver kernels' sources: the HBM-traffic record is valid only for these exact texts
 KERNEL_SRC = [os.path.join(ROOT, "paper_2512_09904_amd", "csrc", f)
               for f in ("sph_kernels.hip", "sph_device.h", "sph_internal.h")]
@@ -86,6 +85,18 @@ def sweep_bytes(kernel, nf, nsr, pf, ps, prec="mixed"):
     raise KeyError(kernel)
 
 
+def model_bytes(kernel, nf, pbar):
+    """Algorithmic bytes of one launch in the hot-path byte model: per fluid
+    particle, 20 B per ordered pair (a frozen pair record: neighbour index,
+    pair vector, kernel gradient) plus the particle's own state.  pbar is the
+    measured mean of ordered pairs (fluid and solid neighbours) per fluid
+    particle.  The kernel sum is fused into the build in that model, so it
+    has no entry of its own."""
+    per = {"build": 20.0 * pbar + 40.0, "visc_heat": 8.0 * pbar + 50.0,
+           "momentum": 20.0 * pbar + 60.0, "continuity": 20.0 * pbar + 60.0}.get(kernel)
+    return None if per is None else nf * per
+
+
 def build_candidates(s, case):
     """Candidate pairs of a 27-cell stencil search: for every fluid particle,
     the fluid and solid particles in its own and the 26 adjacent cells of
@@ -127,10 +138,12 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a), q)) if len(a) else None
 
 
-def cpu_baseline(case, steps=6):
-    """The FP64 oracle on the host cores, on a bounded sample of the same workload."""
+def cpu_baseline(case, steps=6, threads=None):
+    """The FP64 oracle on the host cores (or `threads` of them), on a bounded
+    sample of the same workload."""
     from oracle import oracle as O
     O.build(force=False)
+    prev = O.set_threads(threads) if threads else None
     mats = case.params.get("materials")
     if mats and case.material is not None:
         m = np.asarray(mats, dtype=np.float64)[case.material]
@@ -148,34 +161,37 @@ def cpu_baseline(case, steps=6):
         nac.append(r["n_ac"])
     dt = time.perf_counter() - t0
     sweeps = sum(2 + 2 * n for n in nac)
-    cores = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
+    cores = threads or int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
+    if prev:
+        O.set_threads(prev)
     return {"value": (pf + ps) * sweeps / dt, "unit": "particle-interactions/s", "cores": cores,
             "kind": "oracle", "steps_per_s": steps / dt,
             "sample": f"{steps} advection steps of the full gearbox proxy (dp 1.5 mm, {case.nf} fluid + {case.ns} "
                       f"solid particles) from the initial state, FP64 C/OpenMP oracle, {dt:.1f} s"}
 
 
-def serve_bench(args):
+def run_serving(n, steps, scale, budget_gb, slots, seeds, precision="mixed"):
     """Parameter-sweep serving: continuous batching vs one solve at a time.
 
     Requests: shaft speed U(150, 600) rad/s, immersion U(20, 60) mm, nu
-    U(0.5, 3)e-4, fluid count log-uniform 50k-2M, `serve_steps` advection steps
-    each.  Each request's service time alone is measured first (one slot);
-    arrivals are Poisson with rate 0.85 / mean service time; the
-    one-at-a-time server's latencies follow exactly from the measured service
-    times (FIFO); the batched server is run live.
+    U(0.5, 3)e-4, fluid count log-uniform 50k-2M times `scale`, `steps`
+    advection steps each.  Each request's service time alone is measured
+    first (one slot); arrivals are Poisson with rate 0.85 / mean service
+    time; the one-at-a-time server's latencies follow exactly from the
+    measured service times (FIFO); the batched server is run live on the
+    same requests and arrival times.
     """
     import torch
     from paper_2512_09904_amd import serve, sph
-    budget = int(args.serve_budget_gb * (1 << 30))
+    budget = int(budget_gb * (1 << 30))
     t0 = time.perf_counter()
-    reqs = serve.sweep_requests(n=args.serve_n, seed=64, steps=args.serve_steps, scale=args.serve_scale)
+    reqs = serve.sweep_requests(n=n, seed=64, steps=steps, scale=scale)
     log(f"generated {len(reqs)} requests in {time.perf_counter() - t0:.1f} s; "
         f"fluid {sum(r.case.nf for r in reqs)} total")
     # service time of each request alone
     svc = []
     for r in reqs:
-        pool = sph.Pool(budget, max_slots=1)
+        pool = sph.Pool(budget, max_slots=1, precision=precision)
         torch.cuda.synchronize()
         a = time.perf_counter()
         slot = pool.admit(r.case, r.steps)
@@ -195,7 +211,7 @@ def serve_bench(args):
     sbar = float(svc.mean())
     log(f"alone: mean service {sbar:.3f} s, total {svc.sum():.1f} s")
     results = []
-    for seed in range(64, 64 + args.serve_seeds):
+    for seed in range(64, 64 + seeds):
         rng = np.random.default_rng(seed)
         rate = 0.85 / sbar
         arr = np.cumsum(rng.exponential(1.0 / rate, len(reqs)))
@@ -211,7 +227,7 @@ def serve_bench(args):
         for r, a in zip(reqs, arr):
             r.arrival = float(a)
             r.admitted = r.finished = r.report = None
-        srv = serve.Server(budget, max_slots=args.serve_slots)
+        srv = serve.Server(budget, max_slots=slots, precision=precision)
         a = time.perf_counter()
         ndone = [0]
 
@@ -234,15 +250,40 @@ def serve_bench(args):
                                                particle_steps_per_s=float(sum(r.case.nf * r.steps for r in reqs) / fin.max()))))
         srv.close()
         log(json.dumps(results[-1]))
-    b = results[0]["batched"]
+    workload = (f"{len(reqs)} serving-tank requests (fluid {sum(r.case.nf for r in reqs)} in total), {steps} steps "
+                f"each, Poisson arrivals at 0.85/mean service, budget {budget_gb} GB, {slots} slots, particle "
+                f"scale {scale}")
+    return dict(workload=workload, mean_service_alone_s=sbar, seeds=results)
+
+
+def serve_bench(args):
+    """The full serving sweep as its own JSON line."""
+    res = run_serving(args.serve_n, args.serve_steps, args.serve_scale, args.serve_budget_gb, args.serve_slots,
+                      args.serve_seeds)
+    b = res["seeds"][0]["batched"]
     out = {"metric": "serving sweep: p50/p99 time-to-result and throughput, batched vs one at a time",
            "value": b["particle_steps_per_s"], "unit": "fluid particle-steps/s", "n_gpus": 1,
            "higher_is_better": True, "data": "synthetic", "dtype": "f32+f64",
-           "config": {"workload": f"{len(reqs)} serving-tank requests, {args.serve_steps} steps each, Poisson "
-                                  f"arrivals at 0.85/mean service, budget {args.serve_budget_gb} GB, "
-                                  f"{args.serve_slots} slots, particle scale {args.serve_scale}"},
-           "mean_service_alone_s": sbar, "seeds": results}
+           "config": {"workload": res["workload"]},
+           "mean_service_alone_s": res["mean_service_alone_s"], "seeds": res["seeds"]}
     print(json.dumps(out), flush=True)
+
+
+def serve_quick(args):
+    """A reduced serving sweep carried in the default line: fewer, smaller
+    requests than the full sweep, each arrival seed compared with one at a
+    time on the same requests."""
+    res = run_serving(args.quick_serve_n, args.quick_serve_steps, args.quick_serve_scale, args.serve_budget_gb,
+                      args.serve_slots, args.quick_serve_seeds)
+    rows = []
+    for e in res["seeds"]:
+        b, o = e["batched"], e["one_at_a_time"]
+        rows.append({"seed": e["seed"],
+                     "batched": {k: b[k] for k in ("p50_s", "p95_s", "p99_s", "particle_steps_per_s")},
+                     "one_at_a_time": {k: o[k] for k in ("p50_s", "p95_s", "p99_s", "particle_steps_per_s")},
+                     "peak_slots": e["peak_slots"], "results_equal_alone": e["results_equal_alone"]})
+    return {"workload": res["workload"], "unit": "s (time to result), fluid particle-steps/s",
+            "mean_service_alone_s": res["mean_service_alone_s"], "seeds": rows}
 
 
 def relax_bench(args):
@@ -433,6 +474,15 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=24.0)
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-seeds", type=int, default=1, help="arrival seeds (64, 65, ...)")
+    ap.add_argument("--no-serving", action="store_true", help="leave the reduced serving sweep out of the line")
+    ap.add_argument("--quick-serve-n", type=int, default=32)
+    ap.add_argument("--quick-serve-steps", type=int, default=300)
+    ap.add_argument("--quick-serve-scale", type=float, default=0.5)
+    ap.add_argument("--quick-serve-seeds", type=int, default=3)
+    ap.add_argument("--spin-up", type=int, default=200,
+                    help="untimed steps before the warm-up, past the impulsive start of the gears")
+    ap.add_argument("--cpu-one-thread-steps", type=int, default=1,
+                    help="advection steps of the one-thread oracle sample (0: none)")
     ap.add_argument("--relax", action="store_true",
                     help="particle relaxation of the 40-tooth gear body instead of the solver bench")
     ap.add_argument("--relax-iters", type=int, default=50)
@@ -494,6 +544,12 @@ def main():
     log(f"case: nf={case.nf} ns={case.ns} generated in {time.perf_counter() - t0:.1f} s")
     s = sph.Solver(case, precision=args.precision)
     log("initialised")
+    # untimed spin-up past the impulsive start (acoustic transients of the
+    # sudden start decay within a few box crossings at c0, about 60 steps)
+    if args.spin_up:
+        s.step(args.spin_up)
+        s.reduce()
+        log(f"spin-up: {args.spin_up} steps")
     s.step(args.warmup)
     r0 = s.reduce()
     pf0, ps0 = pair_counts(s, case.nf)
@@ -516,7 +572,7 @@ def main():
     value = pairs * (2 * args.steps + 2 * nsub) / wall
     log(f"graph: {ms_per_step:.3f} ms/step, n_ac={n_ac}, pairs/sweep={pairs:.3e}, {value:.3e} interactions/s")
 
-    # timed region 2: the same steps launched eagerly with HIP events per kernel
+    # timed region 2: the next steps launched eagerly with HIP events per kernel
     s.set_timing(True)
     t0 = time.perf_counter()
     nac_steps = []
@@ -533,28 +589,39 @@ def main():
         kt[k + "_all"] = kt[k]
         kt[k] = np.concatenate([kt[k][q * nl: q * nl + nac_steps[q]] for q in range(args.timed_steps)])
     pf2, ps2 = pair_counts(s, case.nf)
+    pbar = (pf2 + ps2) / case.nf
     per_step_kernel_ms = {k: float(kt[k + "_all" if k + "_all" in kt else k].sum() / args.timed_steps)
                           for k in sph.KERNELS if len(kt[k])}
     log("per-step kernel ms:", json.dumps({k: round(v, 4) for k, v in per_step_kernel_ms.items()}))
     nsr = distinct_wall_particles(s, case.nf)
+    # lane gathers of neighbour records per launch (16-B records in mixed precision)
+    gathers = {"momentum": 2 * (pf2 + ps2), "continuity": 2 * pf2 + 3 * ps2,
+               "visc_heat": 3 * (pf2 + ps2), "sumw": 2 * (pf2 + ps2)}
     kern = {}
     for k in ("build", "sumw", "visc_heat", "momentum", "continuity"):
-        b = sweep_bytes(k, case.nf, nsr, pf2, ps2, args.precision)
         ms = float(np.mean(kt[k]))
-        kern[k] = {"bytes_per_launch": int(b), "avg_launch_ms": round(ms, 5),
-                   "achieved_GBs": round(b / (ms * 1e-3) / 1e9, 1),
-                   "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                   "ms_per_step": round(per_step_kernel_ms[k], 4)}
-    # the build is a search, bound by vector FP64 arithmetic: its algorithmic
-    # work is 8 FP64 flops (three differences, three squares, two sums) per
-    # candidate of the 27-cell stencil
+        e = {"avg_launch_ms": round(ms, 5), "ms_per_step": round(per_step_kernel_ms[k], 4)}
+        mb = model_bytes(k, case.nf, pbar)
+        if mb is not None:
+            e["model_bytes_per_launch"] = int(mb)
+            e["model_GBs"] = round(mb / (ms * 1e-3) / 1e9, 1)
+            e["model_frac"] = round(mb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        b = sweep_bytes(k, case.nf, nsr, pf2, ps2, args.precision)
+        e["index_bytes_per_launch"] = int(b)
+        e["index_GBs"] = round(b / (ms * 1e-3) / 1e9, 1)
+        if k in gathers:
+            e["lane_gathers_per_s"] = gathers[k] / (ms * 1e-3)
+        kern[k] = e
+    # the build is a search: 8 FP64 flops (three differences, three squares,
+    # two sums) per candidate of the 27-cell stencil
     cand = build_candidates(s, case)
     b_flops = 8.0 * cand
     kern["build"]["candidates"] = cand
     kern["build"]["fp64_tflops"] = round(b_flops / (kern["build"]["avg_launch_ms"] * 1e-3) / 1e12, 3)
     kern["build"]["fp64_frac"] = round(kern["build"]["fp64_tflops"] / FP64_PEAK_TFLOPS, 4)
-    # the dominant kernel: the largest share of the step's device time
-    dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
+    # the dominant kernel: the largest share of the step's device time among
+    # the pair sweeps of the byte model
+    dom = max((k for k in kern if "model_bytes_per_launch" in kern[k]), key=lambda k: kern[k]["ms_per_step"])
     avg_ms = kern[dom]["avg_launch_ms"]
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -567,34 +634,37 @@ def main():
         if (tr.get("kernel_sha") == kernel_hash() and tr.get("precision") == args.precision
                 and tr.get("workload") == wl):
             traffic = ent.get("bytes_per_launch")
-    if dom == "build":
-        roofline = {"bound": "alu", "achieved": kern["build"]["fp64_tflops"], "peak": FP64_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": kern["build"]["fp64_frac"], "traffic": traffic, "kernel": "k_build",
-                    "flops_per_launch": b_flops, "avg_launch_ms": avg_ms}
-    else:
-        achieved = kern[dom]["achieved_GBs"]
-        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": "k_" + dom,
-                    "bytes_per_launch": int(kern[dom]["bytes_per_launch"]), "avg_launch_ms": avg_ms}
-        # the sweeps are limited by scattered 16-byte gathers, which the vector
-        # memory unit serves at about one lane per clock per CU
-        gathers = {"momentum": 2 * (pf2 + ps2), "continuity": 2 * pf2 + 3 * ps2,
-                   "visc_heat": 3 * (pf2 + ps2), "sumw": 2 * (pf2 + ps2)}.get(dom)
-        if gathers:
-            rate = gathers / (avg_ms * 1e-3)
-            roofline["gather_rate"] = {"achieved": rate, "peak": GATHER_PEAK, "unit": "lane gathers/s",
-                                       "frac": round(rate / GATHER_PEAK, 4), "gathers_per_launch": int(gathers),
-                                       "peak_basis": "one scattered lane per clock per CU, 256 CUs at 2.4 GHz "
-                                                     "(texture-addresser and L1 counters)"}
+    achieved = kern[dom]["model_GBs"]
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": "k_" + dom,
+                "bytes_per_launch": kern[dom]["model_bytes_per_launch"], "avg_launch_ms": avg_ms,
+                "basis": f"pair-record byte model: {case.nf} fluid particles x (20 B x {pbar:.2f} mean ordered "
+                         f"pairs + 60 B) per launch",
+                "index_design": {"bytes_per_launch": kern[dom]["index_bytes_per_launch"],
+                                 "GBs": kern[dom]["index_GBs"],
+                                 "basis": "bytes this design streams: 4-B row indices, each particle and wall "
+                                          "record once"},
+                "lane_gathers_per_s": kern[dom].get("lane_gathers_per_s")}
     sweep_lat = {k: {"p50_ms": round(pct(kt[k], 50), 5), "p99_ms": round(pct(kt[k], 99), 5), "n": len(kt[k])}
                  for k in ("build", "visc_heat", "momentum", "continuity") if len(kt[k])}
+    s.close()
+
+    serving = None
+    if not args.no_serving:
+        log("serving: reduced parameter sweep, batched vs one at a time")
+        serving = serve_quick(args)
 
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on the host")
         cpu = cpu_baseline(case, args.cpu_steps)
         log(f"cpu baseline: {cpu['value']:.3e} interactions/s on {cpu['cores']} threads")
+        if args.cpu_one_thread_steps:
+            one = cpu_baseline(case, args.cpu_one_thread_steps, threads=1)
+            cpu["one_thread"] = {"value": one["value"], "steps_per_s": one["steps_per_s"], "sample": one["sample"]}
+            log(f"cpu baseline, one thread: {one['value']:.3e} interactions/s")
 
+    hist = {str(k): int(v) for k, v in zip(*np.unique(nac_steps, return_counts=True))}
     out = {
         "metric": "particle-interactions/s & steps/s at 1M particles; p50/p99 sweep latency",
         "value": value,
@@ -614,16 +684,20 @@ def main():
                                f"-{2 * om:.0f}/{om:.0f} rad/s, {imm * 1e3:.0f} mm immersion, nu={nu:g}"
                                + (", viscous dissipation heating" if args.viscous_heating else "")
                                + (", two fluid materials" if args.materials else ""),
-                   "n_fluid": case.nf, "n_solid": case.ns, "n_ac_last": n_ac, "pairs_per_sweep": int(pairs),
-                   "pair_sweeps_per_step": round(sweeps, 3), "precision": args.precision, "parallelism": "single GPU"},
+                   "n_fluid": case.nf, "n_solid": case.ns, "spin_up_steps": args.spin_up,
+                   "pairs_per_sweep": int(pairs), "mean_pairs_per_fluid_particle": round(pbar, 3),
+                   "pair_sweeps_per_step": round(sweeps, 3), "precision": args.precision,
+                   "parallelism": "single GPU"},
+        "substeps": {"timed_mean_n_ac": round(nsub / args.steps, 3), "n_ac_first": r0["n_ac"], "n_ac_last": n_ac,
+                     "event_timed_n_ac_histogram": hist},
         "sweep_latency": sweep_lat,
         "event_timed": {"steps": args.timed_steps, "ms_per_step": 1e3 * wall2 / args.timed_steps,
                         "kernel_ms_per_step": {k: round(v, 4) for k, v in per_step_kernel_ms.items()},
                         "kernels": kern, "wall_particles_in_rows": nsr},
         "roofline": roofline,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
-    s.close()
     print(json.dumps(out), flush=True)
 
 

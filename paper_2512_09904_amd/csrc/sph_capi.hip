@@ -200,7 +200,7 @@ static size_t carve(const Plan& P, void* base, SlotDesc* d) {
   C.take(D.start_s, (nc + 1) * 4);
   C.take(D.bsum_f, nbc * 4);
   C.take(D.bsum_s, nbc * 4);
-  C.take(D.vmax_part, nbf * 4);
+  C.take(D.vmax_part, nbf * 8);
   C.take(D.visc_part, nbf * NB * 7 * 8);
   C.take(D.press_part, nbf * NB * 6 * 8);
   C.take(D.glob_part, nbf * (NGLOB + 1) * 8);

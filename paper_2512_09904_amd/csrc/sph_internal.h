@@ -110,7 +110,7 @@ struct SlotDesc {
   // cells
   uint32_t *rank, *cnt_f, *cnt_s, *start_f, *start_s, *bsum_f, *bsum_s;
   // per fluid-block partials, quantity-major ([quantity][block])
-  float *vmax_part;
+  double *vmax_part;    // per fluid block: max |v| (FP64) for the time step
   double *visc_part;    // [NB * 7]: force(3) torque(3) heat
   double *press_part;   // [NB * 6]: sum over sub-steps of force(3) torque(3)
   double *glob_part;    // [NGLOB + 1]: the globals, then the dissipated power

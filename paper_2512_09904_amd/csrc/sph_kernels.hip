@@ -229,10 +229,10 @@ __global__ __launch_bounds__(BLOCK) void k_fold(const SlotDesc* table, LaunchTab
   typedef typename P::Temp Temp;
   typedef typename P::Pos4 Pos4;
   typedef typename P::Real4 Real4;
-  __shared__ float red[BLOCK / WAVE];
+  __shared__ double red[BLOCK / WAVE];
   SLOT_PROLOGUE(DOM_FLUID);
   const int i = lb * BLOCK + threadIdx.x;
-  float vm = 0.0f;
+  double vm = 0.0;
   uint32_t r = 0;
   if (i < S.nf) {
     Pos4 x = gpc<Pos4>(S.xa)[i];
@@ -253,19 +253,21 @@ __global__ __launch_bounds__(BLOCK) void k_fold(const SlotDesc* table, LaunchTab
                         isfinite((double)v.x) && isfinite((double)v.y) && isfinite((double)v.z) &&
                         isfinite((double)v.w) && isfinite((double)T);
     if (!finite) raise_flag(S, F_NONFINITE);
-    const float v0 = (float)v.x, v1 = (float)v.y, v2 = (float)v.z;
-    vm = sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
+    // |v| in FP64 from the stored components (eq. 25 takes the max)
+    const double v0 = (double)v.x, v1 = (double)v.y, v2 = (double)v.z;
+    vm = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
     int c[3];
     if (!cell_coords<Pos>(S, x.x, x.y, x.z, c)) raise_flag(S, F_DOMAIN);
     r = S.rank[cell_linear(S, c[0], c[1], c[2])];
     S.fcell[i] = r;
   }
   run_atomic_inc(S.cnt_f, r, i < S.nf);
-  vm = wave_max(vm);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) vm = fmax(vm, __shfl_xor(vm, o, WAVE));
   if (threadIdx.x % WAVE == 0) red[threadIdx.x / WAVE] = vm;
   __syncthreads();
   if (threadIdx.x == 0)
-    S.vmax_part[lb] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    S.vmax_part[lb] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
 // ---------------------------------------------------------------------------
@@ -916,17 +918,18 @@ __global__ __launch_bounds__(BLOCK) void k_contact(const SlotDesc* table, Launch
 // and the bodies' tip speeds; n_ac is capped by shortening dt_ad.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(BLOCK) void k_dt(const SlotDesc* table, LaunchTab tab) {
-  __shared__ float red[BLOCK / WAVE];
+  __shared__ double red[BLOCK / WAVE];
   SLOT_PROLOGUE(DOM_SLOT);
   (void)lb;
   const int n = S.nblk[DOM_FLUID];
-  float m = 0.0f;
-  for (int k = threadIdx.x; k < n; k += BLOCK) m = fmaxf(m, S.vmax_part[k]);
-  m = wave_max(m);
+  double m = 0.0;
+  for (int k = threadIdx.x; k < n; k += BLOCK) m = fmax(m, S.vmax_part[k]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, WAVE));
   if (threadIdx.x % WAVE == 0) red[threadIdx.x / WAVE] = m;
   __syncthreads();
   if (threadIdx.x != 0) return;
-  double vm = (double)fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  double vm = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
   for (int b = 0; b < S.nbody; ++b) vm = fmax(vm, S.btip[b]);
   SlotCtl* C = S.ctl;
   double tad, dt;
