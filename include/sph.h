@@ -218,6 +218,26 @@ int sph_get_timing(sph_solver* s, int32_t kernel, int32_t max, float* ms, int32_
  * (SPH_ERR_DOMAIN / _NONFINITE / _CAPACITY), as sph_reduce returns it. */
 int sph_contact_factor(sph_solver* s, double* zeta, double* body_mean);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops that must not call hipMalloc or the host heap): sph_contact_factor
+ * with device outputs, no allocation of any kind on success and no
+ * synchronisation.  zeta_dev: device buffer of ns doubles, the same values as
+ * sph_contact_factor's zeta, bit for bit, in the order of sph_set_solid (may
+ * be NULL); body_mean_dev: device buffer of nbody doubles, each body's mean,
+ * reduced on the device in a fixed order with compensated sums (equal to
+ * sph_contact_factor's host means to about 1e-15 relative; may be NULL).
+ * Both are written asynchronously on the solver's stream: the caller
+ * synchronises before reading them.  The per-block partial sums live in a
+ * static device array of the library (2 MiB, one per GPU, held until the
+ * process ends): at most SPH_CONTACT_NOALLOC_MAX_SOLID solid particles, else
+ * SPH_ERR_ARG.  Every call on a GPU shares that array, so calls that overlap
+ * on one GPU (two streams, two threads) race; calls in stream order do not.
+ * SPH_ERR_STATE before sph_init.  A latched fault is not checked here (that
+ * would synchronise): the kernels of a faulted solve leave the outputs
+ * unwritten and the next sph_reduce returns the fault. */
+#define SPH_CONTACT_NOALLOC_MAX_SOLID (4u << 20)
+int sph_contact_factor_noalloc(sph_solver* s, double* zeta_dev, double* body_mean_dev);
+
 /* An analytic shape bounding the particle relaxation (Section 2.2, eq. 5):
  * its surface is the zero contour of the signed distance phi, negative inside.
  * Cylinder and gear have their axis along y through the centre.

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -16,9 +17,17 @@
 using namespace sphk;
 
 static thread_local std::string g_err;
+static thread_local const char* g_err_lit = nullptr;   // a message of fail_lit (no copy)
 
 static int fail(int code, const std::string& msg) {
   g_err = msg;
+  g_err_lit = nullptr;
+  return code;
+}
+
+// the same for a string literal, without copying it (the allocation-free path)
+static int fail_lit(int code, const char* msg) {
+  g_err_lit = msg;
   return code;
 }
 
@@ -43,7 +52,7 @@ extern "C" const char* sph_error_string(int code) {
   }
 }
 
-extern "C" const char* sph_last_error(void) { return g_err.c_str(); }
+extern "C" const char* sph_last_error(void) { return g_err_lit ? g_err_lit : g_err.c_str(); }
 
 // ---------------------------------------------------------------------------
 // slot plan: validated sizes and the arena layout
@@ -422,21 +431,29 @@ static int launch_rx(sph_pool* P, const LaunchTab& tab, int kid, int iter, const
     if (r_) return r_;     \
   } while (0)
 
-static int enqueue_sort_build(sph_pool* P, const LaunchTab& T) {
-  LCHK(launch(P, T, SPH_K_CLEAR, 0, 0));
-  LCHK(launch(P, T, SPH_K_POSE, 1, 0));
-  LCHK(launch(P, T, SPH_K_FOLD, 0, 0));
-  LCHK(launch(P, T, SPH_K_SCAN1, 0, 0));
-  LCHK(launch(P, T, SPH_K_SCAN2, 0, 0));
-  LCHK(launch(P, T, SPH_K_SCAN3, 0, 0));
-  LCHK(launch(P, T, SPH_K_SCATTER, 0, 0));
-  LCHK(launch(P, T, SPH_K_SCATTER, 1, 0));
-  LCHK(launch(P, T, SPH_K_CELLSORT, 0, 0));
-  LCHK(launch(P, T, SPH_K_REORDER, 0, 0));
-  LCHK(launch(P, T, SPH_K_REORDER, 1, 0));
-  LCHK(launch(P, T, SPH_K_BUILD, 0, 0));
-  LCHK(launch(P, T, SPH_K_SUMW, 0, 0));
-  LCHK(launch(P, T, SPH_K_WALLVEL, 1, 0));
+// timed = false: no event timing and no heap allocation on success (the
+// allocation-free entry point)
+static int enqueue_sort_build(sph_pool* P, const LaunchTab& T, bool timed = true) {
+  auto L = [&](int kid, int which) {
+    if (timed) return launch(P, T, kid, which, 0);
+    if (launch_kernel(P->prec, kid, which, 0, P->d_table, T, P->stream) != hipSuccess)
+      return fail_lit(SPH_ERR_HIP, "kernel launch failed");
+    return (int)SPH_OK;
+  };
+  LCHK(L(SPH_K_CLEAR, 0));
+  LCHK(L(SPH_K_POSE, 1));
+  LCHK(L(SPH_K_FOLD, 0));
+  LCHK(L(SPH_K_SCAN1, 0));
+  LCHK(L(SPH_K_SCAN2, 0));
+  LCHK(L(SPH_K_SCAN3, 0));
+  LCHK(L(SPH_K_SCATTER, 0));
+  LCHK(L(SPH_K_SCATTER, 1));
+  LCHK(L(SPH_K_CELLSORT, 0));
+  LCHK(L(SPH_K_REORDER, 0));
+  LCHK(L(SPH_K_REORDER, 1));
+  LCHK(L(SPH_K_BUILD, 0));
+  LCHK(L(SPH_K_SUMW, 0));
+  LCHK(L(SPH_K_WALLVEL, 1));
   return SPH_OK;
 }
 
@@ -454,6 +471,16 @@ static int enqueue_step(sph_pool* P, const LaunchTab& T, int nac) {
   LCHK(launch(P, T, SPH_K_END, 0, 0));
   LCHK(launch(P, T, SPH_K_FINAL, 0, 0));
   return SPH_OK;
+}
+
+// the launch table of slot `slot` alone (no heap allocation)
+static void tab_one(sph_pool* P, int slot, LaunchTab& T) {
+  std::memset(&T, 0, sizeof(T));
+  T.n = 1;
+  T.slot[0] = slot;
+  if (P->slots[slot].d.diss) T.flags |= TAB_DISS;
+  if (P->slots[slot].d.nmat > 1) T.flags |= TAB_MAT;
+  for (int d = 0; d < NDOM; ++d) T.blk0[d][1] = P->slots[slot].plan.nblk[d];
 }
 
 static void tab_for(sph_pool* P, const std::vector<int>& slots, LaunchTab& T) {
@@ -1018,10 +1045,44 @@ extern "C" int sph_set_solid(sph_solver* s, int64_t n, const double* x0, const d
   return SPH_OK;
 }
 
+// ---------------------------------------------------------------------------
+// scratch of the allocation-free contact factor: per-block, per-body partial
+// sums (value and count) of at most SPH_CONTACT_NOALLOC_MAX_SOLID solid
+// particles, 2 MiB.  Each GPU holds its own copy until the process ends;
+// every call on a GPU shares it, so calls that overlap on one GPU race.  In
+// host code `scratch` is only a host-side stand-in: the device address comes
+// from hipGetSymbolAddress, once per device, and only that address is used.
+// ---------------------------------------------------------------------------
+constexpr int NOALLOC_MAX_BLOCKS = (int)(SPH_CONTACT_NOALLOC_MAX_SOLID / BLOCK);
+static __device__ __align__(256) double scratch[2 * NB * NOALLOC_MAX_BLOCKS];
+constexpr int MAX_DEVICES = 64;
+static double* g_scratch[MAX_DEVICES] = {};
+static std::mutex g_scratch_mu;
+
+// the device address of `scratch` on the current device (looked up once)
+static int scratch_address(double** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail_lit(SPH_ERR_HIP, "hipGetDevice failed");
+  if (dev < 0 || dev >= MAX_DEVICES) return fail_lit(SPH_ERR_STATE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+      return fail_lit(SPH_ERR_HIP, "hipGetSymbolAddress(scratch) failed");
+    g_scratch[dev] = (double*)p;
+  }
+  *out = g_scratch[dev];
+  return SPH_OK;
+}
+
 extern "C" int sph_init(sph_solver* s) {
   if (!s) return fail(SPH_ERR_ARG, "NULL solver");
   if (s->inited) return fail(SPH_ERR_STATE, "already initialised");
   if (s->nbody < 1 || s->nf < 1) return fail(SPH_ERR_STATE, "bodies and fluid must be set first");
+  {
+    double* scr = nullptr;   // set-up of the allocation-free entry point's scratch on this device
+    LCHK(scratch_address(&scr));
+  }
   int32_t slot = -1;
   int rc = admit(s->pool, &s->p, s->nbody, s->bodies, s->nf, s->x.data(), s->v.data(), s->rho.data(), s->T.data(),
                  s->material.empty() ? nullptr : s->material.data(), s->ns, s->x0.data(), s->n0.data(),
@@ -1097,6 +1158,24 @@ extern "C" int sph_contact_factor(sph_solver* s, double* zeta, double* body_mean
       body_mean[b] = cnt ? (sum + comp) / (double)cnt : 0.0;
     }
   }
+  return SPH_OK;
+}
+
+extern "C" int sph_contact_factor_noalloc(sph_solver* s, double* zeta_dev, double* body_mean_dev) {
+  if (!s || !s->inited) return fail_lit(SPH_ERR_STATE, "not initialised");
+  sph_pool* P = s->pool;
+  const SlotHost& S = P->slots[0];
+  if (S.plan.ns > (int64_t)SPH_CONTACT_NOALLOC_MAX_SOLID)
+    return fail_lit(SPH_ERR_ARG, "more solid particles than SPH_CONTACT_NOALLOC_MAX_SOLID");
+  if (S.plan.nblk[DOM_SOLID] > NOALLOC_MAX_BLOCKS) return fail_lit(SPH_ERR_ARG, "solid blocks beyond the scratch");
+  double* scr = nullptr;
+  LCHK(scratch_address(&scr));
+  LaunchTab T;
+  tab_one(P, 0, T);
+  LCHK(enqueue_sort_build(P, T, false));
+  if (launch_contact(P->prec, P->d_table, T, zeta_dev, body_mean_dev ? scr : nullptr, body_mean_dev, P->stream) !=
+      hipSuccess)
+    return fail_lit(SPH_ERR_HIP, "contact factor launch failed");
   return SPH_OK;
 }
 

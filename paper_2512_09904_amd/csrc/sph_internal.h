@@ -135,4 +135,11 @@ hipError_t launch_kernel(int prec, int kid, int which, int sub, const SlotDesc* 
                          const LaunchTab& tab, hipStream_t stream);
 int grid_domain(int kid, int which);
 
+// The contact factor (k_contact) of one slot into zout (caller's order) with,
+// when part is given, per-block, per-body partial sums into part (2 x nbody x
+// the slot's solid blocks doubles) and, when mean is given, the per-body
+// means reduced from them (k_contact_mean).
+hipError_t launch_contact(int prec, const SlotDesc* table, const LaunchTab& tab, double* zout, double* part,
+                          double* mean, hipStream_t stream);
+
 }  // namespace sphk

@@ -874,15 +874,23 @@ __global__ __launch_bounds__(BLOCK) void k_wallvel(const SlotDesc* table, Launch
 // solid particle scans its own 27 fluid cells; an observable, not a step
 // kernel.
 // ---------------------------------------------------------------------------
+// zout: the values in the caller's original order (S.zeta when null); part
+// (optional, nblk blocks): per-block, per-body sums of the values and of the
+// solid-particle counts, quantity-major ([(2 b + k) * nblk + block], k = 0
+// sum, 1 count), reduced by k_contact_mean.
 template <class P>
-__global__ __launch_bounds__(BLOCK) void k_contact(const SlotDesc* table, LaunchTab tab) {
+__global__ __launch_bounds__(BLOCK) void k_contact(const SlotDesc* table, LaunchTab tab, double* zout,
+                                                   double* part) {
 #pragma clang fp contract(off)
   typedef typename P::Pos Pos;
   typedef typename P::Pos4 Pos4;
   typedef typename P::Real4 Real4;
+  __shared__ double lds[BLOCK / WAVE][NB][2];
   SLOT_PROLOGUE(DOM_SOLID);
   const int w = lb * BLOCK + threadIdx.x;
-  if (w >= S.ns) return;
+  double zw = 0.0;
+  int bw = -1;
+  if (w < S.ns) {
   const GLB Pos4* xa = gpc<Pos4>(S.xa);
   const GLB Real4* vr = gpc<Real4>(S.vr);
   const GLB uint32_t* rank = gpc<uint32_t>(S.rank);
@@ -910,7 +918,51 @@ __global__ __launch_bounds__(BLOCK) void k_contact(const SlotDesc* table, Launch
           }
         }
       }
-  S.zeta[S.sid[w]] = z / S.zref;   // in the caller's original order (sid is a permutation)
+  zw = z / S.zref;
+  bw = S.body[w];
+  (zout ? zout : S.zeta)[S.sid[w]] = zw;   // in the caller's original order (sid is a permutation)
+  }
+  if (!part) return;
+  // per-body block sums in a fixed order: lanes by shuffle, then the four waves
+  const int wv = threadIdx.x / WAVE, ln = threadIdx.x % WAVE;
+  for (int b = 0; b < S.nbody; ++b) {
+    const double sv = wave_sum(bw == b ? zw : 0.0);
+    const double cv = (double)__popcll(__ballot(bw == b));
+    if (ln == 0) {
+      lds[wv][b][0] = sv;
+      lds[wv][b][1] = cv;
+    }
+  }
+  __syncthreads();
+  const int nblk = S.nblk[DOM_SOLID];
+  if (threadIdx.x < 2 * S.nbody) {
+    const int b = threadIdx.x / 2, k = threadIdx.x % 2;
+    part[(size_t)threadIdx.x * nblk + lb] = ((lds[0][b][k] + lds[1][b][k]) + lds[2][b][k]) + lds[3][b][k];
+  }
+}
+
+// Mean contact factor of every body from k_contact's block partials: each
+// quantity's partials summed over the blocks in a fixed order with Neumaier
+// compensation (one wavefront per quantity), then sum / count (0 for a body
+// without solid particles).  One block per slot.
+__global__ __launch_bounds__(BLOCK) void k_contact_mean(const SlotDesc* table, LaunchTab tab,
+                                                        const double* part, double* mean) {
+  __shared__ double res[NB][2];
+  SLOT_PROLOGUE(DOM_SLOT);
+  (void)lb;
+  const int nblk = S.nblk[DOM_SOLID];
+  const int wv = threadIdx.x / WAVE, ln = threadIdx.x % WAVE;
+  for (int q = wv; q < 2 * S.nbody; q += BLOCK / WAVE) {
+    KS ks{0.0, 0.0};
+    for (int k = ln; k < nblk; k += WAVE) ks_add(ks, part[(size_t)q * nblk + k]);
+    const KS t = wave_ks(ks);
+    if (ln == 0) res[q / 2][q % 2] = t.s + t.c;
+  }
+  __syncthreads();
+  if (threadIdx.x < S.nbody) {
+    const int b = threadIdx.x;
+    mean[b] = res[b][1] > 0.0 ? res[b][0] / res[b][1] : 0.0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1683,7 +1735,7 @@ static hipError_t launch_p(int kid, int which, int sub, const SlotDesc* T, const
     case SPH_K_REORDER: hipLaunchKernelGGL(k_reorder<P>, g, b, 0, st, T, L, which); break;
     case SPH_K_BUILD: hipLaunchKernelGGL(k_build<P>, g, b, 0, st, T, L); break;
     case SPH_K_SUMW: hipLaunchKernelGGL(k_sumw<P>, g, b, 0, st, T, L); break;
-    case SPH_K_CONTACT: hipLaunchKernelGGL(k_contact<P>, g, b, 0, st, T, L); break;
+    case SPH_K_CONTACT: hipLaunchKernelGGL(k_contact<P>, g, b, 0, st, T, L, nullptr, nullptr); break;
     case SPH_K_WALLVEL: hipLaunchKernelGGL(k_wallvel<P>, g, b, 0, st, T, L); break;
     case SPH_K_DT: hipLaunchKernelGGL(k_dt, g, b, 0, st, T, L); break;
     case SPH_K_VISC_HEAT:
@@ -1703,6 +1755,27 @@ static hipError_t launch_p(int kid, int which, int sub, const SlotDesc* T, const
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <class P>
+static hipError_t launch_contact_p(const SlotDesc* T, const LaunchTab& L, double* zout, double* part,
+                                   double* mean, hipStream_t st) {
+  const int nblk = L.blk0[DOM_SOLID][L.n];
+  if (nblk > 0) hipLaunchKernelGGL(k_contact<P>, dim3(nblk), dim3(BLOCK), 0, st, T, L, zout, part);
+  if (mean && L.blk0[DOM_SLOT][L.n] > 0)
+    hipLaunchKernelGGL(k_contact_mean, dim3(L.blk0[DOM_SLOT][L.n]), dim3(BLOCK), 0, st, T, L,
+                       (const double*)part, mean);
+  return hipGetLastError();
+}
+
+hipError_t launch_contact(int prec, const SlotDesc* table, const LaunchTab& tab, double* zout, double* part,
+                          double* mean, hipStream_t stream) {
+  switch (prec) {
+    case SPH_PREC_MIXED: return launch_contact_p<PMixed>(table, tab, zout, part, mean, stream);
+    case SPH_PREC_FP64: return launch_contact_p<PF64>(table, tab, zout, part, mean, stream);
+    case SPH_PREC_FP32: return launch_contact_p<PF32>(table, tab, zout, part, mean, stream);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_kernel(int prec, int kid, int which, int sub, const SlotDesc* table,

@@ -117,7 +117,7 @@ def lib():
 
 
 EXPORTS = ["sph_error_string", "sph_last_error", "sph_create", "sph_set_bodies", "sph_set_fluid", "sph_set_solid",
-           "sph_init", "sph_step", "sph_reduce", "sph_contact_factor", "sph_relax", "sph_get_fluid", "sph_set_graph", "sph_set_timing",
+           "sph_init", "sph_step", "sph_reduce", "sph_contact_factor", "sph_contact_factor_noalloc", "sph_relax", "sph_get_fluid", "sph_set_graph", "sph_set_timing",
            "sph_get_timing", "sph_dump_size", "sph_debug_dump", "sph_debug_poke_velocity", "sph_destroy",
            "sph_bytes_required", "sph_pool_create", "sph_pool_admit", "sph_pool_step", "sph_pool_poll",
            "sph_pool_get_fluid", "sph_pool_release", "sph_pool_usage", "sph_pool_set_graph", "sph_pool_destroy"]
@@ -286,6 +286,19 @@ class Solver:
         m = np.zeros(max(self.nbody, 1))
         check(lib().sph_contact_factor(self.h, _p(z), _p(m)), "sph_contact_factor")
         return z[: self.ns], m[: self.nbody]
+
+    def contact_factor_noalloc(self, zeta=None, body_mean=None):
+        """The allocation-free contact factor: writes into caller-owned torch
+        float64 device tensors (ns and nbody elements, either may be None)
+        on the solver's stream, asynchronously; the caller synchronises."""
+        import torch
+        for t, n in ((zeta, self.ns), (body_mean, self.nbody)):
+            if t is not None and (t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous()
+                                  or t.numel() < n):
+                raise ValueError("outputs must be contiguous float64 device tensors of the right size")
+        check(lib().sph_contact_factor_noalloc(self.h, C.c_void_p(zeta.data_ptr() if zeta is not None else 0),
+                                               C.c_void_p(body_mean.data_ptr() if body_mean is not None else 0)),
+              "sph_contact_factor_noalloc")
 
     def relax(self, shape: dict, iterations: int):
         """Physics-driven relaxation (Section 2.2) of the fluid particles inside
