@@ -479,8 +479,9 @@ def main():
     ap.add_argument("--quick-serve-steps", type=int, default=300)
     ap.add_argument("--quick-serve-scale", type=float, default=0.5)
     ap.add_argument("--quick-serve-seeds", type=int, default=3)
-    ap.add_argument("--spin-up", type=int, default=200,
-                    help="untimed steps before the warm-up, past the impulsive start of the gears")
+    ap.add_argument("--spin-up", type=int, default=100,
+                    help="untimed steps before the warm-up, past the acoustic transient of the gears' "
+                         "impulsive start (about 60 steps)")
     ap.add_argument("--cpu-one-thread-steps", type=int, default=1,
                     help="advection steps of the one-thread oracle sample (0: none)")
     ap.add_argument("--relax", action="store_true",
@@ -544,8 +545,8 @@ def main():
     log(f"case: nf={case.nf} ns={case.ns} generated in {time.perf_counter() - t0:.1f} s")
     s = sph.Solver(case, precision=args.precision)
     log("initialised")
-    # untimed spin-up past the impulsive start (acoustic transients of the
-    # sudden start decay within a few box crossings at c0, about 60 steps)
+    # untimed spin-up past the impulsive start (the acoustic transient of the
+    # sudden start crosses the box a few times at c0 within about 60 steps)
     if args.spin_up:
         s.step(args.spin_up)
         s.reduce()

@@ -204,16 +204,18 @@ def disk_inside(center, radius, thickness):
     return f
 
 
-def gear_inside(center, z_teeth, r_tip, r_root, face, phase):
-    """Spur-gear proxy about an axis parallel to y: tooth where frac(z th/2pi + 1/4 + phase) < 1/2."""
+def gear_inside(center, z_teeth, r_tip, r_root, face, phase, tooth_frac=0.5):
+    """Spur-gear proxy about an axis parallel to y: tooth where
+    frac(z th/2pi + tooth_frac/2 + phase) < tooth_frac (teeth of tooth_frac of
+    the pitch, centred on th = 0 at phase 0; 1/2 gives the survey's teeth)."""
     c = np.asarray(center, dtype=np.float64)
 
     def f(x):
         d = x - c
         r2 = d[:, 0] ** 2 + d[:, 2] ** 2
         th = np.arctan2(d[:, 2], d[:, 0])
-        fr = np.mod(z_teeth * th / (2.0 * math.pi) + 0.25 + phase, 1.0)
-        tooth = fr < 0.5
+        fr = np.mod(z_teeth * th / (2.0 * math.pi) + 0.5 * tooth_frac + phase, 1.0)
+        tooth = fr < tooth_frac
         inr = (r2 <= r_root * r_root) | ((r2 <= r_tip * r_tip) & tooth)
         return inr & (np.abs(d[:, 1]) <= 0.5 * face)
     return f
@@ -293,25 +295,28 @@ def still_tank(seed: int = 0, dp: float = 2e-3, box=(0.10, 0.05, 0.05), fill=0.0
 
 
 def gearbox(seed: int = 0, dp: float = 1.5e-3, omega_big: float = 300.0, immersion: float = 0.030,
-            nu: float = 1e-4, box=(0.30, 0.15, 0.20)) -> Case:
+            nu: float = 1e-4, box=(0.30, 0.15, 0.20), tooth_frac: float = 0.5,
+            centre_distance: float = 0.120) -> Case:
     """Gearbox proxy: two meshing toothed disks (20/40 teeth, module 4 mm), axes parallel to y.
 
     The 40-tooth gear turns at omega_big, the 20-tooth gear at -2 omega_big; the
     free surface sits `immersion` below the gear centres (paper's lubrication
-    depth convention).
+    depth convention).  Teeth span tooth_frac of the pitch, rectangular in
+    angle; the gears sit centre_distance apart (their pitch circles touch at
+    0.120 m).
     """
     m = 4e-3
     zc = 0.100
     yc = box[1] / 2.0
     face = 0.030
     g1 = dict(center=(0.070, yc, zc), z=20, phase=0.0, omega=-2.0 * omega_big)
-    g2 = dict(center=(0.190, yc, zc), z=40, phase=0.5, omega=omega_big)
+    g2 = dict(center=(0.070 + centre_distance, yc, zc), z=40, phase=0.5, omega=omega_big)
     geos = []
     for g in (g1, g2):
         rp = m * g["z"] / 2.0
         ra, rf = rp + m, rp - 1.25 * m
         geos.append(dict(center=g["center"], half_extent=(ra, face / 2, ra), r_tip=ra, omega=g["omega"],
-                         inside=gear_inside(g["center"], g["z"], ra, rf, face, g["phase"])))
+                         inside=gear_inside(g["center"], g["z"], ra, rf, face, g["phase"], tooth_frac)))
     return _tank("gearbox", box, dp, zc - immersion, geos, rho0=870.0, nu=nu, k_f=0.13, cp_f=2000.0,
                  T_oil=40.0 + KELVIN, T_wall=60.0 + KELVIN, k_solid=20.0, seed=seed)
 

@@ -29,20 +29,42 @@ def _hydro_error(s, c, H):
 
 
 def test_still_tank_stays_hydrostatic(ora):
-    """Walls (eq. 16-19), EoS (eq. 2), gravity and density re-initialisation (eq. 14)."""
+    """Walls (eq. 16-19), EoS (eq. 2), gravity and density re-initialisation
+    (eq. 14), 2000 advection steps (32,000 acoustic sub-steps, 2.2 s) of a
+    still tank:
+    - |v|max stays below 1 % of the reference speed c0/10 once the jittered
+      lattice has settled (P8), and the mass is exact;
+    - at step 600 the pressure of every depth bin away from the walls is
+      within 1 % of rho0 g (H - z) (P11);
+    - after that the max of eq. 14 ratchets the density up (every upward
+      fluctuation of the kernel sum is kept): the mean pressure rises at a
+      slowly growing rate below 3 % of rho0 g H per simulated second
+      (1.5-2.5 % measured; 7 % of rho0 g H at step 2000), and the mass proxy
+      by less than 2e-5.  Applying eq. 14 only where the kernel sum is
+      deficient and eq. 15 elsewhere stops the rise but leaves the depth bins
+      5-6 % off, so the literal reading is kept."""
     H = 0.02
     c = cases.still_tank(dp=2e-3, box=(0.04, 0.02, 0.03), fill=H)
     s = ora.State(c)
     umax = c.params["c0"] / 10.0
+    rho0, g, c0 = c.params["rho0"], abs(c.params["gravity"][2]), c.params["c0"]
     m0 = None
-    for k in range(600):
+    mean_p = {}
+    for k in range(2000):
         r = s.step()
         m0 = m0 or r["mass"]
         if k >= 50:          # after the jittered lattice has settled
             assert r["vmax"] <= 1e-2 * umax, (k, r["vmax"])
         assert r["mass"] == m0
-    assert _hydro_error(s, c, H) <= 0.01
-    assert abs(r["mass_proxy"] / r["mass"] - 1.0) < 1e-3
+        if k + 1 == 600:
+            assert _hydro_error(s, c, H) <= 0.01
+            proxy600 = r["mass_proxy"] / r["mass"] - 1.0
+        if (k + 1) % 200 == 0:
+            mean_p[k + 1] = (float(np.mean(c0 * c0 * (s.rho - rho0))) / (rho0 * g * H), r["t"])
+    ks = sorted(k for k in mean_p if k >= 600)
+    rates = [(mean_p[b][0] - mean_p[a][0]) / (mean_p[b][1] - mean_p[a][1]) for a, b in zip(ks, ks[1:])]
+    assert all(0.0 < q < 0.03 for q in rates), rates
+    assert abs((r["mass_proxy"] / r["mass"] - 1.0) - proxy600) < 2e-5
 
 
 def test_printed_eq13_sign_is_unstable(ora):
