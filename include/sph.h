@@ -68,10 +68,8 @@ typedef struct {
  * velocity into the wall:
  *   SPH_WALL_VISC_SHEPARD (0, default): v_w = 2 u_w - v~_w, u_w the body's
  *     rigid velocity at the wall particle, v~_w the kernel-weighted (Shepard)
- *     mean velocity of the fluid particles within 2h of it (u_w when there
- *     are none).  The sums are exact (fixed point, 2^-52 c0 per term), so
- *     their order does not matter; a fluid speed above 4 c0 lies outside
- *     their range and latches the capacity fault;
+ *     mean of the step-start velocity of the fluid particles within 2h of it
+ *     (u_w when there are none), summed in FP64 in a fixed order;
  *   SPH_WALL_VISC_RIGID (1): v_w = u_w, eq. 18 read literally (the wall then
  *     slips at the resolutions of the paper).
  * The Riemann wall problem of eq. 16-19 always takes u_w. */
@@ -129,8 +127,7 @@ typedef struct {
   int64_t step;         /* completed advection steps */
   int32_t n_ac;         /* acoustic sub-steps of the last step */
   int32_t flags;        /* latched fault bits: 1 domain, 2 non-finite, 4 capacity (a neighbour row
-                           overflowed, a fluid particle touched more than two bodies, or a fluid
-                           speed exceeded 4 c0) */
+                           overflowed, or a fluid particle touched more than two bodies) */
   double dt_ad, dt;     /* last advection step and sub-step */
   double vmax;          /* max |v| of the fluid at the end of the step */
   double mass;          /* sum of fluid masses */

@@ -199,7 +199,6 @@ static size_t carve(const Plan& P, void* base, SlotDesc* d) {
   C.take(D.scell, ns * 4);
   C.take(D.sperm, ns * 4);
   C.take(D.zeta, ns * 8);
-  C.take(D.wacc, ns * 4 * 8);
   C.takev(D.vd, 4 * ns * rs);
   C.take(D.skey, ns * 8);
   C.take(D.rank, nc * 4);

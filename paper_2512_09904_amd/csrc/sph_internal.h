@@ -102,9 +102,6 @@ struct SlotDesc {
   void *xwb, *nwb, *vwb, *levb;
   uint32_t *scell, *sperm;
   double *zeta;         // contact factor per solid particle, original order
-  // Shepard sums around each sorted solid particle (fixed point, 2^-52 units):
-  // [4 w + k] = sum over its fluid neighbours of W dp^3 v_k / c0 (k < 3), W dp^3 (k = 3)
-  int64_t *wacc;
   void *vd;             // dummy velocity of eq. 18 per sorted solid particle (vx, vy, vz, dp^3 sum W)
   uint64_t *skey;
   // cells

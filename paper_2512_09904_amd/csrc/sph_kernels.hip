@@ -473,10 +473,6 @@ __global__ __launch_bounds__(BLOCK) void k_reorder(const SlotDesc* table, Launch
     gp<Real4>(S.lev)[k] = gpc<Real4>(S.levb)[s];
     S.body[k] = S.bodyb[s];
     S.sid[k] = S.sidb[s];
-    // the Shepard sums of eq. 18's dummy velocity start from zero each build
-    GLB u4* acc = gp<u4>(S.wacc + 4 * (size_t)k);
-    acc[0] = u4(0u);
-    acc[1] = u4(0u);
   }
 }
 
@@ -716,21 +712,7 @@ __global__ __launch_bounds__(BLOCK) void k_build(const SlotDesc* table, LaunchTa
 // perfect-lattice sum S0 (eq. 14 with a free surface, eq. 15 without).  Each
 // pair's d^2 is formed exactly as in the cutoff test; the rows are walked in
 // order (fluid, then solid) so the sum is reproducible.
-//
-// The same fluid-solid pairs also feed the Shepard sums of the wall's
-// no-slip dummy velocity (eq. 18 with the generalized wall of Section 2.5):
-// every pair adds W dp^3 v_i / c0 and W dp^3 to its solid particle's four
-// accumulators as fixed-point integers (units of 2^-52), so the sums are
-// exact and the same whatever order the atomics land in.  |v_i| <= 4 c0 and
-// at most ~1200 fluid particles within 2h keep them inside int64.
 // ---------------------------------------------------------------------------
-constexpr double FIX_ONE = 4503599627370496.0;   // 2^52
-constexpr double FIX_VMAX = 4.0;                 // |v| / c0 range of the sums
-
-__device__ __forceinline__ void fix_add(int64_t* a, double x) {
-  atomicAdd((unsigned long long*)a, (unsigned long long)(long long)__builtin_rint(x * FIX_ONE));
-}
-
 template <class P>
 __global__ __launch_bounds__(BLOCK) void k_sumw(const SlotDesc* table, LaunchTab tab) {
 #pragma clang fp contract(off)
@@ -783,29 +765,13 @@ __global__ __launch_bounds__(BLOCK) void k_sumw(const SlotDesc* table, LaunchTab
     const int n = (int)S.nsc[i];
     const GLB uint32_t* R = gpc<uint32_t>(S.srec) + slice * (int64_t)S.ks * WAVE + lane;
     const GLB Pos4* xw = gpc<Pos4>(S.xw);
-    const bool shep = !S.wall_rigid;
-    const double ic0 = 1.0 / S.c0;
-    double fv[3] = {(double)v.x * ic0, (double)v.y * ic0, (double)v.z * ic0};
-    if (shep && n > 0) {
-      bool in = true;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        in = in && fabs(fv[a]) <= FIX_VMAX;
-        fv[a] = fmin(fmax(fv[a], -FIX_VMAX), FIX_VMAX);
-      }
-      if (!in) raise_flag(S, F_CAPACITY);
-    }
     uint32_t wn[SOLID_UNROLL];
 #pragma unroll
     for (int u = 0; u < SOLID_UNROLL; ++u) wn[u] = ldnt(R + (int64_t)u * WAVE);
     for (int k = 0; k < n; k += SOLID_UNROLL) {
       Pos4 xq[SOLID_UNROLL];
-      uint32_t wq[SOLID_UNROLL];
 #pragma unroll
-      for (int u = 0; u < SOLID_UNROLL; ++u) {
-        wq[u] = k + u < n ? wn[u] : 0u;
-        xq[u] = xw[wq[u]];
-      }
+      for (int u = 0; u < SOLID_UNROLL; ++u) xq[u] = xw[k + u < n ? wn[u] : 0u];
       if (k + SOLID_UNROLL < n) {
 #pragma unroll
         for (int u = 0; u < SOLID_UNROLL; ++u) wn[u] = ldnt(R + (int64_t)(k + SOLID_UNROLL + u) * WAVE);
@@ -816,17 +782,7 @@ __global__ __launch_bounds__(BLOCK) void k_sumw(const SlotDesc* table, LaunchTab
         const Pos s2 = ddx * ddx + ddy * ddy;
         const Pos d2 = s2 + ddz * ddz;
         const double w = kernel_W_d2((double)d2, inv_h, kW);
-        if (k + u < n) {
-          sw += w;
-          if (shep) {
-            int64_t* a = S.wacc + 4 * (size_t)wq[u];
-            const double wd = w * dp3;
-            fix_add(a + 0, wd * fv[0]);
-            fix_add(a + 1, wd * fv[1]);
-            fix_add(a + 2, wd * fv[2]);
-            fix_add(a + 3, wd);
-          }
-        }
+        if (k + u < n) sw += w;
       }
     }
   }
@@ -840,28 +796,145 @@ __global__ __launch_bounds__(BLOCK) void k_sumw(const SlotDesc* table, LaunchTab
 
 // ---------------------------------------------------------------------------
 // K: dummy velocity of every solid particle for the wall viscous force
-// (eq. 18): v_w = 2 u_w - v~_w with v~_w = c0 (sum W dp^3 v/c0) / (sum W dp^3)
-// the Shepard mean of the fluid velocity around it (the rigid velocity u_w
-// when no fluid is within 2h, or with the literal reading of eq. 18).
+// (eq. 18 with the generalized wall of Section 2.5): v_w = 2 u_w - v~_w, with
+// v~_w = (sum_j W_wj v_j) / (sum_j W_wj) the Shepard mean of the step-start
+// velocity of the fluid within 2h (the rigid velocity u_w when there is none,
+// or with the literal reading of eq. 18).  The pairs are those of the fluid
+// rows: the same FP64 cutoff test on the same frozen positions (d^2 of -r is
+// d^2 of r, bit for bit), and W from the same d^2.
+//
+// Solid-centric, with the neighbour build's traversal: a wavefront holds 64
+// consecutive solid particles of the Morton order; for each run sharing a
+// cell, the fluid candidates of its 27-cell stencil are spread over the lanes
+// (up to CB per lane, position and velocity loaded once); each particle of the
+// run is then taken in turn, every lane sums W and W v over its candidates
+// within the cutoff, and four wave reductions in a fixed order give the
+// particle's sums.  FP64 throughout, no atomics: the result depends only on
+// the sorted order, so it is the same alone or batched.
 // ---------------------------------------------------------------------------
 template <class P>
 __global__ __launch_bounds__(BLOCK) void k_wallvel(const SlotDesc* table, LaunchTab tab) {
+#pragma clang fp contract(off)
+  typedef typename P::Pos Pos;
+  typedef typename P::Pos4 Pos4;
   typedef typename P::Real Real;
   typedef typename P::Real4 Real4;
+  __shared__ uint32_t lds_pre[BLOCK / WAVE][32];
+  __shared__ uint32_t lds_beg[BLOCK / WAVE][32];
   SLOT_PROLOGUE(DOM_SOLID);
   const int w = lb * BLOCK + threadIdx.x;
-  if (w >= S.ns) return;
-  const Real4 u = gpc<Real4>(S.vw)[w];
+  const int ns = S.ns;
+  const bool act = w < ns;
+  const int ww = act ? w : ns - 1;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wv = threadIdx.x / WAVE;
+  const Real4 u = gpc<Real4>(S.vw)[ww];
+  // sums of this lane's solid particle: W v (3) and W
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (!S.wall_rigid) {
+    const GLB Pos4* xw = gpc<Pos4>(S.xw);
+    const GLB Pos4* xa = gpc<Pos4>(S.xa);
+    const GLB Real4* vr = gpc<Real4>(S.vr);
+    const GLB uint32_t* rank = gpc<uint32_t>(S.rank);
+    const GLB uint32_t* stf = gpc<uint32_t>(S.start_f);
+    const Pos4 q4 = xw[ww];
+    const Pos qx = q4.x, qy = q4.y, qz = q4.z;
+    int c[3];
+    cell_coords<Pos>(S, qx, qy, qz, c);   // in the grid: checked by the pose
+    const double cut2 = S.cut2, inv_h = 1.0 / S.h, kW = S.kW;
+    uint32_t* pre = lds_pre[wv];
+    uint32_t* beg = lds_beg[wv];
+    const uint32_t myr = rank[cell_linear(S, c[0], c[1], c[2])];
+    const uint32_t prevr = (uint32_t)__shfl_up((int)myr, 1, WAVE);
+    const int nact = __popcll(__ballot(act));
+    uint64_t runs = __ballot(act && (lane == 0 || prevr != myr));
+    const int ox = lane % 3 - 1, oy = (lane / 3) % 3 - 1, oz = lane / 9 - 1;
+    while (runs) {
+      const int L = __builtin_ctzll(runs);
+      runs &= runs - 1;
+      const int R = runs ? __builtin_ctzll(runs) : nact;
+      const int nx = __builtin_amdgcn_readlane(c[0], L) + ox, ny = __builtin_amdgcn_readlane(c[1], L) + oy,
+                nz = __builtin_amdgcn_readlane(c[2], L) + oz;
+      const bool valid = lane < 27 && nx >= 0 && ny >= 0 && nz >= 0 && nx < S.dims[0] && ny < S.dims[1] &&
+                         nz < S.dims[2];
+      uint32_t f0 = 0, f1 = 0;
+      if (valid) {
+        const uint32_t r = rank[cell_linear(S, nx, ny, nz)];
+        f0 = stf[r];
+        f1 = stf[r + 1];
+      }
+      uint32_t M;
+      const uint32_t pf = wave_excl_scan(f1 - f0, &M);
+      if (lane < 27) {
+        pre[lane] = pf;
+        beg[lane] = f0;
+      }
+      wave_lds_sync();
+      for (uint32_t b0 = 0; b0 < M; b0 += (uint32_t)(WAVE * CB)) {
+        Pos cx[CB], cy[CB], cz[CB];
+        double cv[CB][3];
+#pragma unroll
+        for (int k = 0; k < CB; ++k) {
+          const uint32_t m = b0 + (uint32_t)(k * WAVE + lane);
+          cx[k] = cy[k] = cz[k] = (Pos)1e30;   // far: never within the cutoff
+          cv[k][0] = cv[k][1] = cv[k][2] = 0.0;
+          if (m < M) {
+            int qq = 0;
+#pragma unroll
+            for (int st = 16; st > 0; st >>= 1)
+              if (qq + st < 27 && pre[qq + st] <= m) qq += st;
+            const uint32_t j = beg[qq] + (m - pre[qq]);
+            const Pos4 pj = xa[j];
+            const Real4 vj = vr[j];
+            cx[k] = pj.x;
+            cy[k] = pj.y;
+            cz[k] = pj.z;
+            cv[k][0] = (double)vj.x;
+            cv[k][1] = (double)vj.y;
+            cv[k][2] = (double)vj.z;
+          }
+        }
+        const int nu = (int)min((uint32_t)CB, (M - b0 + WAVE - 1) / WAVE);
+        for (int p = L; p < R; ++p) {
+          const Pos px = rl(qx, p), py = rl(qy, p), pz = rl(qz, p);
+          double s[4] = {0.0, 0.0, 0.0, 0.0};
+          bool any = false;
+#pragma unroll
+          for (int k = 0; k < CB; ++k) {
+            if (k >= nu) break;
+            // d = x_w - x_j: the negation of the fluid row's x_j - x_w, same d^2
+            const Pos ddx = px - cx[k], ddy = py - cy[k], ddz = pz - cz[k];
+            const Pos s2 = ddx * ddx + ddy * ddy;
+            const Pos d2 = s2 + ddz * ddz;
+            if ((double)d2 < cut2) {
+              const double wgt = kernel_W_d2((double)d2, inv_h, kW);
+              s[0] += wgt * cv[k][0];
+              s[1] += wgt * cv[k][1];
+              s[2] += wgt * cv[k][2];
+              s[3] += wgt;
+              any = true;
+            }
+          }
+          if (!__ballot(any)) continue;
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            const double t = wave_sum(s[a]);
+            if (lane == p) acc[a] += t;
+          }
+        }
+      }
+      wave_lds_sync();
+    }
+  }
+  if (!act) return;
   Real4 o = u;
   o.w = (Real)0;
-  const GLB int64_t* a = gpc<int64_t>(S.wacc) + 4 * (size_t)w;
-  const int64_t sw = a[3];
-  if (!S.wall_rigid && sw > 0) {
-    const double q = S.c0 / (double)sw;
-    o.x = (Real)(2.0 * (double)u.x - (double)a[0] * q);
-    o.y = (Real)(2.0 * (double)u.y - (double)a[1] * q);
-    o.z = (Real)(2.0 * (double)u.z - (double)a[2] * q);
-    o.w = (Real)((double)sw / FIX_ONE);
+  if (!S.wall_rigid && acc[3] > 0.0) {
+    const double inv = 1.0 / acc[3];
+    o.x = (Real)(2.0 * (double)u.x - acc[0] * inv);
+    o.y = (Real)(2.0 * (double)u.y - acc[1] * inv);
+    o.z = (Real)(2.0 * (double)u.z - acc[2] * inv);
+    o.w = (Real)(acc[3] * (S.dp * S.dp * S.dp));
   }
   gp<Real4>(S.vd)[w] = o;
 }
