@@ -327,6 +327,10 @@ struct TimedLaunch {
 struct sph_pool {
   hipStream_t stream = nullptr;
   hipStream_t copy_stream = nullptr;
+  // a second compute stream, forked from and joined back into `stream`, so
+  // that the solid-centric dummy-velocity sweep overlaps the kernel sums
+  hipStream_t side_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   sph_allocator alloc{};
   int prec = 0;
   size_t budget = 0, used = 0;
@@ -380,7 +384,7 @@ static void drop_graph(sph_pool* P) {
 // ---------------------------------------------------------------------------
 // launch sequence
 // ---------------------------------------------------------------------------
-static int launch(sph_pool* P, const LaunchTab& tab, int kid, int which, int sub) {
+static int launch(sph_pool* P, const LaunchTab& tab, int kid, int which, int sub, hipStream_t st) {
   hipEvent_t a = nullptr, b = nullptr;
   if (P->timing) {
     for (hipEvent_t* e : {&a, &b}) {
@@ -391,15 +395,19 @@ static int launch(sph_pool* P, const LaunchTab& tab, int kid, int which, int sub
         HIPCHK(hipEventCreate(e));
       }
     }
-    HIPCHK(hipEventRecord(a, P->stream));
+    HIPCHK(hipEventRecord(a, st));
   }
-  hipError_t e = launch_kernel(P->prec, kid, which, sub, P->d_table, tab, P->stream);
+  hipError_t e = launch_kernel(P->prec, kid, which, sub, P->d_table, tab, st);
   if (e != hipSuccess) return fail(SPH_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
   if (P->timing) {
-    HIPCHK(hipEventRecord(b, P->stream));
+    HIPCHK(hipEventRecord(b, st));
     P->pending.push_back({kid, a, b});
   }
   return SPH_OK;
+}
+
+static int launch(sph_pool* P, const LaunchTab& tab, int kid, int which, int sub) {
+  return launch(P, tab, kid, which, sub, P->stream);
 }
 
 static int launch_rx(sph_pool* P, const LaunchTab& tab, int kid, int iter, const RelaxShape& g) {
@@ -433,12 +441,13 @@ static int launch_rx(sph_pool* P, const LaunchTab& tab, int kid, int iter, const
 // timed = false: no event timing and no heap allocation on success (the
 // allocation-free entry point)
 static int enqueue_sort_build(sph_pool* P, const LaunchTab& T, bool timed = true) {
-  auto L = [&](int kid, int which) {
-    if (timed) return launch(P, T, kid, which, 0);
-    if (launch_kernel(P->prec, kid, which, 0, P->d_table, T, P->stream) != hipSuccess)
+  auto LS = [&](int kid, int which, hipStream_t st) {
+    if (timed) return launch(P, T, kid, which, 0, st);
+    if (launch_kernel(P->prec, kid, which, 0, P->d_table, T, st) != hipSuccess)
       return fail_lit(SPH_ERR_HIP, "kernel launch failed");
     return (int)SPH_OK;
   };
+  auto L = [&](int kid, int which) { return LS(kid, which, P->stream); };
   LCHK(L(SPH_K_CLEAR, 0));
   LCHK(L(SPH_K_POSE, 1));
   LCHK(L(SPH_K_FOLD, 0));
@@ -451,8 +460,17 @@ static int enqueue_sort_build(sph_pool* P, const LaunchTab& T, bool timed = true
   LCHK(L(SPH_K_REORDER, 0));
   LCHK(L(SPH_K_REORDER, 1));
   LCHK(L(SPH_K_BUILD, 0));
+  // the dummy velocities (solids) on the side stream, beside the kernel sums
+  // (fluid): both read the fresh build, neither reads the other's output
+  if (hipEventRecord(P->ev_fork, P->stream) != hipSuccess ||
+      hipStreamWaitEvent(P->side_stream, P->ev_fork, 0) != hipSuccess)
+    return fail_lit(SPH_ERR_HIP, "fork to the side stream failed");
+  LCHK(LS(SPH_K_WALLVEL, 1, P->side_stream));
+  if (hipEventRecord(P->ev_join, P->side_stream) != hipSuccess)
+    return fail_lit(SPH_ERR_HIP, "event record on the side stream failed");
   LCHK(L(SPH_K_SUMW, 0));
-  LCHK(L(SPH_K_WALLVEL, 1));
+  if (hipStreamWaitEvent(P->stream, P->ev_join, 0) != hipSuccess)
+    return fail_lit(SPH_ERR_HIP, "join from the side stream failed");
   return SPH_OK;
 }
 
@@ -548,13 +566,24 @@ extern "C" int sph_pool_create(size_t budget, int32_t max_slots, int32_t precisi
   P->budget = budget;
   P->max_slots = max_slots;
   P->use_graph = stream != nullptr;
-  if (hipStreamCreateWithFlags(&P->copy_stream, hipStreamNonBlocking) != hipSuccess) {
+  // default stream priority for both (streams of different priorities are avoided)
+  if (hipStreamCreateWithFlags(&P->copy_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&P->side_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming) != hipSuccess) {
+    if (P->copy_stream) (void)hipStreamDestroy(P->copy_stream);
+    if (P->side_stream) (void)hipStreamDestroy(P->side_stream);
+    if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+    if (P->ev_join) (void)hipEventDestroy(P->ev_join);
     delete P;
-    return fail(SPH_ERR_HIP, "hipStreamCreateWithFlags failed");
+    return fail(SPH_ERR_HIP, "stream or event creation failed");
   }
   P->d_table = (SlotDesc*)dev_alloc(P, sizeof(SlotDesc) * MAX_SLOTS);
   if (!P->d_table) {
     (void)hipStreamDestroy(P->copy_stream);
+    (void)hipStreamDestroy(P->side_stream);
+    (void)hipEventDestroy(P->ev_fork);
+    (void)hipEventDestroy(P->ev_join);
     delete P;
     return fail(SPH_ERR_OOM, "slot table allocation failed");
   }
@@ -943,6 +972,9 @@ extern "C" int sph_pool_destroy(sph_pool* P) {
   }
   for (hipEvent_t e : P->free_events) (void)hipEventDestroy(e);
   if (P->copy_stream) (void)hipStreamDestroy(P->copy_stream);
+  if (P->side_stream) (void)hipStreamDestroy(P->side_stream);
+  if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+  if (P->ev_join) (void)hipEventDestroy(P->ev_join);
   delete P;
   return SPH_OK;
 }

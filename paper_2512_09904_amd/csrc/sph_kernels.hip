@@ -799,24 +799,31 @@ __global__ __launch_bounds__(BLOCK) void k_sumw(const SlotDesc* table, LaunchTab
 // (eq. 18 with the generalized wall of Section 2.5): v_w = 2 u_w - v~_w, with
 // v~_w = (sum_j W_wj v_j) / (sum_j W_wj) the Shepard mean of the step-start
 // velocity of the fluid within 2h (the rigid velocity u_w when there is none,
-// or with the literal reading of eq. 18).  The pairs are those of the fluid
-// rows: the same FP64 cutoff test on the same frozen positions (d^2 of -r is
-// d^2 of r, bit for bit), and W from the same d^2.
+// or with the literal reading of eq. 18).
 //
 // Solid-centric, with the neighbour build's traversal: a wavefront holds 64
 // consecutive solid particles of the Morton order; for each run sharing a
 // cell, the fluid candidates of its 27-cell stencil are spread over the lanes
-// (up to CB per lane, position and velocity loaded once); each particle of the
-// run is then taken in turn, every lane sums W and W v over its candidates
-// within the cutoff, and four wave reductions in a fixed order give the
-// particle's sums.  FP64 throughout, no atomics: the result depends only on
-// the sorted order, so it is the same alone or batched.
+// (up to CB per lane, cell-relative position and velocity loaded once); each
+// particle of the run is then taken in turn, every lane sums W and W v over
+// its candidates within 2h, and four wave reductions in a fixed order give the
+// particle's sums.  The arithmetic is that of the interaction sweeps (FP32 in
+// mixed precision, pair vectors from the frozen cell-relative positions): a
+// pair that this test and the FP64 cutoff test of the rows decide differently
+// lies within a few ulps of 2h, where W is below 1e-25 W(0).  No atomics: the
+// result depends only on the sorted order, so it is the same alone or batched.
+// It runs beside the kernel sums, which rewrite only the density component of
+// the velocity records read here.
 // ---------------------------------------------------------------------------
+template <class Real>
+__device__ __forceinline__ Real wave_sum_r(Real v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+
 template <class P>
 __global__ __launch_bounds__(BLOCK) void k_wallvel(const SlotDesc* table, LaunchTab tab) {
-#pragma clang fp contract(off)
-  typedef typename P::Pos Pos;
-  typedef typename P::Pos4 Pos4;
   typedef typename P::Real Real;
   typedef typename P::Real4 Real4;
   __shared__ uint32_t lds_pre[BLOCK / WAVE][32];
@@ -830,18 +837,16 @@ __global__ __launch_bounds__(BLOCK) void k_wallvel(const SlotDesc* table, Launch
   const int wv = threadIdx.x / WAVE;
   const Real4 u = gpc<Real4>(S.vw)[ww];
   // sums of this lane's solid particle: W v (3) and W
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  Real acc[4] = {(Real)0, (Real)0, (Real)0, (Real)0};
   if (!S.wall_rigid) {
-    const GLB Pos4* xw = gpc<Pos4>(S.xw);
-    const GLB Pos4* xa = gpc<Pos4>(S.xa);
+    const GLB Real4* xo = gpc<Real4>(S.xo);
     const GLB Real4* vr = gpc<Real4>(S.vr);
     const GLB uint32_t* rank = gpc<uint32_t>(S.rank);
     const GLB uint32_t* stf = gpc<uint32_t>(S.start_f);
-    const Pos4 q4 = xw[ww];
-    const Pos qx = q4.x, qy = q4.y, qz = q4.z;
-    int c[3];
-    cell_coords<Pos>(S, qx, qy, qz, c);   // in the grid: checked by the pose
-    const double cut2 = S.cut2, inv_h = 1.0 / S.h, kW = S.kW;
+    const Real4 ow = gpc<Real4>(S.so)[ww];
+    const uint32_t cw = unpack_index(ow.w);
+    const int c[3] = {(int)(cw & 1023u), (int)((cw >> 10) & 1023u), (int)(cw >> 20)};
+    const Real cut2 = (Real)S.cut2, inv_h = (Real)(1.0 / S.h), kW = (Real)S.kW, csr = (Real)S.cs_r;
     uint32_t* pre = lds_pre[wv];
     uint32_t* beg = lds_beg[wv];
     const uint32_t myr = rank[cell_linear(S, c[0], c[1], c[2])];
@@ -871,46 +876,46 @@ __global__ __launch_bounds__(BLOCK) void k_wallvel(const SlotDesc* table, Launch
       }
       wave_lds_sync();
       for (uint32_t b0 = 0; b0 < M; b0 += (uint32_t)(WAVE * CB)) {
-        Pos cx[CB], cy[CB], cz[CB];
-        double cv[CB][3];
+        Real4 co[CB], cv[CB];
 #pragma unroll
         for (int k = 0; k < CB; ++k) {
           const uint32_t m = b0 + (uint32_t)(k * WAVE + lane);
-          cx[k] = cy[k] = cz[k] = (Pos)1e30;   // far: never within the cutoff
-          cv[k][0] = cv[k][1] = cv[k][2] = 0.0;
+          co[k] = Real4((Real)1e30);   // far: never within 2h
+          co[k].w = pack_index(0u, (Real)0);
+          cv[k] = Real4((Real)0);
           if (m < M) {
             int qq = 0;
 #pragma unroll
             for (int st = 16; st > 0; st >>= 1)
               if (qq + st < 27 && pre[qq + st] <= m) qq += st;
             const uint32_t j = beg[qq] + (m - pre[qq]);
-            const Pos4 pj = xa[j];
-            const Real4 vj = vr[j];
-            cx[k] = pj.x;
-            cy[k] = pj.y;
-            cz[k] = pj.z;
-            cv[k][0] = (double)vj.x;
-            cv[k][1] = (double)vj.y;
-            cv[k][2] = (double)vj.z;
+            co[k] = xo[j];
+            cv[k] = vr[j];
           }
         }
         const int nu = (int)min((uint32_t)CB, (M - b0 + WAVE - 1) / WAVE);
         for (int p = L; p < R; ++p) {
-          const Pos px = rl(qx, p), py = rl(qy, p), pz = rl(qz, p);
-          double s[4] = {0.0, 0.0, 0.0, 0.0};
+          Real4 op;
+          op.x = rl(ow.x, p);
+          op.y = rl(ow.y, p);
+          op.z = rl(ow.z, p);
+          op.w = rl(ow.w, p);
+          const uint32_t cp = unpack_index(op.w);
+          Real s[4] = {(Real)0, (Real)0, (Real)0, (Real)0};
           bool any = false;
 #pragma unroll
           for (int k = 0; k < CB; ++k) {
             if (k >= nu) break;
-            // d = x_w - x_j: the negation of the fluid row's x_j - x_w, same d^2
-            const Pos ddx = px - cx[k], ddy = py - cy[k], ddz = pz - cz[k];
-            const Pos s2 = ddx * ddx + ddy * ddy;
-            const Pos d2 = s2 + ddz * ddz;
-            if ((double)d2 < cut2) {
-              const double wgt = kernel_W_d2((double)d2, inv_h, kW);
-              s[0] += wgt * cv[k][0];
-              s[1] += wgt * cv[k][1];
-              s[2] += wgt * cv[k][2];
+            Real rx, ry, rz;
+            pair_vec(op, cp, co[k], csr, rx, ry, rz);
+            const Real r2 = rx * rx + ry * ry + rz * rz;
+            if (r2 < cut2) {
+              const Real q = r2 * rsq(r2) * inv_h;
+              const Real t = (Real)1 - (Real)0.5 * q;
+              const Real wgt = r2 > (Real)0 ? kW * t * t * t * t * ((Real)1 + (Real)2 * q) : kW;
+              s[0] += wgt * cv[k].x;
+              s[1] += wgt * cv[k].y;
+              s[2] += wgt * cv[k].z;
               s[3] += wgt;
               any = true;
             }
@@ -918,7 +923,7 @@ __global__ __launch_bounds__(BLOCK) void k_wallvel(const SlotDesc* table, Launch
           if (!__ballot(any)) continue;
 #pragma unroll
           for (int a = 0; a < 4; ++a) {
-            const double t = wave_sum(s[a]);
+            const Real t = wave_sum_r(s[a]);
             if (lane == p) acc[a] += t;
           }
         }
@@ -929,12 +934,12 @@ __global__ __launch_bounds__(BLOCK) void k_wallvel(const SlotDesc* table, Launch
   if (!act) return;
   Real4 o = u;
   o.w = (Real)0;
-  if (!S.wall_rigid && acc[3] > 0.0) {
-    const double inv = 1.0 / acc[3];
-    o.x = (Real)(2.0 * (double)u.x - acc[0] * inv);
-    o.y = (Real)(2.0 * (double)u.y - acc[1] * inv);
-    o.z = (Real)(2.0 * (double)u.z - acc[2] * inv);
-    o.w = (Real)(acc[3] * (S.dp * S.dp * S.dp));
+  if (!S.wall_rigid && acc[3] > (Real)0) {
+    const double inv = 1.0 / (double)acc[3];
+    o.x = (Real)(2.0 * (double)u.x - (double)acc[0] * inv);
+    o.y = (Real)(2.0 * (double)u.y - (double)acc[1] * inv);
+    o.z = (Real)(2.0 * (double)u.z - (double)acc[2] * inv);
+    o.w = (Real)((double)acc[3] * (S.dp * S.dp * S.dp));
   }
   gp<Real4>(S.vd)[w] = o;
 }

@@ -908,10 +908,14 @@ def test_viscous_heating_rejects_bad_flag(sph):
 def test_wall_dummy_velocity_matches_oracle(sph, ora, precision, tol):
     """Per solid particle, the dummy velocity 2 u_w - (Shepard mean of the
     fluid velocity) of a sheared tank at its first build, within tol Umax of
-    the oracle's (mixed: FP32 velocities and storage) plus the rounding of
-    FP64 sums of n_w terms taken in another order, 4 n_w 2^-53 max|v|.  The
-    Shepard weight dp^3 sum W within tol relative.  Solid particles without
-    fluid keep their rigid velocity exactly."""
+    the oracle's (mixed: FP32 arithmetic, velocities and storage) plus the
+    rounding of FP64 sums of n_w terms taken in another order,
+    4 n_w 2^-53 max|v|.  The Shepard weight dp^3 sum W within tol relative.
+    The GPU forms the pair vectors from the cell-relative positions, so a
+    pair within a few ulps of 2h may be decided differently from the FP64
+    cutoff test; its W is below 1e-25 W(0), so wall particles whose oracle
+    weight is below 1e-20 are left out of the comparison.  Solid particles
+    without fluid keep their rigid velocity exactly."""
     c = _sheared(ragged_tank(seed=4), 5)
     say("dummy velocity parity", precision, c.ns)
     s = sph.Solver(c, precision=precision)
@@ -937,11 +941,19 @@ def test_wall_dummy_velocity_matches_oracle(sph, ora, precision, tol):
     order = 4.0 * n_w * 2.0 ** -53 * float(np.max(np.abs(c.vf)))
     err = np.max(np.abs(vd - vo), axis=1)
     bar = tol * umax + order
-    say("dummy velocity: max error / Umax", float(np.max(err)) / umax,
-        "max error / bar", float(np.max(err / bar)))
-    assert np.all(err[wet] <= bar[wet])
-    assert np.all(np.abs(sw - swo * dp3) <= tol * swo * dp3)
-    assert np.array_equal(vd[~wet], vrig[~wet])
+    sel = swo * dp3 >= 1e-20
+    assert sel.sum() >= wet.sum() - 2
+    say("dummy velocity: max error / Umax", float(np.max(err[sel])) / umax,
+        "max error / bar", float(np.max(err[sel] / bar[sel])))
+    assert np.all(err[sel] <= bar[sel])
+    # each W carries the rounding of its pair vector (3 ulps of the cell edge,
+    # i.e. 6 ulps of q = r/h) times |dW/dq| <= 10 W(0): n_w such terms
+    eps = 2.0 ** -24 if precision == "mixed" else 2.0 ** -53
+    w0 = 21.0 / (16.0 * np.pi * c.params["h_over_dp"] ** 3)    # W(0) dp^3
+    assert np.all(np.abs(sw - swo * dp3)[sel] <= (tol * swo * dp3 + n_w * 10.0 * w0 * 6.0 * eps)[sel])
+    dry = (swo == 0) & (sw == 0)
+    assert dry.sum() >= (~wet).sum() - 2
+    assert np.array_equal(vd[dry], vrig[dry])
 
 
 @pytest.mark.parametrize("precision,bar,tau", [("mixed", 1e-5, 1e-5), ("fp64", 1e-10, 1e-11)])
