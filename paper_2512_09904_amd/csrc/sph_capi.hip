@@ -439,8 +439,9 @@ static int launch_rx(sph_pool* P, const LaunchTab& tab, int kid, int iter, const
   } while (0)
 
 // timed = false: no event timing and no heap allocation on success (the
-// allocation-free entry point)
-static int enqueue_sort_build(sph_pool* P, const LaunchTab& T, bool timed = true) {
+// allocation-free entry point); wallvel = false: no dummy velocities (calls
+// between steps that do not step: the next step's own build recomputes them)
+static int enqueue_sort_build(sph_pool* P, const LaunchTab& T, bool timed = true, bool wallvel = true) {
   auto LS = [&](int kid, int which, hipStream_t st) {
     if (timed) return launch(P, T, kid, which, 0, st);
     if (launch_kernel(P->prec, kid, which, 0, P->d_table, T, st) != hipSuccess)
@@ -460,6 +461,10 @@ static int enqueue_sort_build(sph_pool* P, const LaunchTab& T, bool timed = true
   LCHK(L(SPH_K_REORDER, 0));
   LCHK(L(SPH_K_REORDER, 1));
   LCHK(L(SPH_K_BUILD, 0));
+  if (!wallvel) {
+    LCHK(L(SPH_K_SUMW, 0));
+    return SPH_OK;
+  }
   // the dummy velocities (solids) on the side stream, beside the kernel sums
   // (fluid): both read the fresh build, neither reads the other's output
   if (hipEventRecord(P->ev_fork, P->stream) != hipSuccess ||
@@ -1161,7 +1166,7 @@ extern "C" int sph_contact_factor(sph_solver* s, double* zeta, double* body_mean
   if (c.flags) return fail(flag_code(c.flags), "solve faulted");
   LaunchTab T;
   tab_for(P, std::vector<int>{0}, T);
-  LCHK(enqueue_sort_build(P, T));
+  LCHK(enqueue_sort_build(P, T, true, false));
   LCHK(launch(P, T, SPH_K_CONTACT, 1, 0));
   LCHK(read_ctl(P, S, &c, true));
   if (c.flags) return fail(flag_code(c.flags), "contact factor build faulted");
@@ -1203,7 +1208,7 @@ extern "C" int sph_contact_factor_noalloc(sph_solver* s, double* zeta_dev, doubl
   LCHK(scratch_address(&scr));
   LaunchTab T;
   tab_one(P, 0, T);
-  LCHK(enqueue_sort_build(P, T, false));
+  LCHK(enqueue_sort_build(P, T, false, false));
   if (launch_contact(P->prec, P->d_table, T, zeta_dev, body_mean_dev ? scr : nullptr, body_mean_dev, P->stream) !=
       hipSuccess)
     return fail_lit(SPH_ERR_HIP, "contact factor launch failed");
@@ -1249,7 +1254,7 @@ extern "C" int sph_relax(sph_solver* s, const sph_shape* sh, int32_t iterations,
   LaunchTab T;
   tab_for(P, std::vector<int>{0}, T);
   for (int it = 0; it < iterations; ++it) {
-    LCHK(enqueue_sort_build(P, T));
+    LCHK(enqueue_sort_build(P, T, true, false));
     LCHK(launch_rx(P, T, SPH_K_RELAX_FORCE, it, g));
     LCHK(launch_rx(P, T, SPH_K_RELAX_MAX, it, g));
     LCHK(launch_rx(P, T, SPH_K_RELAX_MOVE, it, g));

@@ -19,6 +19,8 @@ pytestmark = pytest.mark.gpu
 SPHERE = dict(kind="sphere", center=(0.3, -0.2, 0.1), size=(7.0,))
 GEAR = dict(kind="gear", center=(0.0, 0.0, 0.0), size=(12.0, 9.0, 4.0), teeth=12, phase=0.13)
 OUTSIDE = dict(kind="cylinder", center=(0.0, 0.0, 0.0), size=(4.0, 20.0), inside=0)
+# a box off the lattice's axes, so its faces, edges and corners cut through the particles
+BOX = dict(kind="box", center=(0.2, -0.35, 0.15), size=(6.3, 4.6, 5.2))
 
 
 def say(*a):
@@ -44,7 +46,7 @@ def _case(shape, seed=0):
     return cases.relax_case(shape, 1.0, 14.0 if shape["kind"] == "gear" else 8.0, seed=seed)
 
 
-@pytest.mark.parametrize("shape", [SPHERE, GEAR], ids=["sphere", "gear"])
+@pytest.mark.parametrize("shape", [SPHERE, GEAR, BOX], ids=["sphere", "gear", "box"])
 @pytest.mark.parametrize("precision,tol,rtol", [("fp64", 1e-9, 1e-12), ("mixed", 1e-5, 1e-5)])
 def test_relax_one_iteration_matches_oracle(sph, ora, shape, precision, tol, rtol):
     c = _case(shape)
