@@ -170,7 +170,7 @@ def cpu_baseline(case, steps=6, threads=None):
                       f"solid particles) from the initial state, FP64 C/OpenMP oracle, {dt:.1f} s"}
 
 
-def run_serving(n, steps, scale, budget_gb, slots, seeds, precision="mixed"):
+def run_serving(n, steps, scale, budget_gb, slots, seeds, precision="mixed", policies=("all", "shortest")):
     """Parameter-sweep serving: continuous batching vs one solve at a time.
 
     Requests: shaft speed U(150, 600) rad/s, immersion U(20, 60) mm, nu
@@ -179,7 +179,9 @@ def run_serving(n, steps, scale, budget_gb, slots, seeds, precision="mixed"):
     first (one slot); arrivals are Poisson with rate 0.85 / mean service
     time; the one-at-a-time server's latencies follow exactly from the
     measured service times (FIFO); the batched server is run live on the
-    same requests and arrival times.
+    same requests and arrival times, once per scheduling policy ("all":
+    every admitted solve stepped together; "shortest": shortest remaining
+    time first with aging, batched up to the device's fill).
     """
     import torch
     from paper_2512_09904_amd import serve, sph
@@ -224,31 +226,36 @@ def run_serving(n, steps, scale, budget_gb, slots, seeds, precision="mixed"):
             fin[k] = start + svc[k]
             free = fin[k]
         lat1 = fin - arr
-        for r, a in zip(reqs, arr):
-            r.arrival = float(a)
-            r.admitted = r.finished = r.report = None
-        srv = serve.Server(budget, max_slots=slots, precision=precision)
-        a = time.perf_counter()
-        ndone = [0]
+        entry = dict(seed=seed, rate_per_s=rate,
+                     one_at_a_time=dict(p50_s=float(np.percentile(lat1, 50)),
+                                        p95_s=float(np.percentile(lat1, 95)),
+                                        p99_s=float(np.percentile(lat1, 99)),
+                                        wall_s=float(fin.max()),
+                                        particle_steps_per_s=float(sum(r.case.nf * r.steps for r in reqs) / fin.max())),
+                     batched={}, peak_slots={}, peak_gb={}, results_equal_alone=True)
+        for policy in policies:
+            for r, a in zip(reqs, arr):
+                r.arrival = float(a)
+                r.admitted = r.finished = r.report = None
+            srv = serve.Server(budget, max_slots=slots, precision=precision, policy=policy)
+            a = time.perf_counter()
+            ndone = [0]
 
-        def progress(r, nact, nq, npend):
-            ndone[0] += 1
-            if ndone[0] % 8 == 0:
-                log(f"batched: {ndone[0]} done, {nact} active, {nq} queued, {npend} not arrived")
+            def progress(r, nact, nq, npend):
+                ndone[0] += 1
+                if ndone[0] % 8 == 0:
+                    log(f"batched ({policy}): {ndone[0]} done, {nact} active, {nq} queued, {npend} not arrived")
 
-        srv.run(reqs, progress=progress)
-        wall = time.perf_counter() - a
-        summ = serve.summarize(reqs, wall)
-        same = all(np.array_equal(r.report["bodies"][1]["torque_axis"], r.alone["bodies"][1]["torque_axis"]) and
-                   r.report["heat_total"] == r.alone["heat_total"] for r in reqs)
-        results.append(dict(seed=seed, rate_per_s=rate, batched=summ, peak_slots=srv.peak_active,
-                            peak_gb=srv.peak_bytes / (1 << 30), results_equal_alone=bool(same),
-                            one_at_a_time=dict(p50_s=float(np.percentile(lat1, 50)),
-                                               p95_s=float(np.percentile(lat1, 95)),
-                                               p99_s=float(np.percentile(lat1, 99)),
-                                               wall_s=float(fin.max()),
-                                               particle_steps_per_s=float(sum(r.case.nf * r.steps for r in reqs) / fin.max()))))
-        srv.close()
+            srv.run(reqs, progress=progress)
+            wall = time.perf_counter() - a
+            same = all(np.array_equal(r.report["bodies"][1]["torque_axis"], r.alone["bodies"][1]["torque_axis"]) and
+                       r.report["heat_total"] == r.alone["heat_total"] for r in reqs)
+            entry["batched"][policy] = serve.summarize(reqs, wall)
+            entry["peak_slots"][policy] = srv.peak_active
+            entry["peak_gb"][policy] = srv.peak_bytes / (1 << 30)
+            entry["results_equal_alone"] = entry["results_equal_alone"] and bool(same)
+            srv.close()
+        results.append(entry)
         log(json.dumps(results[-1]))
     workload = (f"{len(reqs)} serving-tank requests (fluid {sum(r.case.nf for r in reqs)} in total), {steps} steps "
                 f"each, Poisson arrivals at 0.85/mean service, budget {budget_gb} GB, {slots} slots, particle "
@@ -260,7 +267,7 @@ def serve_bench(args):
     """The full serving sweep as its own JSON line."""
     res = run_serving(args.serve_n, args.serve_steps, args.serve_scale, args.serve_budget_gb, args.serve_slots,
                       args.serve_seeds)
-    b = res["seeds"][0]["batched"]
+    b = res["seeds"][0]["batched"]["shortest" if "shortest" in res["seeds"][0]["batched"] else "all"]
     out = {"metric": "serving sweep: p50/p99 time-to-result and throughput, batched vs one at a time",
            "value": b["particle_steps_per_s"], "unit": "fluid particle-steps/s", "n_gpus": 1,
            "higher_is_better": True, "data": "synthetic", "dtype": "f32+f64",
@@ -277,10 +284,11 @@ def serve_quick(args):
                       args.serve_slots, args.quick_serve_seeds)
     rows = []
     for e in res["seeds"]:
-        b, o = e["batched"], e["one_at_a_time"]
+        o = e["one_at_a_time"]
+        keys = ("p50_s", "p95_s", "p99_s", "particle_steps_per_s")
         rows.append({"seed": e["seed"],
-                     "batched": {k: b[k] for k in ("p50_s", "p95_s", "p99_s", "particle_steps_per_s")},
-                     "one_at_a_time": {k: o[k] for k in ("p50_s", "p95_s", "p99_s", "particle_steps_per_s")},
+                     "batched": {pol: {k: b[k] for k in keys} for pol, b in e["batched"].items()},
+                     "one_at_a_time": {k: o[k] for k in keys},
                      "peak_slots": e["peak_slots"], "results_equal_alone": e["results_equal_alone"]})
     return {"workload": res["workload"], "unit": "s (time to result), fluid particle-steps/s",
             "mean_service_alone_s": res["mean_service_alone_s"], "seeds": rows}

@@ -324,8 +324,18 @@ int sph_pool_admit(sph_pool* pool, const sph_params* p, int32_t nbody, const sph
                    int64_t nf, const double* x, const double* v, const double* rho,
                    const double* T, const int32_t* material, int64_t ns, const double* x0,
                    const double* n0, const int32_t* body, int64_t target_steps, int32_t* slot);
-/* Enqueue n advection steps for every active slot in batched launches. */
+/* Enqueue n advection steps for every active slot that is not held, in
+ * batched launches. */
 int sph_pool_step(sph_pool* pool, int32_t n_adv_steps);
+/* Hold (hold = 1) or resume (hold = 0) an admitted slot.  A held slot is left
+ * out of later sph_pool_step calls: its state stays resident and unchanged and
+ * it keeps its share of the budget; a resumed slot continues where it stopped,
+ * with the same result as if it had never been held.  A scheduler uses this to
+ * give the device to a subset of the admitted solves (the shortest remaining
+ * ones, say).  A change of the stepped set makes the next sph_pool_step
+ * capture a new step graph.  SPH_ERR_ARG for a slot not in use or a hold flag
+ * other than 0 or 1. */
+int sph_pool_hold(sph_pool* pool, int32_t slot, int32_t hold);
 /* Non-blocking: *done = 1 once the slot has finished its target steps (or
  * faulted) and its work has completed on the device; then reports are filled.
  * The return value carries the slot's latched fault, if any.  Until the

@@ -307,6 +307,7 @@ struct SlotHost {
   int32_t nbody = 0;
   sph_body bodies[NB];
   int64_t target = 0, launched = 0;
+  bool held = false;               // left out of pool steps until resumed
   hipEvent_t ev_done = nullptr;
   bool ev_recorded = false;
   hipEvent_t ev_admit = nullptr;   // the slot's upload has completed on the main stream
@@ -523,7 +524,7 @@ static void recompose(sph_pool* P) {
   int nac = 1;
   for (int s = 0; s < P->max_slots; ++s) {
     const SlotHost& S = P->slots[s];
-    if (S.used && S.launched < S.target) {
+    if (S.used && !S.held && S.launched < S.target) {
       act.push_back(s);
       nac = std::max(nac, S.d.nac_bound);
     }
@@ -858,6 +859,17 @@ static int pool_step(sph_pool* P, int32_t n) {
 }
 
 extern "C" int sph_pool_step(sph_pool* P, int32_t n) { return pool_step(P, n); }
+
+extern "C" int sph_pool_hold(sph_pool* P, int32_t slot, int32_t hold) {
+  if (!P || slot < 0 || slot >= P->max_slots || !P->slots[slot].used) return fail(SPH_ERR_ARG, "bad slot");
+  if (hold != 0 && hold != 1) return fail(SPH_ERR_ARG, "hold must be 0 or 1");
+  SlotHost& S = P->slots[slot];
+  if (S.held != (hold == 1)) {
+    S.held = hold == 1;
+    P->comp_dirty = true;
+  }
+  return SPH_OK;
+}
 
 static int read_ctl(sph_pool* P, SlotHost& S, SlotCtl* ctl, bool sync_main) {
   if (sync_main) {

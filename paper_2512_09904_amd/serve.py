@@ -3,12 +3,17 @@
 Requests arrive over time (Poisson arrivals in the sweep workload).  A
 request is admitted into a slot of the HIP pool as soon as a slot and enough
 of the HBM budget are free; its particle state stays resident on the GPU
-until it finishes.  All admitted solves advance together: every pool step is
+until it finishes.  Admitted solves advance together: every pool step is
 one batched launch sequence (a captured hipGraph per slot composition) over
-all active slots, so work of requests that arrived at different times
-overlaps on the device.  Finished slots are released at once and queued
-requests take their place.  Each solve's result does not depend on its
-neighbours in the batch (slot-aligned blocks, deterministic reductions).
+the stepped slots, so work of requests that arrived at different times
+overlaps on the device.  Which admitted slots are stepped is the policy:
+"all" steps every one (processor sharing); "shortest" orders them by
+remaining time less a credit for time waited, steps the first ones, enough
+of them to fill the device and more only while that slows the first by a
+bounded factor, and holds the rest (see `shortest_first`).
+Finished slots are released at once and queued requests take their place.
+Each solve's result does not depend on its neighbours in the batch, nor on
+when it was held (slot-aligned blocks, deterministic reductions).
 """
 from __future__ import annotations
 
@@ -23,7 +28,7 @@ import numpy as np
 from . import cases, sph
 
 
-@dataclasses.dataclass
+@dataclasses.dataclass(eq=False)
 class Request:
     rid: int
     arrival: float          # seconds after the start of the run
@@ -33,6 +38,8 @@ class Request:
     finished: Optional[float] = None
     report: Optional[dict] = None
     slot: Optional[int] = None
+    remaining: int = 0      # advection steps not yet enqueued
+    held: bool = False
 
     @property
     def latency(self):
@@ -61,13 +68,57 @@ def sweep_requests(n=64, seed=64, steps=500, nf_lo=5e4, nf_hi=2e6, rate=None, sc
     return reqs
 
 
+# time of one advection step of a slot of n fluid particles stepped alone:
+# STEP_COST[0] + STEP_COST[1] * n seconds (serving tank on one MI355X; the
+# fixed part is the launch sequence, the rest the sweeps)
+STEP_COST = (0.57e-3, 3.3e-9)
+
+
+def priority(r: Request, now: float, aging: float, cost=STEP_COST) -> float:
+    """Scheduling key of the "shortest" policy (smaller first): the request's
+    remaining time if it ran alone, less `aging` times the time since it
+    arrived, so a long request that has waited gains on newer short ones."""
+    return r.remaining * (cost[0] + cost[1] * r.case.nf) - aging * (now - r.arrival)
+
+
+def shortest_first(active: dict, fill: int, now: float = 0.0, aging: float = 0.0, slowdown: float = 0.0,
+                   cost=STEP_COST) -> set:
+    """Slots to step under the "shortest" policy.  The admitted requests are
+    taken in order of `priority` (ties by arrival, then slot): the first one
+    always; each next one while the fluid particles taken are below `fill`
+    (too few to keep the device busy), and beyond that only if the batched
+    step stays within (1 + slowdown) times the first request's step alone.
+    A request whose steps are all enqueued is neither stepped nor held (it
+    is finishing on the device)."""
+    order = sorted(((s, r) for s, r in active.items() if r.remaining > 0),
+                   key=lambda kv: (priority(kv[1], now, aging, cost), kv[1].arrival, kv[0]))
+    run, acc, limit = set(), 0, 0.0
+    for slot, r in order:
+        if not run:
+            limit = (1.0 + slowdown) * (cost[0] + cost[1] * r.case.nf)
+        elif acc >= fill and cost[0] + cost[1] * (acc + r.case.nf) > limit:
+            continue
+        run.add(slot)
+        acc += r.case.nf
+    return run
+
+
 class Server:
-    """Admits requests by HBM budget and free slots; steps all active slots together."""
+    """Admits requests by HBM budget and free slots; steps the admitted slots
+    that the policy picks ("all" or "shortest", see the module text)."""
 
     def __init__(self, hbm_budget: int, max_slots: int = 16, precision: str = "mixed",
-                 steps_per_call: int = 10, graph: bool = True, pool=None):
+                 steps_per_call: int = 10, graph: bool = True, pool=None, policy: str = "all",
+                 fill: int = 1_000_000, slowdown: float = 0.5, aging: float = 2.0, cost=STEP_COST):
+        if policy not in ("all", "shortest"):
+            raise ValueError(f"unknown policy {policy!r}")
         self.pool = pool if pool is not None else sph.Pool(hbm_budget, max_slots=max_slots,
                                                            precision=precision, graph=graph)
+        self.policy = policy
+        self.fill = int(fill)
+        self.slowdown = float(slowdown)
+        self.aging = float(aging)
+        self.cost = cost
         self.precision = precision
         self.k = steps_per_call
         self.max_slots = max_slots
@@ -92,21 +143,39 @@ class Server:
             while pending and pending[0].arrival <= now:
                 queue.append(pending.popleft())
             while queue:
-                r = queue[0]
+                # "all": arrival order; "shortest": priority order
+                if self.policy == "all":
+                    r = queue[0]
+                else:
+                    for q in queue:
+                        q.remaining = q.steps
+                    r = min(queue, key=lambda q: (priority(q, now, self.aging, self.cost), q.arrival))
                 if self.pool.bytes_required(r.case, self.precision) > self.budget:
                     raise ValueError(f"request {r.rid} can never fit the HBM budget")
                 slot = self.pool.admit(r.case, r.steps)
                 if slot is None:
                     break
-                queue.popleft()
+                queue.remove(r)
                 r.slot = slot
                 r.admitted = clock() - t0
+                r.remaining = r.steps
+                r.held = False
                 active[slot] = r
             used, nact = self.pool.usage()
             self.peak_bytes = max(self.peak_bytes, used)
             self.peak_active = max(self.peak_active, nact)
             if active:
+                if self.policy == "shortest":
+                    run = shortest_first(active, self.fill, clock() - t0, self.aging, self.slowdown, self.cost)
+                    for slot, r in active.items():
+                        want = slot not in run
+                        if r.held != want:
+                            self.pool.hold(slot, want)
+                            r.held = want
                 self.pool.step(self.k)
+                for r in active.values():
+                    if not r.held:
+                        r.remaining = max(0, r.remaining - self.k)
                 if torch is not None:
                     ev = torch.cuda.Event()
                     ev.record(self.pool.stream)

@@ -119,7 +119,7 @@ def lib():
 EXPORTS = ["sph_error_string", "sph_last_error", "sph_create", "sph_set_bodies", "sph_set_fluid", "sph_set_solid",
            "sph_init", "sph_step", "sph_reduce", "sph_contact_factor", "sph_contact_factor_noalloc", "sph_relax", "sph_get_fluid", "sph_set_graph", "sph_set_timing",
            "sph_get_timing", "sph_dump_size", "sph_debug_dump", "sph_debug_poke_velocity", "sph_destroy",
-           "sph_bytes_required", "sph_pool_create", "sph_pool_admit", "sph_pool_step", "sph_pool_poll",
+           "sph_bytes_required", "sph_pool_create", "sph_pool_admit", "sph_pool_step", "sph_pool_hold", "sph_pool_poll",
            "sph_pool_get_fluid", "sph_pool_release", "sph_pool_usage", "sph_pool_set_graph", "sph_pool_destroy"]
 
 
@@ -410,6 +410,10 @@ class Pool:
 
     def step(self, n=1):
         check(lib().sph_pool_step(self.h, C.c_int32(n)), "sph_pool_step")
+
+    def hold(self, slot, hold=True):
+        """Leave the slot out of later steps (hold=True) or step it again (False)."""
+        check(lib().sph_pool_hold(self.h, C.c_int32(slot), C.c_int32(1 if hold else 0)), "sph_pool_hold")
 
     def poll(self, slot):
         """(done, report or None); a faulted slot reports done with report['rc'] != 0."""

@@ -4,6 +4,7 @@ Each request's result must be identical (bitwise) whether it runs alone or
 batched with others admitted at different times, since slots own whole
 blocks and every reduction has a fixed order.
 """
+import ctypes
 import sys
 import time
 
@@ -88,6 +89,63 @@ def test_alone_equals_in_mix(sph):
         assert ra["bodies"][1]["torque_axis"] == rm["bodies"][1]["torque_axis"]
         assert ra["heat_total"] == rm["heat_total"]
 
+
+
+def test_held_slot_is_unchanged_and_resumes_to_its_solo_result(sph):
+    """A held slot is left out of pool steps: its state and report do not
+    move while the others step, it does not finish, and once resumed it ends
+    bitwise where its solo run ends; the slots stepped meanwhile are not
+    disturbed either."""
+    reqs = _requests()
+    steps = [6, 8, 5]
+    say("serving: hold and resume")
+    alone = {q: _run_pool(sph, [reqs[q]], [steps[q]], [0])[0] for q in range(3)}
+    pool = sph.Pool(1 << 40, max_slots=4)
+    slots = [pool.admit(reqs[q], steps[q]) for q in range(3)]
+    pool.step(2)
+    pool.hold(slots[0])
+    pool.hold(slots[2])
+    before = [pool.get_fluid(slots[q]) for q in (0, 2)]
+    pool.step(3)                      # only request 1 steps
+    after = [pool.get_fluid(slots[q]) for q in (0, 2)]
+    for b, a in zip(before, after):
+        for key in ("x", "v", "rho", "T"):
+            assert np.array_equal(a[key], b[key]), key
+    assert not pool.poll(slots[0])[0] and not pool.poll(slots[2])[0]
+    pool.hold(slots[1])               # every slot held: a step does nothing
+    mid = pool.get_fluid(slots[1])
+    pool.step(2)
+    assert all(np.array_equal(pool.get_fluid(slots[1])[k], mid[k]) for k in ("x", "v", "rho", "T"))
+    pool.hold(slots[0], False)
+    pool.hold(slots[0], False)        # resuming twice is harmless
+    pool.hold(slots[1], False)
+    pool.hold(slots[2], False)
+    out = {}
+    for _ in range(20):
+        pool.step(1)
+        for q in range(3):
+            if q not in out:
+                done, rep = pool.poll(slots[q])
+                if done:
+                    out[q] = (pool.get_fluid(slots[q]), rep)
+        if len(out) == 3:
+            break
+    for q in range(3):
+        ga, ra = alone[q]
+        gm, rm = out[q]
+        assert rm["rc"] == 0 and rm["step"] == steps[q] == ra["step"]
+        for key in ("x", "v", "rho", "T"):
+            assert np.array_equal(ga[key], gm[key]), (q, key)
+        assert ra["bodies"][1]["torque_axis"] == rm["bodies"][1]["torque_axis"]
+        assert ra["heat_total"] == rm["heat_total"] and ra["t"] == rm["t"]
+    # a slot that is not in use, and a flag other than 0 or 1, are refused
+    pool.release(slots[1])
+    with pytest.raises(sph.SphError) as e:
+        pool.hold(slots[1])
+    assert e.value.code == sph.SPH_ERR_ARG
+    rc = sph.lib().sph_pool_hold(pool.h, ctypes.c_int32(slots[0]), ctypes.c_int32(2))
+    assert rc == sph.SPH_ERR_ARG
+    pool.close()
 
 
 def test_alone_equals_in_mix_with_viscous_heating(sph):
