@@ -284,6 +284,11 @@ int sph_debug_dump(sph_solver* s, int32_t what, void* buf, size_t bytes);
 /* Overwrite one fluid particle's velocity (fault-handling tests; the host
  * makes the state non-finite, no kernel is perturbed). */
 int sph_debug_poke_velocity(sph_solver* s, int64_t original_index, const double* v3);
+/* enable = 1 (the default): the first acoustic sub-step's opening half update
+ * and momentum run inside the viscous/heat sweep; 0: as launches of their
+ * own.  Both give the same state bit for bit (the parity tests check it).
+ * SPH_ERR_ARG for another value. */
+int sph_debug_set_fusion(sph_solver* s, int32_t enable);
 int sph_destroy(sph_solver* s);
 
 /* kernels of one advection step (timing ids) */

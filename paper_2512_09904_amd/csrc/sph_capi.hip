@@ -339,6 +339,7 @@ struct sph_pool {
   SlotDesc* d_table = nullptr;
   SlotHost slots[MAX_SLOTS];
   bool use_graph = true, timing = false, comp_dirty = true;
+  bool fuse_first = true;   // sub-step 0's half update and momentum inside the viscous/heat sweep
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   LaunchTab tab{};
@@ -483,11 +484,19 @@ static int enqueue_sort_build(sph_pool* P, const LaunchTab& T, bool timed = true
 static int enqueue_step(sph_pool* P, const LaunchTab& T, int nac) {
   LCHK(enqueue_sort_build(P, T));
   LCHK(launch(P, T, SPH_K_DT, 0, 0));
-  LCHK(launch(P, T, SPH_K_VISC_HEAT, 0, 0));
   // sub-step s: momentum, then continuity, which also closes s and opens
-  // s + 1 (the first opening half update is its own launch)
-  LCHK(launch(P, T, SPH_K_HALF_A, 0, 0));
-  for (int s = 0; s < nac; ++s) {
+  // s + 1; the viscous/heat sweep runs sub-step 0's opening half and momentum
+  // (unfused: their own launches, the same arithmetic)
+  int s0 = 0;
+  if (P->fuse_first) {
+    LCHK(launch(P, T, SPH_K_VISC_HEAT, 1, 0));
+    LCHK(launch(P, T, SPH_K_CONTINUITY, 0, 0));
+    s0 = 1;
+  } else {
+    LCHK(launch(P, T, SPH_K_VISC_HEAT, 0, 0));
+    LCHK(launch(P, T, SPH_K_HALF_A, 0, 0));
+  }
+  for (int s = s0; s < nac; ++s) {
     LCHK(launch(P, T, SPH_K_MOMENTUM, 0, s));
     LCHK(launch(P, T, SPH_K_CONTINUITY, 0, s));
   }
@@ -1465,6 +1474,14 @@ extern "C" int sph_debug_dump(sph_solver* s, int32_t what, void* buf, size_t byt
     }
     default: return fail(SPH_ERR_ARG, "unknown dump selector");
   }
+}
+
+extern "C" int sph_debug_set_fusion(sph_solver* s, int32_t enable) {
+  if (!s) return fail(SPH_ERR_ARG, "NULL solver");
+  if (enable != 0 && enable != 1) return fail(SPH_ERR_ARG, "enable must be 0 or 1");
+  s->pool->fuse_first = enable == 1;
+  drop_graph(s->pool);
+  return SPH_OK;
 }
 
 extern "C" int sph_debug_poke_velocity(sph_solver* s, int64_t orig, const double* v3) {

@@ -1114,13 +1114,29 @@ __device__ __forceinline__ void grad_add(Real* G, Real c, Real dx, Real dy, Real
 // MAT: the launch holds a slot with several fluid materials: k and cp per
 // particle (material index gathered per neighbour), K_ij = 4 k_i k_j /
 // (k_i + k_j) from a per-block table.
+// MOM0: the same pass also runs the first acoustic sub-step's opening half
+// (rho + dt/2 Drho, x + dt/2 v) and its Riemann momentum update, which read
+// the same neighbours and frozen pair vectors: each neighbour's half-step
+// density is formed from its gathered state and Drho with the arithmetic of
+// the separate half update, so the results equal the unfused sequence bit
+// for bit and a fluid pair costs four gathers instead of five.
 // ---------------------------------------------------------------------------
-template <class P, bool DISS, bool MAT>
-__global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, LaunchTab tab) {
+// the fused variant without dissipation is held to VISC_MOM0_WAVES waves per
+// SIMD (VISC_MOM0_WAVES_F64 in FP64): a few spilled registers cost less than
+// the lost latency hiding
+#ifndef VISC_MOM0_WAVES_F64
+#define VISC_MOM0_WAVES_F64 1
+#endif
+#define VISC_MOM0_WAVES 3
+template <class P, bool DISS, bool MAT, bool MOM0>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(
+    MOM0 && !DISS ? (std::is_same<typename P::Real, double>::value ? VISC_MOM0_WAVES_F64 : VISC_MOM0_WAVES) : 1)))
+void k_visc_heat(const SlotDesc* table, LaunchTab tab) {
   typedef typename P::Real Real;
   typedef typename P::Temp Temp;
   typedef typename P::Real4 Real4;
   __shared__ double lds[4 * NB * 7];
+  __shared__ double lds_p[MOM0 ? 4 * NB * 6 : 1];
   __shared__ double lds_d[BLOCK / WAVE];
   __shared__ Real Ktab[MAT ? NMAT * NMAT : 1];
   SLOT_PROLOGUE(DOM_FLUID);
@@ -1138,12 +1154,15 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
   if (threadIdx.x < NB * 6) S.press_part[(size_t)threadIdx.x * nbf + lb] = 0.0;
   BodyAcc<7> acc;
   acc.init();
+  BodyAcc<6> pacc;   // MOM0: pressure force and torque of the first sub-step
+  pacc.init();
   bool wall = false;
   double vphi = 0.0;   // V_i Phi_i
   if (i < nf) {
     const GLB Real4* vr = gpc<Real4>(S.vr);
     const GLB Temp* T = gpc<Temp>(S.T);
     const GLB Real4* xo = gpc<Real4>(S.xo);
+    const GLB Real* drho = gpc<Real>(S.drho);
     const Real m = (Real)S.mass;
     const Real inv_h = (Real)(1.0 / S.h), kF = (Real)S.kF, csr = (Real)S.cs_r;
     const Real4 vi = vr[i];
@@ -1159,6 +1178,18 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
     Real G[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) G[q] = 0;
+    // MOM0: own half-step state (density opened by dt/2 Drho) and the
+    // pressure acceleration of the first sub-step
+    Real hdt = 0, wih = 0, rhoih = 0, pih = 0, c2p = 0, c0 = 0;
+    Real px = 0, py = 0, pz = 0;
+    if constexpr (MOM0) {
+      hdt = (Real)(0.5 * S.ctl->dt);
+      wih = vi.w + hdt * drho[i];
+      rhoih = rho_abs<P>(S, wih);
+      pih = press<P>(S, wih);
+      c2p = (Real)2 * rcp(rhoih);
+      c0 = (Real)S.c0;
+    }
     const int lane = i & (WAVE - 1);
     const int64_t slice = i >> 6;
     {
@@ -1173,11 +1204,13 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
         for (int u = 0; u < ROW_UNROLL; ++u) j[u] = k + u < n ? jn[u] : (uint32_t)i;
         Real4 vj[ROW_UNROLL], oj[ROW_UNROLL];
         Temp Tj[ROW_UNROLL];
+        Real dj[ROW_UNROLL];
 #pragma unroll
         for (int u = 0; u < ROW_UNROLL; ++u) {
           oj[u] = xo[j[u]];
           vj[u] = vr[j[u]];
           Tj[u] = T[j[u]];
+          if constexpr (MOM0) dj[u] = drho[j[u]];
         }
         if (k + ROW_UNROLL < n) {
 #pragma unroll
@@ -1187,7 +1220,8 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
         for (int u = 0; u < ROW_UNROLL; ++u) {
           Real rx, ry, rz;
           pair_vec(oi, ci, oj[u], csr, rx, ry, rz);
-          const Real Fk = k + u < n ? kernel_F(rx * rx + ry * ry + rz * rz, inv_h, kF) : (Real)0;
+          const Real r2 = rx * rx + ry * ry + rz * rz;
+          const Real Fk = k + u < n ? kernel_F(r2, inv_h, kF) : (Real)0;
           const Real Vj = m * rcp(rho_abs<P>(S, vj[u].w));
           const Real cv = c2 * Vj * Fk;
           ax += cv * (vi.x - vj[u].x);
@@ -1196,6 +1230,20 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
           const Real Kij = mats ? Ktab[mi * NMAT + S.mat[j[u]]] : Kff;
           hs += Vj * Kij * (Real)(Ti - Tj[u]) * Fk;
           if (DISS) grad_add(G, Vj * Fk, vj[u].x - vi.x, vj[u].y - vi.y, vj[u].z - vi.z, rx, ry, rz);
+          if constexpr (MOM0) {
+            // eq. 10-12 at the half-step densities, velocities of the step's start
+            const Real inv = r2 > (Real)0 ? rsq(r2) : (Real)0;
+            const Real wjh = vj[u].w + hdt * dj[u];
+            const Real rhoj = rho_abs<P>(S, wjh);
+            const Real pj = press<P>(S, wjh);
+            const Real dU = -((vi.x - vj[u].x) * rx + (vi.y - vj[u].y) * ry + (vi.z - vj[u].z) * rz) * inv;
+            const Real beta = fmin((Real)3 * fmax(dU, (Real)0), c0);
+            const Real ps = (Real)0.5 * (pih + pj) + rhoih * rhoj * beta * dU * rcp(rhoih + rhoj);
+            const Real sp = -c2p * (m * rcp(rhoj)) * ps * Fk;
+            px += sp * rx;
+            py += sp * ry;
+            pz += sp * rz;
+          }
         }
       }
     }
@@ -1249,6 +1297,20 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
         const double contrib[7] = {gx, gy, gz, ly * gz - lz * gy, lz * gx - lx * gz, lx * gy - ly * gx,
                                    (double)m * cpI * (double)(rc * term)};
         if (!acc.add(b, contrib)) raise_flag(S, F_CAPACITY);
+        if constexpr (MOM0) {
+          // the wall pressure of the one-sided Riemann problem (eq. 16-19)
+          const Real PR = pih - rhoih * ((Real)S.g[0] * rx + (Real)S.g[1] * ry + (Real)S.g[2] * rz);
+          const Real rhoR = (Real)S.rho0 + PR * (Real)(1.0 / (S.c0 * S.c0));
+          const Real ps = (rhoih * PR + rhoR * pih) * rcp(rhoih + rhoR);
+          const Real sp = -c2p * Vw * ps * Fk;
+          const Real qx = sp * rx, qy = sp * ry, qz = sp * rz;
+          px += qx;
+          py += qy;
+          pz += qz;
+          const double hx = -(double)m * qx, hy = -(double)m * qy, hz = -(double)m * qz;
+          const double pc[6] = {hx, hy, hz, ly * hz - lz * hy, lz * hx - lx * hz, lx * hy - ly * hx};
+          if (!pacc.add(b, pc)) raise_flag(S, F_CAPACITY);
+        }
         }
       }
       if (DISS && S.diss) {
@@ -1266,12 +1328,34 @@ __global__ __launch_bounds__(BLOCK) void k_visc_heat(const SlotDesc* table, Laun
       a.z = az;
       a.w = rc * hs;
       gp<Real4>(S.ah)[i] = a;
+      if constexpr (MOM0) {
+        // v_new = v + dt (a_p + a_visc + g); the opening and the closing half
+        // drifts x += dt/2 v, x += dt/2 v_new, in that order
+        const Real dt = (Real)S.ctl->dt;
+        Real4 vn;
+        vn.x = vi.x + dt * (px + ax + (Real)S.g[0]);
+        vn.y = vi.y + dt * (py + ay + (Real)S.g[1]);
+        vn.z = vi.z + dt * (pz + az + (Real)S.g[2]);
+        vn.w = wih;
+        gp<Real4>(S.vrn)[i] = vn;
+        GLB Real4* dr = gp<Real4>(S.drift);
+        Real4 d = dr[i];
+        d.x += hdt * vi.x;
+        d.y += hdt * vi.y;
+        d.z += hdt * vi.z;
+        d.x += hdt * vn.x;
+        d.y += hdt * vn.y;
+        d.z += hdt * vn.z;
+        dr[i] = d;
+      }
     }
   }
-  if (__syncthreads_or(wall))
+  if (__syncthreads_or(wall)) {
     block_body_reduce<7>(acc, S.nbody, S.visc_part, nbf, lb, false, lds);
-  else if (threadIdx.x < NB * 7)
+    if constexpr (MOM0) block_body_reduce<6>(pacc, S.nbody, S.press_part, nbf, lb, true, lds_p);
+  } else if (threadIdx.x < NB * 7) {
     S.visc_part[(size_t)threadIdx.x * nbf + lb] = 0.0;
+  }
   if (DISS && S.diss) {
     const double sw = wave_sum(vphi);
     if ((threadIdx.x & (WAVE - 1)) == 0) lds_d[threadIdx.x / WAVE] = sw;
@@ -1817,12 +1901,21 @@ static hipError_t launch_p(int kid, int which, int sub, const SlotDesc* T, const
     case SPH_K_WALLVEL: hipLaunchKernelGGL(k_wallvel<P>, g, b, 0, st, T, L); break;
     case SPH_K_DT: hipLaunchKernelGGL(k_dt, g, b, 0, st, T, L); break;
     case SPH_K_VISC_HEAT:
-      if (L.flags & TAB_MAT) {
-        if (L.flags & TAB_DISS) hipLaunchKernelGGL((k_visc_heat<P, true, true>), g, b, 0, st, T, L);
-        else hipLaunchKernelGGL((k_visc_heat<P, false, true>), g, b, 0, st, T, L);
+      // which = 1: with the first acoustic sub-step's half update and momentum
+      if (which == 1) {
+        if (L.flags & TAB_MAT) {
+          if (L.flags & TAB_DISS) hipLaunchKernelGGL((k_visc_heat<P, true, true, true>), g, b, 0, st, T, L);
+          else hipLaunchKernelGGL((k_visc_heat<P, false, true, true>), g, b, 0, st, T, L);
+        } else {
+          if (L.flags & TAB_DISS) hipLaunchKernelGGL((k_visc_heat<P, true, false, true>), g, b, 0, st, T, L);
+          else hipLaunchKernelGGL((k_visc_heat<P, false, false, true>), g, b, 0, st, T, L);
+        }
+      } else if (L.flags & TAB_MAT) {
+        if (L.flags & TAB_DISS) hipLaunchKernelGGL((k_visc_heat<P, true, true, false>), g, b, 0, st, T, L);
+        else hipLaunchKernelGGL((k_visc_heat<P, false, true, false>), g, b, 0, st, T, L);
       } else {
-        if (L.flags & TAB_DISS) hipLaunchKernelGGL((k_visc_heat<P, true, false>), g, b, 0, st, T, L);
-        else hipLaunchKernelGGL((k_visc_heat<P, false, false>), g, b, 0, st, T, L);
+        if (L.flags & TAB_DISS) hipLaunchKernelGGL((k_visc_heat<P, true, false, false>), g, b, 0, st, T, L);
+        else hipLaunchKernelGGL((k_visc_heat<P, false, false, false>), g, b, 0, st, T, L);
       }
       break;
     case SPH_K_HALF_A: hipLaunchKernelGGL(k_half_a<P>, g, b, 0, st, T, L, sub); break;

@@ -8,9 +8,9 @@ one batched launch sequence (a captured hipGraph per slot composition) over
 the stepped slots, so work of requests that arrived at different times
 overlaps on the device.  Which admitted slots are stepped is the policy:
 "all" steps every one (processor sharing); "shortest" orders them by
-remaining time less a credit for time waited, steps the first ones, enough
-of them to fill the device and more only while that slows the first by a
-bounded factor, and holds the rest (see `shortest_first`).
+remaining time less a credit for time waited, steps the first one and those
+that fit beside it without slowing it beyond a bound, and holds the rest
+(see `shortest_first`).
 Finished slots are released at once and queued requests take their place.
 Each solve's result does not depend on its neighbours in the batch, nor on
 when it was held (slot-aligned blocks, deterministic reductions).
@@ -85,18 +85,18 @@ def shortest_first(active: dict, fill: int, now: float = 0.0, aging: float = 0.0
                    cost=STEP_COST) -> set:
     """Slots to step under the "shortest" policy.  The admitted requests are
     taken in order of `priority` (ties by arrival, then slot): the first one
-    always; each next one while the fluid particles taken are below `fill`
-    (too few to keep the device busy), and beyond that only if the batched
-    step stays within (1 + slowdown) times the first request's step alone.
-    A request whose steps are all enqueued is neither stepped nor held (it
-    is finishing on the device)."""
+    always, each next one only if the batched step stays within the larger
+    of (1 + slowdown) times the first one's step alone and the step of
+    `fill` particles (small requests share the device freely, a large one
+    does not slow a small one down).  A request whose steps are all enqueued
+    is neither stepped nor held (it is finishing on the device)."""
     order = sorted(((s, r) for s, r in active.items() if r.remaining > 0),
                    key=lambda kv: (priority(kv[1], now, aging, cost), kv[1].arrival, kv[0]))
     run, acc, limit = set(), 0, 0.0
     for slot, r in order:
         if not run:
-            limit = (1.0 + slowdown) * (cost[0] + cost[1] * r.case.nf)
-        elif acc >= fill and cost[0] + cost[1] * (acc + r.case.nf) > limit:
+            limit = max((1.0 + slowdown) * (cost[0] + cost[1] * r.case.nf), cost[0] + cost[1] * fill)
+        elif cost[0] + cost[1] * (acc + r.case.nf) > limit:
             continue
         run.add(slot)
         acc += r.case.nf
@@ -109,7 +109,7 @@ class Server:
 
     def __init__(self, hbm_budget: int, max_slots: int = 16, precision: str = "mixed",
                  steps_per_call: int = 10, graph: bool = True, pool=None, policy: str = "all",
-                 fill: int = 1_000_000, slowdown: float = 0.5, aging: float = 2.0, cost=STEP_COST):
+                 fill: int = 500_000, slowdown: float = 0.5, aging: float = 4.0, cost=STEP_COST):
         if policy not in ("all", "shortest"):
             raise ValueError(f"unknown policy {policy!r}")
         self.pool = pool if pool is not None else sph.Pool(hbm_budget, max_slots=max_slots,

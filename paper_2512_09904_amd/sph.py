@@ -118,7 +118,7 @@ def lib():
 
 EXPORTS = ["sph_error_string", "sph_last_error", "sph_create", "sph_set_bodies", "sph_set_fluid", "sph_set_solid",
            "sph_init", "sph_step", "sph_reduce", "sph_contact_factor", "sph_contact_factor_noalloc", "sph_relax", "sph_get_fluid", "sph_set_graph", "sph_set_timing",
-           "sph_get_timing", "sph_dump_size", "sph_debug_dump", "sph_debug_poke_velocity", "sph_destroy",
+           "sph_get_timing", "sph_dump_size", "sph_debug_dump", "sph_debug_poke_velocity", "sph_debug_set_fusion", "sph_destroy",
            "sph_bytes_required", "sph_pool_create", "sph_pool_admit", "sph_pool_step", "sph_pool_hold", "sph_pool_poll",
            "sph_pool_get_fluid", "sph_pool_release", "sph_pool_usage", "sph_pool_set_graph", "sph_pool_destroy"]
 
@@ -307,6 +307,10 @@ class Solver:
         check(lib().sph_relax(self.h, C.byref(shape_struct(shape)), C.c_int32(int(iterations)), C.byref(r)),
               "sph_relax")
         return {k: getattr(r, k) for k, _ in RelaxReport._fields_}
+
+    def set_fusion(self, on=True):
+        """Run the first sub-step inside the viscous/heat sweep (default) or unfused."""
+        check(lib().sph_debug_set_fusion(self.h, C.c_int32(1 if on else 0)), "sph_debug_set_fusion")
 
     def set_timing(self, on=True):
         check(lib().sph_set_timing(self.h, C.c_int32(int(on))), "sph_set_timing")

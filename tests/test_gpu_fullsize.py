@@ -304,16 +304,26 @@ def test_two_slab_conduction_on_the_solver():
 # ---------------------------------------------------------------------------
 
 @pytest.mark.skipif(not __import__("os").environ.get("SPH_LONG_TESTS"),
-                    reason="long run (about 6 minutes): set SPH_LONG_TESTS=1")
-@pytest.mark.timeout(1100)
+                    reason="long run (about 6 minutes on the GPU box): set SPH_LONG_TESTS=1")
+@pytest.mark.timeout(1500)
 def test_fp64_mode_tracks_oracle_long_horizon(sph, ora):
     """The FP64 GPU mode, reference of the 1e5-step precision study, against
     the oracle on the precision-stress tank (dp 0.788 mm, 196 k fluid
-    particles, disk at 450 rad/s) for 400 adaptive steps, each side on its
-    own time steps.  Every step dt_ad agrees to 1e-9 and n_ac exactly; the
-    state error, printed every 50 steps, stays below 1e-6 of dp, Umax, the
-    density scale and the temperature span; mass exact; the thermal energy,
-    heat inflow and the time integral of the disk torque agree to 1e-8."""
+    particles, disk at 450 rad/s) for 1000 adaptive steps, each side on its
+    own time steps.
+
+    Steps 1-400: dt_ad agrees to 1e-9 and n_ac exactly every step, and the
+    state error (every 50 steps) stays below 1e-6 of dp, Umax, the density
+    scale and the temperature span.  Beyond that the two FP64 trajectories
+    separate as any two do whose inputs differ in the last bit: the oracle
+    run against itself with every fluid position moved by one ulp drifts to
+    2.5e-7 dp at step 400 (this pair: 1.8e-7) and at step 1000 to 2.7e-4 dp
+    and 5e-4 Umax, with relative differences of 4e-8 in the simulated time
+    and the heat inflow, 2e-9 in the disk's torque integral and 2e-12 in the
+    thermal energy.  So from step 401 on n_ac may differ on at most three
+    steps, and at step 1000 the bars are 25x or more above that one-ulp
+    spread: time, heat inflow and torque integral within 1e-6, thermal
+    energy within 1e-10, the state within 5e-2 (the same flow); mass exact."""
     c = cases.tank_c1(dp=0.788e-3, omega=450.0)
     say("fp64 vs oracle, long horizon", c.nf, c.ns)
     o = ora.State(c)
@@ -321,12 +331,16 @@ def test_fp64_mode_tracks_oracle_long_horizon(sph, ora):
     umax, c0, rho0 = c.meta["umax"], c.params["c0"], c.params["rho0"]
     worst = {}
     tq_o = 0.0
-    for k in range(400):
+    nac_diff = 0
+    for k in range(1000):
         ro = o.step()
         s.step(1)
         rg = s.reduce()
-        assert rg["n_ac"] == ro["n_ac"], k
-        assert rg["dt_ad"] == pytest.approx(ro["dt_ad"], rel=1e-9), k
+        if k < 400:
+            assert rg["n_ac"] == ro["n_ac"], k
+            assert rg["dt_ad"] == pytest.approx(ro["dt_ad"], rel=1e-9), k
+        else:
+            nac_diff += rg["n_ac"] != ro["n_ac"]
         assert rg["mass"] == pytest.approx(ro["mass"], rel=1e-13)
         tq_o += ro["dt_ad"] * ro["bodies"][1]["torque_axis"]
         if (k + 1) % 50 == 0:
@@ -334,11 +348,17 @@ def test_fp64_mode_tracks_oracle_long_horizon(sph, ora):
             e = dict(x=np.max(np.abs(g["x"] - o.x)) / c.params["dp"], v=np.max(np.abs(g["v"] - o.v)) / umax,
                      rho=np.max(np.abs(g["rho"] - o.rho)) / (rho0 * (umax / c0) ** 2),
                      T=np.max(np.abs(g["T"] - o.T)) / 20.0)
-            say(f"step {k + 1}: t {rg['t']:.5f} n_ac {rg['n_ac']} errors {e}")
-            worst = {q: max(worst.get(q, 0.0), v) for q, v in e.items()}
+            say(f"step {k + 1}: t {rg['t']:.5f} n_ac {rg['n_ac']} errors {e} "
+                f"time {abs(rg['t'] / o.t - 1):.2e} heat {abs(rg['heat_total'] / o.cum['heat'] - 1):.2e} "
+                f"torque {abs(rg['bodies'][1]['torque_axis_int'] / tq_o - 1):.2e}")
+            if k < 400:
+                worst = {q: max(worst.get(q, 0.0), v) for q, v in e.items()}
     s.close()
-    say("worst normalised errors over 400 steps", worst)
+    say("worst normalised errors over 400 steps", worst, "n_ac differing past step 400:", nac_diff)
     assert max(worst.values()) <= 1e-6, worst
-    assert rg["thermal"] == pytest.approx(ro["thermal"], rel=1e-12)
-    assert rg["heat_total"] == pytest.approx(o.cum["heat"], rel=1e-8)
-    assert rg["bodies"][1]["torque_axis_int"] == pytest.approx(tq_o, rel=1e-8)
+    assert nac_diff <= 3, nac_diff
+    assert max(e.values()) <= 5e-2, e
+    assert rg["t"] == pytest.approx(o.t, rel=1e-6)
+    assert rg["thermal"] == pytest.approx(ro["thermal"], rel=1e-10)
+    assert rg["heat_total"] == pytest.approx(o.cum["heat"], rel=1e-6)
+    assert rg["bodies"][1]["torque_axis_int"] == pytest.approx(tq_o, rel=1e-6)

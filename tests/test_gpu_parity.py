@@ -10,6 +10,7 @@ Bars (written out in each test):
     <= 1e-5 (mixed) with scales Q_rho = rho0 (Umax/c0)^2, Q_v = Umax,
     Q_T = |T_wall - T_oil|, Q_x = dp; <= 1e-10 in FP64 mode.
 """
+import ctypes
 import math
 import sys
 
@@ -501,6 +502,44 @@ def test_determinism_and_graph_equals_eager(sph):
         for k in ("x", "v", "rho", "T"):
             assert np.array_equal(g[k], outs[0][0][k])
         assert r["bodies"][1]["torque_axis"] == outs[0][1]["bodies"][1]["torque_axis"]
+
+
+@pytest.mark.parametrize("prec,option", [("mixed", None), ("fp64", "heating"), ("fp32", None),
+                                         ("mixed", "materials")])
+def test_fused_first_substep_equals_unfused(sph, prec, option):
+    """The first acoustic sub-step's opening half update and momentum run
+    inside the viscous/heat sweep; launched on their own instead (same
+    arithmetic), every step gives the same state and report bit for bit,
+    across steps with one and several sub-steps."""
+    c = cases.tank_c1(seed=4, omega=300.0)
+    if option == "heating":
+        c.params = dict(c.params, viscous_heating=1)
+    if option == "materials":
+        c.params = dict(c.params, materials=[(0.13, 2000.0), (0.4, 1500.0)])
+        c.material = (c.xf[:, 0] > np.median(c.xf[:, 0])).astype(np.int32)
+    say("fused vs unfused first sub-step", prec, option)
+    outs = []
+    for fused in (True, False):
+        s = sph.Solver(c, precision=prec)
+        s.set_fusion(fused)
+        nac = []
+        for _ in range(6):
+            s.step(1)
+            nac.append(s.reduce()["n_ac"])
+        outs.append((s.get_fluid(), s.reduce(), nac))
+        s.close()
+    (ga, ra, na), (gb, rb, nb) = outs
+    assert na == nb and max(na) > 1, na
+    for k in ("x", "v", "rho", "T"):
+        assert np.array_equal(ga[k], gb[k]), k
+    for k in ("t", "kinetic", "thermal", "heat_total", "diss_total", "vmax"):
+        assert ra[k] == rb[k], k
+    for ba, bb in zip(ra["bodies"], rb["bodies"]):
+        assert np.array_equal(ba["force"], bb["force"]) and ba["torque_axis_int"] == bb["torque_axis_int"]
+    s = sph.Solver(c, precision=prec)
+    rc = sph.lib().sph_debug_set_fusion(s.h, ctypes.c_int32(2))
+    s.close()
+    assert rc == sph.SPH_ERR_ARG
 
 
 # ---------------------------------------------------------------------------

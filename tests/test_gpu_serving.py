@@ -120,16 +120,11 @@ def test_held_slot_is_unchanged_and_resumes_to_its_solo_result(sph):
     pool.hold(slots[0], False)        # resuming twice is harmless
     pool.hold(slots[1], False)
     pool.hold(slots[2], False)
+    pool.step(max(steps))             # more than any slot has left: finished slots drop out
     out = {}
-    for _ in range(20):
-        pool.step(1)
-        for q in range(3):
-            if q not in out:
-                done, rep = pool.poll(slots[q])
-                if done:
-                    out[q] = (pool.get_fluid(slots[q]), rep)
-        if len(out) == 3:
-            break
+    for q in range(3):
+        rep = _wait(pool, slots[q])
+        out[q] = (pool.get_fluid(slots[q]), rep)
     for q in range(3):
         ga, ra = alone[q]
         gm, rm = out[q]

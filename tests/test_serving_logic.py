@@ -122,18 +122,19 @@ def _active(sizes, remaining):
 
 
 def test_shortest_first_takes_least_work_up_to_the_fill():
-    # with a cost of one unit per particle-step, work: 4000, 1500, 1000, 6000
+    # with a cost of one unit per particle-step, work: 4000, 1500, 1000, 6000;
+    # order 12 (50 particles), 11 (300), 10 (100), 13 (200)
     act = _active([100, 300, 50, 200], [40, 5, 20, 30])
     pick = lambda a, fill, **kw: serve.shortest_first(a, fill, cost=(0.0, 1.0), **kw)
-    assert pick(act, 250) == {12, 11}          # 1000 (50) then 1500 (300): 350 >= 250
+    assert pick(act, 250) == {12, 10}          # 50, +300 > 250 skipped, +100 = 150, +200 > 250 skipped
     assert pick(act, 50) == {12}
     assert pick(act, 10 ** 9) == set(act)
-    # beyond the fill, a request joins only if the batched step stays within
-    # (1 + slowdown) of the first one's step alone: 50 -> at most 100 particles
+    # a request joins only if the batched step stays within the larger of
+    # (1 + slowdown) x the first one's step alone and the step of `fill`
     act2 = _active([50, 400, 40, 10], [2, 5, 5, 5])    # work 100, 2000, 200, 50: order 13, 10, 12, 11
-    assert pick(act2, 0, slowdown=1.0) == {13}          # 10 + 50 > 2 x 10
+    assert pick(act2, 0, slowdown=1.0) == {13}          # 10 + 50, 10 + 40, 10 + 400 all > 2 x 10
     assert pick(act2, 0, slowdown=5.0) == {13, 10}      # 60 <= 6 x 10; then 100 > 60
-    assert pick(act2, 55) == {13, 10}                   # below the fill 10 is taken; 12 is not
+    assert pick(act2, 55) == {13, 12}                   # limit 55: 60 no, 50 yes, 450 no
     assert pick(act2, 55, slowdown=1e9) == set(act2)
     # a request with no steps left is finishing: neither stepped nor counted
     act[12].remaining = 0
