@@ -460,6 +460,7 @@ static int enqueue_sort_build(sph_pool* P, const LaunchTab& T, bool timed = true
   LCHK(L(SPH_K_SCATTER, 0));
   LCHK(L(SPH_K_SCATTER, 1));
   LCHK(L(SPH_K_CELLSORT, 0));
+  LCHK(L(SPH_K_CELLSORT, 1));
   LCHK(L(SPH_K_REORDER, 0));
   LCHK(L(SPH_K_REORDER, 1));
   LCHK(L(SPH_K_BUILD, 0));

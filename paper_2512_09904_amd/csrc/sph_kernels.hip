@@ -376,66 +376,29 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(const SlotDesc* table, Launch
   if (act) key[start[r] + k] = (uint64_t)id[i] << 32 | (uint32_t)i;
 }
 
-// Sorts one cell's run of keys (original id << 32 | staged index) and writes
-// the staged indices in id order.  Runs of up to RUN_LDS entries are sorted
-// in this thread's LDS slots (loaded once; a run found in order is written
-// as is); longer runs are insertion-sorted in place in global memory.
-constexpr int RUN_LDS = 32;
-__device__ __forceinline__ void sort_run_keys(uint64_t* key, uint32_t* perm, uint32_t b, uint32_t e, uint64_t* buf) {
-  const uint32_t n = e - b;
-  if (n == 0) return;
-  if (n <= (uint32_t)RUN_LDS) {
-    bool sorted = true;
-    uint64_t last = 0;
-    // four independent loads in flight per step
-    for (uint32_t k0 = 0; k0 < n; k0 += 4) {
-      uint64_t v[4];
-#pragma unroll
-      for (uint32_t u = 0; u < 4; ++u) v[u] = k0 + u < n ? key[b + k0 + u] : ~0ull;
-#pragma unroll
-      for (uint32_t u = 0; u < 4; ++u) {
-        if (k0 + u < n) {
-          sorted = sorted && (k0 + u == 0 || v[u] > last);
-          last = v[u];
-          buf[(k0 + u) * BLOCK] = v[u];
-        }
-      }
-    }
-    if (!sorted) {
-      for (uint32_t k = 1; k < n; ++k) {
-        const uint64_t v = buf[k * BLOCK];
-        uint32_t m = k;
-        while (m > 0 && buf[(m - 1) * BLOCK] > v) {
-          buf[m * BLOCK] = buf[(m - 1) * BLOCK];
-          --m;
-        }
-        buf[m * BLOCK] = v;
-      }
-    }
-    for (uint32_t k = 0; k < n; ++k) perm[b + k] = (uint32_t)buf[k * BLOCK];
-    return;
-  }
-  for (uint32_t k = b + 1; k < e; ++k) {
-    const uint64_t v = key[k];
-    uint32_t m = k;
-    while (m > b && key[m - 1] > v) {
-      key[m] = key[m - 1];
-      --m;
-    }
-    key[m] = v;
-  }
-  for (uint32_t k = b; k < e; ++k) perm[k] = (uint32_t)key[k];
-}
-
-__global__ __launch_bounds__(BLOCK) void k_cellsort(const SlotDesc* table, LaunchTab tab) {
-  __shared__ uint64_t lds[BLOCK * RUN_LDS];
-  SLOT_PROLOGUE(DOM_CELL);
-  const int c = lb * BLOCK + threadIdx.x;
-  if (c >= S.ncells) return;
-  // slot k of this thread is lds[k * BLOCK + thread]: the k-th entries of a
-  // wave are adjacent
-  sort_run_keys(S.fkey, S.fperm, S.start_f[c], S.start_f[c + 1], lds + threadIdx.x);
-  sort_run_keys(S.skey, S.sperm, S.start_s[c], S.start_s[c + 1], lds + threadIdx.x);
+// Orders each cell's run of keys (original id << 32 | staged index) by id and
+// writes the staged indices in that order.  One thread per key position: the
+// key's cell comes from its staged index, its rank in the cell is the number
+// of the cell's keys below it (ids are unique, so the ranks are a
+// permutation of the run), and its staged index goes to that place.  The
+// lanes of a wavefront mostly share a cell, so the run's keys are read once
+// per wavefront from cache, and the stores of a cell's permutation are
+// contiguous.
+__global__ __launch_bounds__(BLOCK) void k_cellsort(const SlotDesc* table, LaunchTab tab, int which) {
+  SLOT_PROLOGUE(which ? DOM_SOLID : DOM_FLUID);
+  const int n = which ? S.ns : S.nf;
+  const int p = lb * BLOCK + threadIdx.x;
+  if (p >= n) return;
+  const uint64_t* key = which ? S.skey : S.fkey;
+  const uint32_t* cell = which ? S.scell : S.fcell;
+  const uint32_t* start = which ? S.start_s : S.start_f;
+  uint32_t* perm = which ? S.sperm : S.fperm;
+  const uint64_t kp = key[p];
+  const uint32_t r = cell[(uint32_t)kp];
+  const uint32_t b = start[r], e = start[r + 1];
+  uint32_t rank = 0;
+  for (uint32_t q = b; q < e; ++q) rank += key[q] < kp ? 1u : 0u;
+  perm[b + rank] = (uint32_t)kp;
 }
 
 // ---------------------------------------------------------------------------
@@ -1860,7 +1823,6 @@ int grid_domain(int kid, int which) {
     case SPH_K_CLEAR:
     case SPH_K_SCAN1:
     case SPH_K_SCAN3:
-    case SPH_K_CELLSORT:
       return DOM_CELL;
     case SPH_K_POSE:
     case SPH_K_CONTACT:
@@ -1871,6 +1833,7 @@ int grid_domain(int kid, int which) {
     case SPH_K_FINAL:
       return DOM_SLOT;
     case SPH_K_SCATTER:
+    case SPH_K_CELLSORT:
     case SPH_K_REORDER:
       return which ? DOM_SOLID : DOM_FLUID;
     default:
@@ -1893,7 +1856,7 @@ static hipError_t launch_p(int kid, int which, int sub, const SlotDesc* T, const
     case SPH_K_SCAN2: hipLaunchKernelGGL(k_scan2, g, b, 0, st, T, L); break;
     case SPH_K_SCAN3: hipLaunchKernelGGL(k_scan3, g, b, 0, st, T, L); break;
     case SPH_K_SCATTER: hipLaunchKernelGGL(k_scatter, g, b, 0, st, T, L, which); break;
-    case SPH_K_CELLSORT: hipLaunchKernelGGL(k_cellsort, g, b, 0, st, T, L); break;
+    case SPH_K_CELLSORT: hipLaunchKernelGGL(k_cellsort, g, b, 0, st, T, L, which); break;
     case SPH_K_REORDER: hipLaunchKernelGGL(k_reorder<P>, g, b, 0, st, T, L, which); break;
     case SPH_K_BUILD: hipLaunchKernelGGL(k_build<P>, g, b, 0, st, T, L); break;
     case SPH_K_SUMW: hipLaunchKernelGGL(k_sumw<P>, g, b, 0, st, T, L); break;
