@@ -440,10 +440,20 @@ static int launch_rx(sph_pool* P, const LaunchTab& tab, int kid, int iter, const
     if (r_) return r_;     \
   } while (0)
 
+// the main stream waits for the side stream's dummy velocities
+static int join_side(sph_pool* P) {
+  if (hipStreamWaitEvent(P->stream, P->ev_join, 0) != hipSuccess)
+    return fail_lit(SPH_ERR_HIP, "join from the side stream failed");
+  return SPH_OK;
+}
+
 // timed = false: no event timing and no heap allocation on success (the
 // allocation-free entry point); wallvel = false: no dummy velocities (calls
-// between steps that do not step: the next step's own build recomputes them)
-static int enqueue_sort_build(sph_pool* P, const LaunchTab& T, bool timed = true, bool wallvel = true) {
+// between steps that do not step: the next step's own build recomputes them);
+// join = false: the caller joins the side stream itself (join_side) before
+// the first kernel that reads the dummy velocities
+static int enqueue_sort_build(sph_pool* P, const LaunchTab& T, bool timed = true, bool wallvel = true,
+                              bool join = true) {
   auto LS = [&](int kid, int which, hipStream_t st) {
     if (timed) return launch(P, T, kid, which, 0, st);
     if (launch_kernel(P->prec, kid, which, 0, P->d_table, T, st) != hipSuccess)
@@ -477,14 +487,13 @@ static int enqueue_sort_build(sph_pool* P, const LaunchTab& T, bool timed = true
   if (hipEventRecord(P->ev_join, P->side_stream) != hipSuccess)
     return fail_lit(SPH_ERR_HIP, "event record on the side stream failed");
   LCHK(L(SPH_K_SUMW, 0));
-  if (hipStreamWaitEvent(P->stream, P->ev_join, 0) != hipSuccess)
-    return fail_lit(SPH_ERR_HIP, "join from the side stream failed");
-  return SPH_OK;
+  return join ? join_side(P) : (int)SPH_OK;
 }
 
 static int enqueue_step(sph_pool* P, const LaunchTab& T, int nac) {
-  LCHK(enqueue_sort_build(P, T));
-  LCHK(launch(P, T, SPH_K_DT, 0, 0));
+  LCHK(enqueue_sort_build(P, T, true, true, false));
+  LCHK(launch(P, T, SPH_K_DT, 0, 0));   // reads no dummy velocity: runs beside them
+  LCHK(join_side(P));
   // sub-step s: momentum, then continuity, which also closes s and opens
   // s + 1; the viscous/heat sweep runs sub-step 0's opening half and momentum
   // (unfused: their own launches, the same arithmetic)

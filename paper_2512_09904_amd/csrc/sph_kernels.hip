@@ -1673,6 +1673,8 @@ __global__ __launch_bounds__(BLOCK) void k_end(const SlotDesc* table, LaunchTab 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(FINAL_BLOCK) void k_final(const SlotDesc* table, LaunchTab tab) {
   __shared__ double res[NGLOB + NB * 13 + 1];
+  __shared__ double bheat[NB];
+  __shared__ int bfin[NB];
   SLOT_PROLOGUE(DOM_SLOT);
   (void)lb;
   const int nblk = S.nblk[DOM_FLUID];
@@ -1747,15 +1749,23 @@ __global__ __launch_bounds__(FINAL_BLOCK) void k_final(const SlotDesc* table, La
     }
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
+  // the reports: lane b of the first wavefront finishes body b, lane 0 then
+  // the globals; each lane loads the control fields it needs before it
+  // stores anything (a store could alias a later load and hold it back)
+  if (threadIdx.x >= WAVE) return;
   SlotCtl* C = S.ctl;
   const double tad = C->dt_ad;
-  const double inv_nac = 1.0 / (double)C->n_ac;
-  double qsum = 0.0;
-  bool finite = true;
-  for (int b = 0; b < S.nbody; ++b) {
+  const int32_t nac = C->n_ac;
+  const int b = threadIdx.x;
+  if (b < S.nbody) {
+    double cum[3], cumc[3];
+    for (int k = 0; k < 3; ++k) {
+      cum[k] = C->cum[b][k];
+      cumc[k] = C->cum_c[b][k];
+    }
+    const double inv_nac = 1.0 / (double)nac;
     const double* r = res + NGLOB + b * 13;
-    sph_body_report& br = C->brep[b];
+    sph_body_report br;
     for (int k = 0; k < 3; ++k) {
       br.force[k] = r[k] + r[7 + k] * inv_nac;
       br.torque[k] = r[3 + k] + r[10 + k] * inv_nac;
@@ -1768,7 +1778,7 @@ __global__ __launch_bounds__(FINAL_BLOCK) void k_final(const SlotDesc* table, La
     const double inc[3] = {tad * br.torque_axis, tad * br.power, tad * br.heat_rate};
     double tot[3];
     for (int k = 0; k < 3; ++k) {
-      KS acc{C->cum[b][k], C->cum_c[b][k]};
+      KS acc{cum[k], cumc[k]};
       ks_add(acc, inc[k]);
       C->cum[b][k] = acc.s;
       C->cum_c[b][k] = acc.c;
@@ -1777,28 +1787,45 @@ __global__ __launch_bounds__(FINAL_BLOCK) void k_final(const SlotDesc* table, La
     br.torque_axis_int = tot[0];
     br.energy_int = tot[1];
     br.heat_int = tot[2];
-    qsum += br.heat_rate;
-    finite = finite && isfinite(br.torque_axis) && isfinite(br.heat_rate) && isfinite(br.force[0]) &&
-             isfinite(br.force[1]) && isfinite(br.force[2]);
+    C->brep[b] = br;
+    bheat[b] = br.heat_rate;
+    bfin[b] = isfinite(br.torque_axis) && isfinite(br.heat_rate) && isfinite(br.force[0]) &&
+              isfinite(br.force[1]) && isfinite(br.force[2]);
   }
-  C->t += tad;
-  C->step += 1;
-  C->substeps += C->n_ac;
+  wave_lds_sync();
+  if (b != 0) return;
+  const double dtc = C->dt, t0 = C->t;
+  const int64_t step0 = C->step, sub0 = C->substeps;
+  const uint32_t flags0 = C->flags;
+  KS heat{C->heat_total, C->heat_c}, diss{C->diss_total, C->diss_c};
+  double qsum = 0.0;
+  bool finite = true;
+  for (int q = 0; q < S.nbody; ++q) {
+    qsum += bheat[q];
+    finite = finite && bfin[q];
+  }
+  const double t1 = t0 + tad;
+  const int64_t step1 = step0 + 1, sub1 = sub0 + nac;
   const double hs = tad * qsum;
   const double ds = S.diss ? tad * res[q_diss] : 0.0;
-  KS heat{C->heat_total, C->heat_c}, diss{C->diss_total, C->diss_c};
   ks_add(heat, hs);
   ks_add(diss, ds);
+  finite = finite && isfinite(res[1]) && isfinite(res[2]) && isfinite(res[3]) && isfinite(ds);
+  const uint32_t flags1 = finite ? flags0 : (flags0 | F_NONFINITE);
+  C->t = t1;
+  C->step = step1;
+  C->substeps = sub1;
   C->heat_total = heat.s;
   C->heat_c = heat.c;
   C->diss_total = diss.s;
   C->diss_c = diss.c;
-  sph_report& R = C->rep;
-  R.t = C->t;
-  R.step = C->step;
-  R.n_ac = C->n_ac;
+  if (!finite) C->flags = flags1;
+  sph_report R;
+  R.t = t1;
+  R.step = step1;
+  R.n_ac = nac;
   R.dt_ad = tad;
-  R.dt = C->dt;
+  R.dt = dtc;
   R.mass = res[0];
   R.kinetic = res[1];
   R.thermal = res[2];
@@ -1806,12 +1833,11 @@ __global__ __launch_bounds__(FINAL_BLOCK) void k_final(const SlotDesc* table, La
   R.vmax = res[4];
   R.heat_step = hs;
   R.heat_total = heat.s + heat.c;
-  R.substeps = C->substeps;
+  R.substeps = sub1;
   R.diss_step = ds;
   R.diss_total = diss.s + diss.c;
-  finite = finite && isfinite(res[1]) && isfinite(res[2]) && isfinite(res[3]) && isfinite(ds);
-  if (!finite) C->flags |= F_NONFINITE;
-  R.flags = (int32_t)C->flags;
+  R.flags = (int32_t)flags1;
+  C->rep = R;
 }
 
 
