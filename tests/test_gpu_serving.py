@@ -216,6 +216,35 @@ def test_fp64_pool_mix_equals_fp64_solver(sph):
     assert r["thermal"] == rm["thermal"] and r["heat_total"] == rm["heat_total"]
 
 
+@pytest.mark.parametrize("policy", ["all", "shortest"])
+def test_server_results_equal_solo_runs(sph, policy):
+    """The continuous-batching server with each policy over six requests of
+    different sizes and step counts, at most three slots: every request's
+    final state and report equal its solo run bit for bit, whatever it was
+    batched with and however often the "shortest" policy held it (its fill
+    of 8,000 particles holds the larger requests behind the smaller ones)."""
+    from paper_2512_09904_amd import serve
+    cs = [cases.serving_tank(n, om, imm, nu, seed=k) for k, (n, om, imm, nu) in
+          enumerate([(9000, 300.0, 0.04, 1e-4), (3000, 450.0, 0.03, 2e-4), (6000, 200.0, 0.05, 1.5e-4),
+                     (2500, 350.0, 0.035, 1e-4), (7000, 500.0, 0.045, 2.5e-4), (4000, 250.0, 0.025, 0.8e-4)])]
+    steps = [12, 6, 9, 5, 8, 7]
+    say("serving: server", policy)
+    alone = [_run_pool(sph, [c], [n], [0])[0] for c, n in zip(cs, steps)]
+    reqs = [serve.Request(rid=k, arrival=0.0, case=c, steps=n) for k, (c, n) in enumerate(zip(cs, steps))]
+    for r in reqs:
+        r.keep_state = True
+    srv = serve.Server(1 << 40, max_slots=3, steps_per_call=2, policy=policy, fill=8000)
+    srv.run(reqs)
+    srv.close()
+    for r, (ga, ra) in zip(reqs, alone):
+        assert r.report["rc"] == 0 and r.report["step"] == r.steps == ra["step"]
+        for key in ("x", "v", "rho", "T"):
+            assert np.array_equal(r.final[key], ga[key]), (r.rid, key)
+        assert r.report["bodies"][1]["torque_axis_int"] == ra["bodies"][1]["torque_axis_int"]
+        assert r.report["heat_total"] == ra["heat_total"] and r.report["t"] == ra["t"]
+    assert srv.peak_active <= 3
+
+
 def test_admission_respects_budget(sph):
     reqs = _requests()
     need = [sph.Pool.bytes_required(c) for c in reqs]
