@@ -50,8 +50,8 @@ def sweep_requests(n=64, seed=64, steps=500, nf_lo=5e4, nf_hi=2e6, rate=None, sc
     """The parameter-sweep workload: U(150, 600) rad/s, immersion U(20, 60) mm,
     nu U(0.5, 3)e-4, fluid count log-uniform in [nf_lo, nf_hi], Poisson arrivals.
 
-    `scale` multiplies the particle counts (small runs for tests).
-    Returns (requests without arrival times, rng) when rate is None.
+    `scale` multiplies the particle counts (small runs for tests).  Without
+    `rate` every arrival time is 0 (the caller sets them).
     """
     rng = np.random.default_rng(seed)
     reqs = []
