@@ -757,6 +757,33 @@ __global__ __launch_bounds__(BLOCK) void k_sumw(const SlotDesc* table, LaunchTab
   vr[i] = v;
 }
 
+// Sum over the wavefront by DPP lane moves (no LDS traffic), in a fixed
+// order: pairs, quads, half-rows and rows of 16 by quad and mirror
+// permutations, then row 1 and row 3 take the row before them (row_bcast:15)
+// and rows 2 and 3 the first 32 lanes' sum (row_bcast:31).  The total is in
+// lane 63; every lane must be active.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_take(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROWS, 0xf, false));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_take(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROWS, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROWS, 0xf, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+template <class Real>
+__device__ __forceinline__ Real wave_total(Real v) {
+  v += dpp_take<0xb1, 0xf>(v);    // quad_perm [1,0,3,2]
+  v += dpp_take<0x4e, 0xf>(v);    // quad_perm [2,3,0,1]
+  v += dpp_take<0x141, 0xf>(v);   // row_half_mirror
+  v += dpp_take<0x140, 0xf>(v);   // row_mirror
+  v += dpp_take<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_take<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  return rl(v, WAVE - 1);
+}
+
 // ---------------------------------------------------------------------------
 // K: dummy velocity of every solid particle for the wall viscous force
 // (eq. 18 with the generalized wall of Section 2.5): v_w = 2 u_w - v~_w, with
@@ -778,13 +805,6 @@ __global__ __launch_bounds__(BLOCK) void k_sumw(const SlotDesc* table, LaunchTab
 // It runs beside the kernel sums, which rewrite only the density component of
 // the velocity records read here.
 // ---------------------------------------------------------------------------
-template <class Real>
-__device__ __forceinline__ Real wave_sum_r(Real v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-  return v;
-}
-
 template <class P>
 __global__ __launch_bounds__(BLOCK) void k_wallvel(const SlotDesc* table, LaunchTab tab) {
   typedef typename P::Real Real;
@@ -886,7 +906,7 @@ __global__ __launch_bounds__(BLOCK) void k_wallvel(const SlotDesc* table, Launch
           if (!__ballot(any)) continue;
 #pragma unroll
           for (int a = 0; a < 4; ++a) {
-            const Real t = wave_sum_r(s[a]);
+            const Real t = wave_total(s[a]);
             if (lane == p) acc[a] += t;
           }
         }
