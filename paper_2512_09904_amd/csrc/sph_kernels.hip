@@ -447,12 +447,13 @@ __global__ __launch_bounds__(BLOCK) void k_reorder(const SlotDesc* table, Launch
 //
 // A wavefront holds 64 consecutive particles of the Morton order, i.e. runs
 // of particles sharing a cell.  For each run the candidates of its 27-cell
-// stencil are spread over the lanes (up to CB per lane, loaded once); the
-// run's particles are then taken one at a time: each lane tests its
-// candidates against the particle's position (broadcast from its lane into
-// scalar registers), one ballot per candidate slot gives the hits, and the
-// hit lanes write their indices to consecutive entries of the particle's row
-// (particle-major, so a ballot's stores are contiguous).  Every test is one
+// stencil are spread over the lanes in chunks of CB per lane, each candidate
+// loaded once; for each chunk the run's particles are taken one at a time:
+// each lane tests its candidates against the particle's position (broadcast
+// from its lane into scalar registers), one ballot per candidate slot gives
+// the hits, and the hit lanes write their indices to consecutive entries of
+// the particle's row (particle-major, so a ballot's stores are contiguous;
+// chunks of one run append in candidate order).  Every test is one
 // of the particle's own stencil, and no lane waits on another's hits.  A row
 // lists the stencil's cells in a fixed order, indices ascending within a
 // cell.  At the end each lane moves its particle's row (still in cache) into
@@ -510,7 +511,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 // Candidates of one run's stencil against the run's particles [L, R) of the
 // wave.  pre/beg: per stencil cell (27) the prefix of candidate counts and the
 // first index.  Hits of particle p go to row[p] + off, counted in lane p's cnt.
-constexpr int CB = 8;
+// candidate slots per lane: four keeps the build at five waves per SIMD
+// (92 registers); eight (124 registers, four waves) was 3 % slower
+constexpr int CB = 4;
 template <class Pos, class Pos4>
 __device__ __forceinline__ void run_candidates(const GLB Pos4* x, const uint32_t* pre, const uint32_t* beg,
                                                uint32_t M, int L, int R, int wbase, Pos xi, Pos yi, Pos zi,
@@ -794,10 +797,10 @@ __device__ __forceinline__ Real wave_total(Real v) {
 // Solid-centric, with the neighbour build's traversal: a wavefront holds 64
 // consecutive solid particles of the Morton order; for each run sharing a
 // cell, the fluid candidates of its 27-cell stencil are spread over the lanes
-// (up to CB per lane, cell-relative position and velocity loaded once); each
-// particle of the run is then taken in turn, every lane sums W and W v over
-// its candidates within 2h, and four wave reductions in a fixed order give the
-// particle's sums.  The arithmetic is that of the interaction sweeps (FP32 in
+// in chunks of CBW per lane (cell-relative position and velocity loaded
+// once); for each chunk the run's particles are taken in turn, every lane
+// sums W and W v over its candidates within 2h, and four wave reductions in a
+// fixed order add the chunk's share to the particle's sums.  The arithmetic is that of the interaction sweeps (FP32 in
 // mixed precision, pair vectors from the frozen cell-relative positions): a
 // pair that this test and the FP64 cutoff test of the rows decide differently
 // lies within a few ulps of 2h, where W is below 1e-25 W(0).  No atomics: the
@@ -805,6 +808,9 @@ __device__ __forceinline__ Real wave_total(Real v) {
 // It runs beside the kernel sums, which rewrite only the density component of
 // the velocity records read here.
 // ---------------------------------------------------------------------------
+// candidate slots per lane of the dummy-velocity sweep: four (six waves per
+// SIMD) against eight (three waves) took it from 0.29 to 0.20 ms
+constexpr int CBW = 4;
 template <class P>
 __global__ __launch_bounds__(BLOCK) void k_wallvel(const SlotDesc* table, LaunchTab tab) {
   typedef typename P::Real Real;
@@ -858,10 +864,10 @@ __global__ __launch_bounds__(BLOCK) void k_wallvel(const SlotDesc* table, Launch
         beg[lane] = f0;
       }
       wave_lds_sync();
-      for (uint32_t b0 = 0; b0 < M; b0 += (uint32_t)(WAVE * CB)) {
-        Real4 co[CB], cv[CB];
+      for (uint32_t b0 = 0; b0 < M; b0 += (uint32_t)(WAVE * CBW)) {
+        Real4 co[CBW], cv[CBW];
 #pragma unroll
-        for (int k = 0; k < CB; ++k) {
+        for (int k = 0; k < CBW; ++k) {
           const uint32_t m = b0 + (uint32_t)(k * WAVE + lane);
           co[k] = Real4((Real)1e30);   // far: never within 2h
           co[k].w = pack_index(0u, (Real)0);
@@ -876,7 +882,7 @@ __global__ __launch_bounds__(BLOCK) void k_wallvel(const SlotDesc* table, Launch
             cv[k] = vr[j];
           }
         }
-        const int nu = (int)min((uint32_t)CB, (M - b0 + WAVE - 1) / WAVE);
+        const int nu = (int)min((uint32_t)CBW, (M - b0 + WAVE - 1) / WAVE);
         for (int p = L; p < R; ++p) {
           Real4 op;
           op.x = rl(ow.x, p);
@@ -887,7 +893,7 @@ __global__ __launch_bounds__(BLOCK) void k_wallvel(const SlotDesc* table, Launch
           Real s[4] = {(Real)0, (Real)0, (Real)0, (Real)0};
           bool any = false;
 #pragma unroll
-          for (int k = 0; k < CB; ++k) {
+          for (int k = 0; k < CBW; ++k) {
             if (k >= nu) break;
             Real rx, ry, rz;
             pair_vec(op, cp, co[k], csr, rx, ry, rz);
