@@ -1110,16 +1110,15 @@ __device__ __forceinline__ void grad_add(Real* G, Real c, Real dx, Real dy, Real
 // the separate half update, so the results equal the unfused sequence bit
 // for bit and a fluid pair costs four gathers instead of five.
 // ---------------------------------------------------------------------------
-// the fused variant without dissipation is held to VISC_MOM0_WAVES waves per
-// SIMD (VISC_MOM0_WAVES_F64 in FP64): a few spilled registers cost less than
-// the lost latency hiding
-#ifndef VISC_MOM0_WAVES_F64
-#define VISC_MOM0_WAVES_F64 1
-#endif
-#define VISC_MOM0_WAVES 3
+// The fused variant without dissipation is held to three waves per SIMD in
+// FP32 and mixed arithmetic (168 registers, 20 bytes spilled per lane): the
+// few spills cost less than the latency hiding the third wave brings.  The
+// FP64 and dissipation variants keep the compiler's budget (held down they
+// spill 100-400 bytes per lane and run slower).
+constexpr int visc_min_waves(bool mom0, bool diss, bool f64) { return mom0 && !diss && !f64 ? 3 : 1; }
 template <class P, bool DISS, bool MAT, bool MOM0>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(
-    MOM0 && !DISS ? (std::is_same<typename P::Real, double>::value ? VISC_MOM0_WAVES_F64 : VISC_MOM0_WAVES) : 1)))
+    visc_min_waves(MOM0, DISS, std::is_same<typename P::Real, double>::value))))
 void k_visc_heat(const SlotDesc* table, LaunchTab tab) {
   typedef typename P::Real Real;
   typedef typename P::Temp Temp;
