@@ -40,8 +40,11 @@ namespace sphk {
 // inside it, so their 32-byte gathers become LDS reads; the rest are gathered
 // from global memory.  Used by the FP64 kernel-sum sweep, whose anchor
 // gathers (two 16-byte requests per pair) otherwise bound it by the vector
-// memory unit's rate of one scattered lane per clock.
-constexpr int WIN = 1024;
+// memory unit's rate of one scattered lane per clock.  512 particles (16 KB
+// of LDS per block) rather than 1024: fewer neighbours fall inside, but twice
+// as many blocks fit on a CU, which the sweep gains more from beside the
+// dummy-velocity sweep on the other stream.
+constexpr int WIN = 512;
 struct Window {
   uint32_t w0, wn;
 };
