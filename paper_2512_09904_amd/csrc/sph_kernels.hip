@@ -21,18 +21,19 @@ namespace sphk {
 
 // Rows are walked ROW_UNROLL entries at a time (SOLID_UNROLL for the wall
 // rows, VISC_SOLID_UNROLL for the viscous/heat sweep's wall rows, CONT_UNROLL
-// in the continuity sweep, which runs faster with sixteen gathers in flight
-// at two waves per SIMD: group sizes measured per sweep), and the next group's indices are
-// loaded before the current group's gathers are consumed, so a wavefront
-// keeps two dependent loads in flight.  Entries past a row's count are loaded
-// from the row's capacity (always in bounds: capacities are multiples of
-// sixteen, and a group beyond the first is loaded only when it starts below
-// the count) and replaced by a null entry: own index, F = 0, which adds
-// exactly zero to every sum.
+// in the continuity sweep, which runs fastest with twelve gathers in flight
+// at three waves per SIMD: group sizes measured per sweep), and the next
+// group's indices are loaded before the current group's gathers are
+// consumed, so a wavefront keeps two dependent loads in flight.  Entries past
+// a row's count are loaded from within the row's capacity (capacities are
+// multiples of sixteen, a group beyond the first is loaded only when it
+// starts below the count, and the continuity sweep's groups of twelve clamp
+// their last loads to the row's last entry) and replaced by a null entry: own
+// index, F = 0, which adds exactly zero to every sum.
 #define ROW_UNROLL 8
 #define SOLID_UNROLL 8
 #define VISC_SOLID_UNROLL 4
-#define CONT_UNROLL 16
+#define CONT_UNROLL 12
 
 // A block's window of the fluid anchors: the WIN particles around the
 // block's own BLOCK (clamped to the array), staged in LDS with coalesced
@@ -1565,7 +1566,8 @@ __global__ __launch_bounds__(BLOCK) void k_continuity(const SlotDesc* table, Lau
       }
       if (k + CONT_UNROLL < n) {
 #pragma unroll
-        for (int u = 0; u < CONT_UNROLL; ++u) jn[u] = ldnt(R + (int64_t)(k + CONT_UNROLL + u) * WAVE);
+        for (int u = 0; u < CONT_UNROLL; ++u)
+          jn[u] = ldnt(R + (int64_t)min(k + CONT_UNROLL + u, S.kf - 1) * WAVE);
       }
 #pragma unroll
       for (int u = 0; u < CONT_UNROLL; ++u) {
