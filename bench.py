@@ -73,9 +73,10 @@ def sweep_bytes(kernel, nf, nsr, pf, ps, prec="mixed"):
         # vrn, offsets, counts read; drho and vr written; wall offsets, normals, velocities
         return nf * (v4 + v4 + cnt + rb + v4) + rows + nsr * 3 * v4
     if kernel == "visc_heat":
-        # with the first sub-step's momentum: vr, offsets, T, Drho, counts read; ah and vrn written;
-        # drift read and written; wall offsets, dummy velocities, lever arms
-        return nf * (v4 + v4 + pb + rb + cnt + v4 + v4 + 2 * v4) + rows + nsr * 3 * v4
+        # with the first sub-step's momentum: vr, offsets, T, Drho, the 16-byte (T, Drho) records
+        # of the neighbour gathers, counts read; ah and vrn written; drift read and written; wall
+        # offsets, dummy velocities, lever arms
+        return nf * (v4 + v4 + pb + rb + 16 + cnt + v4 + v4 + 2 * v4) + rows + nsr * 3 * v4
     if kernel == "build":
         # anchors read; offsets and counts written; rows written (the particle-major staging is
         # read back from cache); wall positions

@@ -158,6 +158,7 @@ static size_t carve(const Plan& P, void* base, SlotDesc* d) {
   C.takev(D.vrn, 4 * nf * rs);
   C.takev(D.drho, nf * rs);
   C.takev(D.T, nf * ts);
+  C.takev(D.td, 16 * nf);
   C.takev(D.ah, 4 * nf * rs);
   C.take(D.fid, nf * 4);
   C.take(D.sumW, nf * 8);

@@ -78,6 +78,7 @@ struct SlotDesc {
   SlotCtl* ctl;
   // fluid state (sorted order) and its gather buffers
   void *xa, *drift, *vr, *vrn, *drho, *T, *ah;
+  void *td;             // (T, Drho) per sorted particle side by side, 16 B: the fused sweep's gather
   uint32_t *fid;
   double *sumW;
   uint32_t *fcell, *fperm;

@@ -405,8 +405,17 @@ __global__ __launch_bounds__(BLOCK) void k_cellsort(const SlotDesc* table, Launc
   perm[b + rank] = (uint32_t)kp;
 }
 
+// A fluid particle's temperature and density rate side by side (16 bytes),
+// so the fused first sub-step takes both of a neighbour's in one gather.
+template <class P>
+struct alignas(16) TempRate {
+  typename P::Temp T;
+  typename P::Real d;
+};
+
 // ---------------------------------------------------------------------------
-// K: gather the staged arrays into cell-sorted order
+// K: gather the staged arrays into cell-sorted order (fluid: also the
+// (T, Drho) records)
 // ---------------------------------------------------------------------------
 template <class P>
 __global__ __launch_bounds__(BLOCK) void k_reorder(const SlotDesc* table, LaunchTab tab, int which) {
@@ -421,8 +430,13 @@ __global__ __launch_bounds__(BLOCK) void k_reorder(const SlotDesc* table, Launch
     const uint32_t s = S.fperm[k];
     gp<Pos4>(S.xa)[k] = gpc<Pos4>(S.xa2)[s];
     gp<Real4>(S.vr)[k] = gpc<Real4>(S.vr2)[s];
-    gp<Real>(S.drho)[k] = gpc<Real>(S.drho2)[s];
-    gp<Temp>(S.T)[k] = gpc<Temp>(S.T2)[s];
+    const Real dr = gpc<Real>(S.drho2)[s];
+    const Temp tk = gpc<Temp>(S.T2)[s];
+    gp<Real>(S.drho)[k] = dr;
+    gp<Temp>(S.T)[k] = tk;
+    GLB TempRate<P>* td = gp<TempRate<P>>(S.td) + k;
+    td->T = tk;
+    td->d = dr;
     S.fid[k] = S.fid2[s];
     if (S.mat) S.mat[k] = S.mat2[s];
   } else {
@@ -1112,7 +1126,9 @@ __device__ __forceinline__ void grad_add(Real* G, Real c, Real dx, Real dy, Real
 // the same neighbours and frozen pair vectors: each neighbour's half-step
 // density is formed from its gathered state and Drho with the arithmetic of
 // the separate half update, so the results equal the unfused sequence bit
-// for bit and a fluid pair costs four gathers instead of five.
+// for bit.  A fluid pair costs three gathers (cell offset, velocity and
+// density, the (T, Drho) record the reorder wrote) instead of the five of
+// the separate launches.
 // ---------------------------------------------------------------------------
 // The fused variant without dissipation is held to three waves per SIMD in
 // FP32 and mixed arithmetic (168 registers, 20 bytes spilled per lane): the
@@ -1155,6 +1171,7 @@ void k_visc_heat(const SlotDesc* table, LaunchTab tab) {
     const GLB Temp* T = gpc<Temp>(S.T);
     const GLB Real4* xo = gpc<Real4>(S.xo);
     const GLB Real* drho = gpc<Real>(S.drho);
+    const GLB TempRate<P>* td = gpc<TempRate<P>>(S.td);
     const Real m = (Real)S.mass;
     const Real inv_h = (Real)(1.0 / S.h), kF = (Real)S.kF, csr = (Real)S.cs_r;
     const Real4 vi = vr[i];
@@ -1201,8 +1218,12 @@ void k_visc_heat(const SlotDesc* table, LaunchTab tab) {
         for (int u = 0; u < ROW_UNROLL; ++u) {
           oj[u] = xo[j[u]];
           vj[u] = vr[j[u]];
-          Tj[u] = T[j[u]];
-          if constexpr (MOM0) dj[u] = drho[j[u]];
+          if constexpr (MOM0) {
+            Tj[u] = td[j[u]].T;
+            dj[u] = td[j[u]].d;
+          } else {
+            Tj[u] = T[j[u]];
+          }
         }
         if (k + ROW_UNROLL < n) {
 #pragma unroll
