@@ -614,9 +614,11 @@ def main():
                           for k in sph.KERNELS if len(kt[k])}
     log("per-step kernel ms:", json.dumps({k: round(v, 4) for k, v in per_step_kernel_ms.items()}))
     nsr = distinct_wall_particles(s, case.nf)
-    # lane gathers of neighbour records per launch (16-B records in mixed precision)
+    # lane gathers of neighbour records per launch (16-B records in mixed precision; the viscous/heat
+    # sweep's fluid pairs: offsets, velocity state, the (T, Drho) record, and the material index with
+    # two materials)
     gathers = {"momentum": 2 * (pf2 + ps2), "continuity": 2 * pf2 + 3 * ps2,
-               "visc_heat": 4 * pf2 + 3 * ps2, "sumw": 2 * (pf2 + ps2)}
+               "visc_heat": (4 if args.materials else 3) * pf2 + 3 * ps2, "sumw": 2 * (pf2 + ps2)}
     kern = {}
     for k in ("build", "sumw", "visc_heat", "momentum", "continuity"):
         if not len(kt[k]):
